@@ -1,0 +1,199 @@
+"""Throughput of the hybridization hot path on one MI355X.
+
+One step = the whole path for one batch of elements: per-element assembly of
+M_T and f_T, Cholesky, H_T and its scatter into CSR H, r (setup), then the
+element-by-element recovery of u from lambda.  The Jacobi-PCG that produces
+lambda runs once before the timed region and is reported separately.
+
+Prints one JSON line (see the design doc for the roofline accounting).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "hybridized elements/s (setup+recover) vs FP64 plain at stated error; p50/p99 lat"
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+FP64_PEAK = 78.6e12        # flop/s, MI355X FP64 (vector = matrix)
+
+
+def per_element_counts(k: int, ne: int, nnz: int, m: int, nv: int):
+    """Algorithmic bytes and flops per element of the setup kernel (with the
+    right-hand side) and of the recovery kernel."""
+    K2 = (k + 1) ** 2
+    n = 3 * K2 * (k + 2)
+    nb = 6 * K2
+    Q = (k + 2) ** 3
+    npk = n * (n + 1) // 2
+    inputs = 8 * 4 + 24.0 * nv / ne + 8 + 8 + 24 + 6 * 4 + 8 + 36   # e2v, coords, alpha, beta, f, maps
+    setup_bytes = inputs + 8 * npk + 8 * n + 8.0 * nnz / ne + 8.0 * m / ne
+    setup_flops = 2 * n * n * Q + n ** 3 / 3 + 2 * nb ** 3 / 3
+    rec_bytes = 8 * npk + 8 * n + 8 * nb + 8 * n + 6 * 4 + 8
+    rec_flops = 2 * n * n
+    return dict(setup_bytes=setup_bytes, setup_flops=setup_flops, recover_bytes=rec_bytes, recover_flops=rec_flops)
+
+
+def cpu_baseline(prob, target_s: float = 12.0):
+    """The oracle as it stands, single-threaded BLAS, on a bounded sample of
+    the same workload: setup (with rhs) + recovery of the first S elements."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hybrid as ohyb
+    from oracle import topology as otopo
+    topo = otopo.build_topology(prob.mesh.e2v)
+    mid, _ = otopo.multiplier_map(topo, prob.k)
+    m = topo.nfaces * (prob.k + 1) ** 2
+    lam = np.random.default_rng(0).standard_normal(m)
+    args = (prob.k, prob.mesh.xyz, prob.mesh.e2v, prob.alpha, prob.beta, prob.f)
+
+    def run(S):
+        els = np.arange(S)
+        t0 = time.perf_counter()
+        hyb = ohyb.hybridize(*args, topo=topo, elements=els, mult_id=mid)
+        ohyb.recover(hyb, prob.mesh.xyz, prob.mesh.e2v, prob.alpha, prob.beta, prob.f, lam, elements=els)
+        return time.perf_counter() - t0
+
+    with threadpool_limits(1):
+        S = min(256, prob.mesh.ne)
+        t = run(S)
+        S = int(min(prob.mesh.ne, max(S, S * target_s / max(t, 1e-3))))
+        t = run(S)
+    return {"value": S / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {S} of {prob.mesh.ne} elements of the same workload, setup incl. rhs + recovery, "
+                      f"{t:.1f} s, 1 thread (BLAS limited to 1)"}
+
+
+def parity_sample(prob, plan, lam_np, nface=48, nel=48, seed=0):
+    """Error of the GPU H rows, r and u against the oracle on sampled faces
+    and elements (both elements of a sampled face are computed, so its rows
+    of H are complete)."""
+    import scipy.sparse as sp
+
+    from oracle import hybrid as ohyb
+    from oracle import topology as otopo
+    rng = np.random.default_rng(seed)
+    topo = otopo.build_topology(prob.mesh.e2v)
+    faces = rng.choice(topo.nfaces, size=min(nface, topo.nfaces), replace=False)
+    els = np.unique(np.concatenate([topo.face_owner[faces, 0], topo.face_nbr[faces, 0],
+                                    rng.choice(prob.mesh.ne, size=min(nel, prob.mesh.ne), replace=False)]))
+    args = (prob.k, prob.mesh.xyz, prob.mesh.e2v, prob.alpha, prob.beta, prob.f)
+    ref = ohyb.hybridize(*args, topo=topo, elements=els)
+    rp, ci, val = [t.cpu().numpy() for t in plan.csr()]
+    Hg = sp.csr_matrix((val, ci, rp), shape=(plan.m, plan.m))
+    K2 = (prob.k + 1) ** 2
+    eH = er = 0.0
+    rg = plan.r().cpu().numpy()
+    for F in faces:
+        for j in range(K2):
+            row = F * K2 + j
+            a = ref.H.getrow(row).toarray().ravel()
+            b = Hg.getrow(row).toarray().ravel()
+            eH = max(eH, np.abs(a - b).max() / np.abs(a).max())
+            er = max(er, abs(ref.r[row] - rg[row]) / np.abs(ref.r).max())
+    u_ref = ohyb.recover(ref, prob.mesh.xyz, prob.mesh.e2v, prob.alpha, prob.beta, prob.f, lam_np, elements=els)
+    u = plan.recover(lam_np).cpu().numpy()[els]
+    eu = np.abs(u - u_ref).max() / np.abs(u_ref).max()
+    return {"H_row_rel": eH, "r_rel_to_max": er, "u_rel": eu,
+            "sample": f"{len(faces)} faces' rows of H and r, {len(els)} elements' u"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design in DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1801_08914_amd import Plan
+
+    prob = synth.config_c2()
+    k, ne = prob.k, prob.mesh.ne
+    plan = Plan(prob.mesh.xyz, prob.mesh.e2v, k).bind("cuda:0")
+    dev = torch.device("cuda:0")
+    alpha = torch.as_tensor(prob.alpha, device=dev)
+    beta = torch.as_tensor(prob.beta, device=dev)
+    f = torch.as_tensor(prob.f, device=dev)
+    u = torch.empty((ne, plan.n), dtype=torch.float64, device=dev)
+
+    # lambda for the recovery: one Jacobi-PCG solve (not part of the metric)
+    plan.setup(alpha, beta, f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, info = plan.solve(1e-12, 20000)
+    torch.cuda.synchronize()
+    pcg_ms = (time.perf_counter() - t0) * 1e3
+    rc, det = plan.status()
+    assert rc == 0, (rc, det)
+
+    for _ in range(args.warmup):
+        plan.setup(alpha, beta, f)
+        plan.recover(lam, u)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.setup(alpha, beta, f)
+        plan.recover(lam, u)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = plan.timing_read()
+    plan.timing(False)
+    rc, det = plan.status()
+    assert rc == 0, (rc, det)
+
+    ms_step = dt * 1e3 / args.steps
+    value = ne * args.steps / dt
+    cnt = per_element_counts(k, ne, plan.nnz, plan.m, prob.mesh.nv)
+    t_setup = kt["setup_ms"] / max(kt["setup_n"], 1) * 1e-3
+    t_rec = kt["recover_ms"] / max(kt["recover_n"], 1) * 1e-3
+    B = cnt["setup_bytes"] * ne
+    Fl = cnt["setup_flops"] * ne
+    hbm_frac = B / t_setup / HBM_PEAK
+    fp_frac = Fl / t_setup / FP64_PEAK
+    bound = "hbm" if B / HBM_PEAK >= Fl / FP64_PEAK else "fp64"
+    roof = {"bound": bound, "kernel": "k_setup (assembly+Cholesky+H_T scatter+rhs)",
+            "achieved": B / t_setup / 1e9 if bound == "hbm" else Fl / t_setup / 1e12,
+            "peak": 8000.0 if bound == "hbm" else 78.6,
+            "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+            "frac": hbm_frac if bound == "hbm" else fp_frac,
+            "traffic": None,
+            "kernel_ms": t_setup * 1e3,
+            "fp64_achieved_tflops": Fl / t_setup / 1e12, "fp64_frac": fp_frac,
+            "hbm_achieved_gbs": B / t_setup / 1e9, "hbm_frac": hbm_frac,
+            "recover_kernel_ms": t_rec * 1e3,
+            "recover_hbm_gbs": cnt["recover_bytes"] * ne / t_rec / 1e9,
+            "bytes_per_element": cnt["setup_bytes"], "flops_per_element": cnt["setup_flops"]}
+    out = {"metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": prob.name + " RT1 structured 32^3, alpha lognormal(0,1), beta=1, f~N(0,1), seed 2",
+                      "elements": ne, "k": k, "m": plan.m, "nnz": plan.nnz, "precision": "fp64-plain"},
+           "pcg": {"iters": info["iters"], "rel_res": info["rel_res"], "ms": pcg_ms},
+           "roofline": roof}
+    if not args.no_parity:
+        out["error_vs_oracle"] = parity_sample(prob, plan, lam.cpu().numpy())
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

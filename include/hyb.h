@@ -1,0 +1,223 @@
+/*
+ * hyb.h -- C ABI of the MI355X hybridization library (libhyb.so).
+ *
+ * Algebraic hybridization of the H(div) problem
+ *     (alpha u, v) + (beta div u, div v) = (f, v)
+ * on Raviart-Thomas RT_k hexahedra, k = 0..3 (Dobrev, Kolev, Lee, Tomov,
+ * Vassilevski, "Algebraic hybridization and static condensation with
+ * application to scalable H(div) preconditioning", arXiv:1801.08914).
+ * Letters: alpha is the mass coefficient and beta the div-div coefficient
+ * (the paper's Sec. 3.2 uses the opposite letters).
+ *
+ * Theorem 2.1: with the block-diagonal broken matrix A_hat = blockdiag(M_T)
+ * and a constraint matrix C whose null space is the conforming subspace, the
+ * Lagrange multipliers solve H lambda = C A_hat^{-1} f_hat with the SPD matrix
+ * H = C A_hat^{-1} C^T, and the broken solution is
+ * x_hat = A_hat^{-1} (f_hat - C^T lambda).  H is the sum over elements of
+ * H_T = C_T M_T^{-1} C_T^T, the inverse of the element Schur complement on
+ * its face dofs with signs (Sec. 3.1 and Sec. 5).
+ *
+ * Call order: hyb_plan_create (host only, no GPU needed) -> hyb_bind ->
+ * hyb_setup -> [hyb_rhs] -> hyb_solve -> hyb_recover -> hyb_destroy.
+ *
+ * Conventions (fixed by this library; the paper leaves them to its FE code):
+ *   - element vertex v = a + 2b + 4c sits at reference corner (a,b,c) of
+ *     [0,1]^3; the geometry is the trilinear map of the 8 vertices and every
+ *     element must have det J > 0;
+ *   - face f = 2d + s is the face xi_d = s, outward sign eps_f = 2s - 1;
+ *     faces on the domain boundary are essential (prescribed normal flux g);
+ *   - local dof order is interior dofs first (3 k (k+1)^2 of them), then the
+ *     (k+1)^2 dofs of face 0, ..., face 5; a face dof (j0, j1) has index
+ *     n_i + f (k+1)^2 + j0 + (k+1) j1; dofs are nodal normal components at
+ *     Gauss-Lobatto (normal direction) x Gauss-Legendre (tangential) nodes;
+ *   - interior faces are numbered by increasing (owner, owner's local face),
+ *     the owner being the element with the smaller index; multiplier
+ *     mu = face (k+1)^2 + j0 + (k+1) j1 in the owner's face frame;
+ *   - H is CSR: rows mu ascending, columns ascending, int64 row_ptr, int32
+ *     columns, double values.
+ *
+ * Errors: every call returns HYB_OK (0) or a negative HYB_E_* code; no
+ * exception crosses the ABI.  Device-side failures (det J <= 0 at a
+ * quadrature point, a non-positive Cholesky pivot) are recorded in the bound
+ * status buffer and reported by hyb_status after the stream is synchronised.
+ * Device calls are asynchronous on the stream given in hyb_opts.
+ *
+ * Memory: the caller owns every device buffer (hyb_buffers); the plan owns
+ * only host metadata.  Device pointers must stay valid until hyb_destroy.
+ */
+#ifndef HYB_H
+#define HYB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum hyb_status_code {
+  HYB_OK = 0,
+  HYB_E_ARG = -1,       /* bad argument: k outside 0..3, null pointer, size */
+  HYB_E_MESH = -2,      /* vertex id out of range, face shared by > 2 elements */
+  HYB_E_JACOBIAN = -3,  /* det J <= 0 (host corner check or device qp check) */
+  HYB_E_NOT_SPD = -4,   /* non-positive pivot in an element Cholesky */
+  HYB_E_STATE = -5,     /* call out of order (e.g. rhs before setup) */
+  HYB_E_NOMEM = -6,     /* a bound buffer is missing */
+  HYB_E_NOCONV = -7,    /* PCG did not reach rtol within maxit */
+  HYB_E_HIP = -8        /* HIP runtime error; detail holds the hipError_t */
+};
+
+enum hyb_precision {
+  HYB_FP64 = 0          /* every step in double precision */
+};
+
+typedef struct hyb_mesh {
+  int64_t nv;             /* number of vertices */
+  int64_t ne;             /* number of hexahedra */
+  const double* xyz;      /* host, nv x 3, row-major */
+  const int32_t* e2v;     /* host, ne x 8, vertex v = a + 2b + 4c */
+} hyb_mesh;
+
+typedef struct hyb_opts {
+  int precision;          /* HYB_FP64 */
+  void* stream;           /* hipStream_t for every device call; NULL = null stream */
+} hyb_opts;
+
+/* Sizes of the caller-owned device buffers, filled by hyb_plan_create. */
+typedef struct hyb_sizes {
+  int64_t ne;             /* elements */
+  int32_t k;              /* order */
+  int32_t n_local;        /* broken dofs per element, 3 (k+1)^2 (k+2) */
+  int32_t n_interior;     /* 3 k (k+1)^2 */
+  int32_t n_face_dofs;    /* (k+1)^2 */
+  int64_t n_faces;        /* interior faces */
+  int64_t n_boundary_faces;
+  int64_t m;              /* multipliers = n_faces (k+1)^2 */
+  int64_t nnz;            /* nonzeros of H */
+  int64_t factor_len;     /* doubles per element in the factor buffer */
+  int64_t bytes_maps;     /* device map buffer (topology, geometry, tables) */
+  int64_t bytes_factor;   /* ne * factor_len * 8 */
+  int64_t bytes_y;        /* ne * n_local * 8 (cached L^{-1} f_hat) */
+  int64_t bytes_work;     /* PCG work vectors and reductions */
+} hyb_sizes;
+
+/* Caller-allocated device buffers (e.g. torch tensors' data pointers). */
+typedef struct hyb_buffers {
+  void* maps;             /* bytes_maps */
+  double* factor;         /* bytes_factor */
+  double* y;              /* bytes_y */
+  int64_t* row_ptr;       /* m + 1 */
+  int32_t* col;           /* nnz */
+  double* val;            /* nnz */
+  double* r;              /* m: the reduced right-hand side */
+  double* work;           /* bytes_work */
+  int32_t* status;        /* 4 ints: code, first failing element, spare */
+} hyb_buffers;
+
+typedef struct hyb_solve_info {
+  int32_t iters;          /* PCG iterations done */
+  int32_t converged;      /* 1 if ||r_k|| <= rtol ||r_0|| */
+  double rel_res;         /* ||r_k|| / ||r_0|| (2-norm) */
+} hyb_solve_info;
+
+typedef struct hyb_plan hyb_plan_t;
+
+/*
+ * Host-only planning (Sec. 2.3 and Sec. 5: the constraint structure).  Copies
+ * the mesh, hashes faces, finds owners and the neighbour frame codes, numbers
+ * the multipliers, builds the CSR pattern of H and the per-element scatter
+ * slots, and checks det J > 0 at the 8 corners of every element.  Needs no
+ * GPU.  On success *out owns the plan (free with hyb_destroy).
+ * Errors: HYB_E_ARG, HYB_E_MESH, HYB_E_JACOBIAN (detail via hyb_last_detail).
+ */
+int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt,
+                    hyb_plan_t** out, hyb_sizes* sizes);
+
+/*
+ * Host copies of the plan's topology, for checks (any pointer may be NULL):
+ * elem_face ne x 6 (interior face id or -1), elem_pi ne x 6 (neighbour frame
+ * code, 0 for owners and boundary faces), face_owner n_faces x 2 and
+ * face_nbr n_faces x 2 (element, local face), row_ptr m + 1, col nnz.
+ */
+int hyb_plan_topology(const hyb_plan_t* plan, int32_t* elem_face, uint8_t* elem_pi,
+                      int32_t* face_owner, int32_t* face_nbr,
+                      int64_t* row_ptr, int32_t* col);
+
+/* Element id (or other detail) of the last error on this thread. */
+int64_t hyb_last_detail(void);
+
+/*
+ * Attach caller-owned device buffers and upload the maps, row_ptr and col
+ * (asynchronously on the plan's stream).  Errors: HYB_E_NOMEM if a required
+ * pointer is NULL, HYB_E_HIP.
+ */
+int hyb_bind(hyb_plan_t* plan, const hyb_buffers* buf);
+
+/*
+ * Local assembly, factorization and global assembly (Sec. 5):
+ * per element, M_T by Gauss quadrature (q = k+2 per direction), boundary-face
+ * rows/columns replaced by identity, M_T = L L^T in i-first order, the face
+ * block L_bb inverted, H_T = D L_bb^{-T} L_bb^{-1} D (D = diag(eps)) and its
+ * scatter into H.val (each entry is a sum of at most two element terms).
+ * alpha, beta: device, ne doubles.  If f (device, ne x 3, element-constant
+ * load) is non-NULL the right-hand side is formed as in hyb_rhs in the same
+ * pass.  g (device, ne x 6 (k+1)^2 boundary normal-flux dofs, NULL = 0) is
+ * only read with f.  alpha and beta must stay valid while hyb_rhs is called
+ * with boundary data g (the correction -M_re g_e reassembles M_T from them).
+ */
+int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta,
+              const double* f, const double* g);
+
+/*
+ * Right-hand side for a new load on the current factors (Theorem 2.1):
+ * f_hat_T by quadrature (minus M_re g_e), y_T = L^{-1} f_hat_T (kept for
+ * recovery), r = sum_T C_T M_T^{-1} f_hat_T into the bound r buffer.
+ * Errors: HYB_E_STATE before hyb_setup.
+ */
+int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g);
+
+/*
+ * Jacobi-preconditioned CG on H lambda = r (device, deterministic
+ * reductions); stops when ||r_k||_2 <= rtol ||r_0||_2 or after maxit
+ * iterations.  lambda: device, m doubles (input: initial guess is zero;
+ * output: solution).  Returns HYB_E_NOCONV if not converged.
+ */
+int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda,
+              hyb_solve_info* info);
+
+/*
+ * Recovery of the broken flux (Theorem 2.1 back substitution):
+ * u_T = M_T^{-1} (f_hat_T - C_T^T lambda_T), boundary dofs = g.
+ * lambda: device, m doubles; u: device, ne x n_local doubles, local order.
+ * Errors: HYB_E_STATE before hyb_rhs / hyb_setup with f.
+ */
+int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u);
+
+/*
+ * Synchronise the plan's stream and read the device status: returns HYB_OK
+ * or the first device error (HYB_E_JACOBIAN / HYB_E_NOT_SPD); *detail (may
+ * be NULL) receives the failing element.
+ */
+int hyb_status(hyb_plan_t* plan, int64_t* detail);
+
+/* Static text for a status code. */
+const char* hyb_strerror(int code);
+
+/*
+ * Kernel timing with HIP events recorded on the plan's stream around every
+ * launch of the element setup kernel and of the recovery kernel.
+ * hyb_timing_enable(plan, 1) starts collecting (and clears earlier pairs);
+ * hyb_timing_read synchronises on the last event and returns the summed
+ * milliseconds and launch counts of each kernel since enabling (any output
+ * pointer may be NULL), then clears them.
+ */
+int hyb_timing_enable(hyb_plan_t* plan, int on);
+int hyb_timing_read(hyb_plan_t* plan, double* ms_setup, int* n_setup, double* ms_recover, int* n_recover);
+
+/* Free the plan's host state (device buffers stay with the caller). */
+void hyb_destroy(hyb_plan_t* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYB_H */

@@ -26,9 +26,9 @@ import scipy.sparse.linalg as spla
 from . import element, rt_basis, topology as topo_mod
 
 
-def _ess_code(topo, e0: int, e1: int) -> np.ndarray:
+def _ess_code_of(topo, els: np.ndarray) -> np.ndarray:
     """6-bit mask per element: bit f set when local face f is on the boundary."""
-    bnd = topo.elem_face[e0:e1] < 0
+    bnd = topo.elem_face[els] < 0
     return (bnd * (1 << np.arange(6))).sum(axis=1)
 
 
@@ -105,26 +105,25 @@ class Hybridized:
     mult_id: np.ndarray   # (ne, 6 (k+1)^2) multiplier id of every local face dof, -1 on boundary
 
 
-def hybridize(k: int, xyz, e2v, alpha, beta, f, g_face=None, topo=None, q=None, e_range=None):
+def hybridize(k: int, xyz, e2v, alpha, beta, f, g_face=None, topo=None, q=None, elements=None, mult_id=None):
     """Global H (CSR, sorted, duplicates summed) and r = sum_T C_T^T-scatter of
-    r_T.  ``e_range`` restricts the element loop (for timing samples): H and r
-    then hold only those elements' contributions."""
+    r_T.  ``elements`` (index array) restricts the element loop, for sampled
+    checks and timing samples: H and r then hold only those elements' terms
+    (a row of H is complete when both elements of its face are included)."""
     topo = topo or topo_mod.build_topology(e2v)
-    mid, _ = topo_mod.multiplier_map(topo, k)
+    mid = topo_mod.multiplier_map(topo, k)[0] if mult_id is None else mult_id
     m = topo.nfaces * rt_basis.n_face(k)
-    ne = e2v.shape[0]
-    lo, hi = e_range if e_range is not None else (0, ne)
+    els = np.arange(e2v.shape[0]) if elements is None else np.asarray(elements, dtype=np.int64)
     rows, cols, vals = [], [], []
     r = np.zeros(m)
-    for s, t, M, fT in element.element_system_chunked(k, xyz, e2v[lo:hi], alpha[lo:hi], beta[lo:hi],
-                                                      f[lo:hi], q=q):
-        s, t = s + lo, t + lo
-        codes = _ess_code(topo, s, t)
+    for s, t, M, fT in element.element_system_chunked(k, xyz, e2v[els], alpha[els], beta[els], f[els], q=q):
+        ids_el = els[s:t]
+        codes = _ess_code_of(topo, ids_el)
         for code in np.unique(codes):
             sel = np.nonzero(codes == code)[0]
-            gsel = None if g_face is None else g_face[s + sel]
+            gsel = None if g_face is None else g_face[ids_el[sel]]
             HT, rT = local_schur(k, M[sel], fT[sel], int(code), gsel)
-            keep_ids = mid[s + sel]
+            keep_ids = mid[ids_el[sel]]
             ids = keep_ids[:, keep_ids[0] >= 0]          # same mask -> same kept columns
             mT = ids.shape[1]
             rows.append(np.repeat(ids, mT, axis=1).reshape(-1))
@@ -153,24 +152,22 @@ def solve_reduced(H: sp.csr_matrix, r: np.ndarray, rtol: float = 1e-14) -> np.nd
     return spla.spsolve(H.tocsc(), r)
 
 
-def recover(hyb: Hybridized, xyz, e2v, alpha, beta, f, lam, g_face=None, q=None, e_range=None):
-    """Broken solution u (ne, n) from multipliers lam (Theorem 2.1 back
-    substitution), element by element."""
+def recover(hyb: Hybridized, xyz, e2v, alpha, beta, f, lam, g_face=None, q=None, elements=None):
+    """Broken solution u (len(elements) or ne, n) from multipliers lam
+    (Theorem 2.1 back substitution), element by element."""
     k, topo = hyb.k, hyb.topo
     n = rt_basis.ndofs(k)
-    ne = e2v.shape[0]
-    lo, hi = e_range if e_range is not None else (0, ne)
-    u = np.zeros((hi - lo, n))
-    for s, t, M, fT in element.element_system_chunked(k, xyz, e2v[lo:hi], alpha[lo:hi], beta[lo:hi],
-                                                      f[lo:hi], q=q):
-        s, t = s + lo, t + lo
-        codes = _ess_code(topo, s, t)
+    els = np.arange(e2v.shape[0]) if elements is None else np.asarray(elements, dtype=np.int64)
+    u = np.zeros((els.size, n))
+    for s, t, M, fT in element.element_system_chunked(k, xyz, e2v[els], alpha[els], beta[els], f[els], q=q):
+        ids_el = els[s:t]
+        codes = _ess_code_of(topo, ids_el)
         for code in np.unique(codes):
             sel = np.nonzero(codes == code)[0]
-            ids = hyb.mult_id[s + sel]
+            ids = hyb.mult_id[ids_el[sel]]
             ids = ids[:, ids[0] >= 0]
-            gsel = None if g_face is None else g_face[s + sel]
-            u[s + sel - lo] = local_recover(k, M[sel], fT[sel], int(code), lam[ids], gsel)
+            gsel = None if g_face is None else g_face[ids_el[sel]]
+            u[s + sel] = local_recover(k, M[sel], fT[sel], int(code), lam[ids], gsel)
     return u
 
 

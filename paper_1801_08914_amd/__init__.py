@@ -1,0 +1,181 @@
+"""MI355X hybridization library: thin Python binding over libhyb.so.
+
+Every step of the path runs in the library's HIP kernels; this module only
+marshals arguments (numpy arrays for the host-side mesh, torch tensors for
+device buffers and the current HIP stream).  There is no CPU fallback: if
+``libhyb.so`` is missing, every entry point raises.
+
+Usage::
+
+    plan = Plan(xyz, e2v, k)            # host topology (no GPU needed)
+    plan.bind()                          # device buffers on cuda:0
+    plan.setup(alpha, beta, f)           # M_T, Cholesky, H_T -> H, r
+    lam, info = plan.solve(1e-12, 2000)  # Jacobi-PCG on H
+    u = plan.recover(lam)                # broken flux, ne x n
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import _abi
+
+__all__ = ["Plan", "HybError", "load_library", "LIB_PATH"]
+
+LIB_PATH = _abi.LIB_PATH
+HybError = _abi.HybError
+load_library = _abi.load_library
+
+
+def _dptr(t):
+    return ctypes.c_void_p(0 if t is None else int(t.data_ptr()))
+
+
+class Plan:
+    """One hybridization problem: mesh + order, its topology and device buffers."""
+
+    def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None):
+        lib = load_library()
+        self._lib = lib
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.e2v = np.ascontiguousarray(e2v, dtype=np.int32)
+        self.k = int(k)
+        mesh = _abi.HybMesh(self.xyz.shape[0], self.e2v.shape[0],
+                            self.xyz.ctypes.data_as(ctypes.c_void_p),
+                            self.e2v.ctypes.data_as(ctypes.c_void_p))
+        self._stream_obj = stream
+        opts = _abi.HybOpts(0, ctypes.c_void_p(self._stream_handle()))
+        self._plan = ctypes.c_void_p()
+        sz = _abi.HybSizes()
+        rc = lib.hyb_plan_create(ctypes.byref(mesh), self.k, ctypes.byref(opts), ctypes.byref(self._plan),
+                                 ctypes.byref(sz))
+        _abi.check(lib, rc)
+        self.sizes = sz
+        self.ne, self.n, self.m, self.nnz = sz.ne, sz.n_local, sz.m, sz.nnz
+        self.bufs = None
+
+    def _stream_handle(self) -> int:
+        if self._stream_obj is None:
+            return 0                     # the null stream (torch's default stream)
+        return int(self._stream_obj.cuda_stream)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_plan", None) and self._plan.value:
+                self._lib.hyb_destroy(self._plan)
+                self._plan = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- host
+    def topology(self):
+        """Host copies: elem_face (ne,6), elem_pi (ne,6), face_owner (F,2),
+        face_nbr (F,2), row_ptr (m+1,), col (nnz,)."""
+        s = self.sizes
+        ef = np.empty((s.ne, 6), np.int32)
+        ep = np.empty((s.ne, 6), np.uint8)
+        fo = np.empty((s.n_faces, 2), np.int32)
+        fn = np.empty((s.n_faces, 2), np.int32)
+        rp = np.empty(s.m + 1, np.int64)
+        ci = np.empty(s.nnz, np.int32)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _abi.check(self._lib, self._lib.hyb_plan_topology(self._plan, p(ef), p(ep), p(fo), p(fn), p(rp), p(ci)))
+        return dict(elem_face=ef, elem_pi=ep, face_owner=fo, face_nbr=fn, row_ptr=rp, col=ci)
+
+    # -------------------------------------------------------------- device
+    def bind(self, device="cuda:0"):
+        """Allocate every device buffer with torch on ``device`` and attach it."""
+        import torch
+        s = self.sizes
+        dev = torch.device(device)
+        u8 = lambda nbytes: torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)  # noqa: E731
+        f64 = lambda n: torch.empty(max(int(n), 1), dtype=torch.float64, device=dev)  # noqa: E731
+        b = dict(
+            maps=u8(s.bytes_maps),
+            factor=f64(s.bytes_factor // 8),
+            y=f64(s.bytes_y // 8),
+            row_ptr=torch.empty(s.m + 1, dtype=torch.int64, device=dev),
+            col=torch.empty(max(s.nnz, 1), dtype=torch.int32, device=dev),
+            val=f64(s.nnz),
+            r=f64(s.m),
+            work=f64(s.bytes_work // 8 + 1),
+            status=torch.zeros(4, dtype=torch.int32, device=dev),
+        )
+        hb = _abi.HybBuffers(*[_dptr(b[name]) for name in _abi.BUFFER_FIELDS])
+        self.device = dev
+        self.bufs = b
+        _abi.check(self._lib, self._lib.hyb_bind(self._plan, ctypes.byref(hb)))
+        return self
+
+    def _dev(self, x, shape):
+        import torch
+        if x is None:
+            return None
+        t = torch.as_tensor(x, dtype=torch.float64, device=self.device).reshape(shape).contiguous()
+        return t
+
+    def setup(self, alpha, beta, f=None, g=None):
+        """Local assembly + Cholesky + H_T scatter (and the rhs when f is given)."""
+        ne = self.ne
+        self._alpha = self._dev(alpha, (ne,))
+        self._beta = self._dev(beta, (ne,))
+        self._f = self._dev(f, (ne, 3))
+        self._g = self._dev(g, (ne, 6 * (self.k + 1) ** 2))
+        rc = self._lib.hyb_setup(self._plan, _dptr(self._alpha), _dptr(self._beta), _dptr(self._f), _dptr(self._g))
+        _abi.check(self._lib, rc)
+
+    def rhs(self, f, g=None):
+        ne = self.ne
+        self._f = self._dev(f, (ne, 3))
+        self._g = self._dev(g, (ne, 6 * (self.k + 1) ** 2))
+        _abi.check(self._lib, self._lib.hyb_rhs(self._plan, _dptr(self._f), _dptr(self._g)))
+
+    def solve(self, rtol=1e-12, maxit=10000, lam=None):
+        import torch
+        if lam is None:
+            lam = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.device)
+        info = _abi.HybSolveInfo()
+        rc = self._lib.hyb_solve(self._plan, ctypes.c_double(rtol), int(maxit), _dptr(lam), ctypes.byref(info))
+        if rc not in (0, _abi.HYB_E_NOCONV):
+            _abi.check(self._lib, rc)
+        return lam[: self.m], dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res)
+
+    def recover(self, lam, u=None):
+        import torch
+        lam = self._dev(lam, (self.m,)) if not isinstance(lam, torch.Tensor) else lam.contiguous()
+        if u is None:
+            u = torch.empty((self.ne, self.n), dtype=torch.float64, device=self.device)
+        _abi.check(self._lib, self._lib.hyb_recover(self._plan, _dptr(lam), _dptr(u)))
+        return u
+
+    def status(self):
+        """Synchronise and return (code, element) of the first device error."""
+        d = ctypes.c_int64()
+        rc = self._lib.hyb_status(self._plan, ctypes.byref(d))
+        return rc, d.value
+
+    def timing(self, on: bool = True):
+        """Start (or stop) HIP-event timing of the setup and recovery kernels."""
+        _abi.check(self._lib, self._lib.hyb_timing_enable(self._plan, 1 if on else 0))
+
+    def timing_read(self):
+        """Summed kernel milliseconds since timing(True): dict with
+        setup_ms, setup_n, recover_ms, recover_n (then cleared)."""
+        ms_s, ms_r = ctypes.c_double(), ctypes.c_double()
+        n_s, n_r = ctypes.c_int(), ctypes.c_int()
+        _abi.check(self._lib, self._lib.hyb_timing_read(self._plan, ctypes.byref(ms_s), ctypes.byref(n_s),
+                                                         ctypes.byref(ms_r), ctypes.byref(n_r)))
+        return dict(setup_ms=ms_s.value, setup_n=n_s.value, recover_ms=ms_r.value, recover_n=n_r.value)
+
+    def csr(self):
+        """Device CSR arrays (row_ptr, col, val) of H."""
+        b = self.bufs
+        return b["row_ptr"], b["col"][: self.nnz], b["val"][: self.nnz]
+
+    def r(self):
+        return self.bufs["r"][: self.m]
+
+    def y(self):
+        return self.bufs["y"][: self.ne * self.n].view(self.ne, self.n)

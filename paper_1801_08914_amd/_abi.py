@@ -1,0 +1,100 @@
+"""ctypes declarations of include/hyb.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhyb.so")
+
+HYB_OK = 0
+HYB_E_ARG = -1
+HYB_E_MESH = -2
+HYB_E_JACOBIAN = -3
+HYB_E_NOT_SPD = -4
+HYB_E_STATE = -5
+HYB_E_NOMEM = -6
+HYB_E_NOCONV = -7
+HYB_E_HIP = -8
+
+# Every extern "C" symbol declared in include/hyb.h.
+EXPORTS = [
+    "hyb_plan_create", "hyb_plan_topology", "hyb_last_detail", "hyb_bind", "hyb_setup", "hyb_rhs",
+    "hyb_solve", "hyb_recover", "hyb_status", "hyb_strerror", "hyb_destroy",
+    "hyb_timing_enable", "hyb_timing_read",
+]
+
+
+class HybError(RuntimeError):
+    def __init__(self, code: int, msg: str, detail: int):
+        super().__init__(f"hyb error {code} ({msg}), detail {detail}")
+        self.code = code
+        self.detail = detail
+
+
+class HybMesh(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("xyz", ctypes.c_void_p),
+                ("e2v", ctypes.c_void_p)]
+
+
+class HybOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class HybSizes(ctypes.Structure):
+    _fields_ = [("ne", ctypes.c_int64), ("k", ctypes.c_int32), ("n_local", ctypes.c_int32),
+                ("n_interior", ctypes.c_int32), ("n_face_dofs", ctypes.c_int32),
+                ("n_faces", ctypes.c_int64), ("n_boundary_faces", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("factor_len", ctypes.c_int64), ("bytes_maps", ctypes.c_int64),
+                ("bytes_factor", ctypes.c_int64), ("bytes_y", ctypes.c_int64), ("bytes_work", ctypes.c_int64)]
+
+
+BUFFER_FIELDS = ["maps", "factor", "y", "row_ptr", "col", "val", "r", "work", "status"]
+
+
+class HybBuffers(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in BUFFER_FIELDS]
+
+
+class HybSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_res", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def load_library():
+    """Load libhyb.so from the package directory; raise if it was not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.hyb_plan_create.argtypes = [vp, ci, vp, vp, vp]
+    lib.hyb_plan_topology.argtypes = [vp] * 7
+    lib.hyb_last_detail.restype = i64
+    lib.hyb_last_detail.argtypes = []
+    lib.hyb_bind.argtypes = [vp, vp]
+    lib.hyb_setup.argtypes = [vp, vp, vp, vp, vp]
+    lib.hyb_rhs.argtypes = [vp, vp, vp]
+    lib.hyb_solve.argtypes = [vp, ctypes.c_double, ci, vp, vp]
+    lib.hyb_recover.argtypes = [vp, vp, vp]
+    lib.hyb_status.argtypes = [vp, vp]
+    lib.hyb_strerror.restype = ctypes.c_char_p
+    lib.hyb_strerror.argtypes = [ci]
+    lib.hyb_timing_enable.argtypes = [vp, ci]
+    lib.hyb_timing_read.argtypes = [vp, vp, vp, vp, vp]
+    lib.hyb_destroy.argtypes = [vp]
+    lib.hyb_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("hyb_destroy", "hyb_last_detail", "hyb_strerror"):
+            getattr(lib, name).restype = ci
+    _LIB = lib
+    return lib
+
+
+def check(lib, rc: int):
+    if rc != HYB_OK:
+        raise HybError(rc, lib.hyb_strerror(rc).decode(), int(lib.hyb_last_detail()))

@@ -1,0 +1,428 @@
+// C ABI of the hybridization library: plan, bind, setup, rhs, solve,
+// recover, status.  Kernels are in setup_generic.hpp and pcg.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/hyb.h"
+#include "pcg.hpp"
+#include "plan.hpp"
+#include "setup_generic.hpp"
+
+struct hyb_plan {
+  hyb::Plan P;
+};
+
+namespace {
+
+thread_local int64_t g_last_detail = -1;
+
+inline hipStream_t stream_of(const hyb::Plan& P) { return reinterpret_cast<hipStream_t>(P.opts.stream); }
+
+hyb::DeviceMaps device_maps(const hyb::Plan& P) {
+  const auto* base = static_cast<const uint8_t*>(P.buf.maps);
+  const auto& L = P.lay;
+  hyb::DeviceMaps m;
+  m.e2v = reinterpret_cast<const int32_t*>(base + L.e2v);
+  m.xyz = reinterpret_cast<const double*>(base + L.xyz);
+  m.elem_face = reinterpret_cast<const int32_t*>(base + L.elem_face);
+  m.elem_pi = base + L.elem_pi;
+  m.elem_slot = base + L.elem_slot;
+  m.face_rowbase = reinterpret_cast<const int64_t*>(base + L.face_rowbase);
+  m.face_nslots = reinterpret_cast<const int32_t*>(base + L.face_nslots);
+  m.tab_s = reinterpret_cast<const double*>(base + L.tab_s);
+  m.tab_d = reinterpret_cast<const double*>(base + L.tab_d);
+  m.tab_w = reinterpret_cast<const double*>(base + L.tab_w);
+  m.tab_ref = reinterpret_cast<const double*>(base + L.tab_ref);
+  m.gauss_x = reinterpret_cast<const double*>(base + L.tab_x);
+  return m;
+}
+
+int hip_fail(hipError_t err) {
+  g_last_detail = int64_t(err);
+  return HYB_E_HIP;
+}
+
+#define HYB_HIP(call)                              \
+  do {                                             \
+    hipError_t err_ = (call);                      \
+    if (err_ != hipSuccess) return hip_fail(err_); \
+  } while (0)
+
+int fill(hipStream_t s, double* x, int64_t n, double v) {
+  if (n <= 0) return HYB_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(hyb::k_fill, dim3(unsigned(blocks)), dim3(256), 0, s, x, n, v);
+  HYB_HIP(hipGetLastError());
+  return HYB_OK;
+}
+
+template <int K, int TEAM, int EPB>
+int launch_setup(const hyb::SetupArgs& a, hipStream_t s) {
+  if (a.ne == 0) return HYB_OK;
+  const int64_t blocks = (a.ne + EPB - 1) / EPB;
+  hipLaunchKernelGGL((hyb::k_setup_generic<K, TEAM, EPB>), dim3(unsigned(blocks)), dim3(TEAM * EPB), 0, s, a);
+  HYB_HIP(hipGetLastError());
+  return HYB_OK;
+}
+
+template <int K, int TEAM, int EPB>
+int launch_recover(const hyb::RecoverArgs& a, hipStream_t s) {
+  if (a.ne == 0) return HYB_OK;
+  const int64_t blocks = (a.ne + EPB - 1) / EPB;
+  hipLaunchKernelGGL((hyb::k_recover_generic<K, TEAM, EPB>), dim3(unsigned(blocks)), dim3(TEAM * EPB), 0, s, a);
+  HYB_HIP(hipGetLastError());
+  return HYB_OK;
+}
+
+int dispatch_setup(int k, const hyb::SetupArgs& a, hipStream_t s) {
+  switch (k) {
+    case 0: return launch_setup<0, 16, 16>(a, s);
+    case 1: return launch_setup<1, 64, 4>(a, s);
+    case 2: return launch_setup<2, 256, 1>(a, s);
+    default: return HYB_E_ARG;
+  }
+}
+
+int dispatch_recover(int k, const hyb::RecoverArgs& a, hipStream_t s) {
+  switch (k) {
+    case 0: return launch_recover<0, 16, 16>(a, s);
+    case 1: return launch_recover<1, 64, 4>(a, s);
+    case 2: return launch_recover<2, 256, 1>(a, s);
+    default: return HYB_E_ARG;
+  }
+}
+
+hipEvent_t take_event(hyb::Plan& P) {
+  if (!P.ev_pool.empty()) {
+    void* e = P.ev_pool.back();
+    P.ev_pool.pop_back();
+    return reinterpret_cast<hipEvent_t>(e);
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Record an event on the plan's stream into list (start or stop of a pair).
+void mark(hyb::Plan& P, std::vector<void*>& list) {
+  if (!P.timing) return;
+  hipEvent_t e = take_event(P);
+  if (!e) return;
+  hipEventRecord(e, stream_of(P));
+  list.push_back(e);
+}
+
+int64_t work_bytes(int64_t m, int nblk) { return 8 * (5 * m + 2 * int64_t(nblk)) + 256; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t hyb_last_detail(void) { return g_last_detail; }
+
+const char* hyb_strerror(int code) {
+  switch (code) {
+    case HYB_OK: return "ok";
+    case HYB_E_ARG: return "invalid argument";
+    case HYB_E_MESH: return "invalid mesh connectivity";
+    case HYB_E_JACOBIAN: return "non-positive Jacobian determinant";
+    case HYB_E_NOT_SPD: return "element matrix not positive definite";
+    case HYB_E_STATE: return "call out of order";
+    case HYB_E_NOMEM: return "missing device buffer";
+    case HYB_E_NOCONV: return "PCG did not converge";
+    case HYB_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t** out, hyb_sizes* sizes) {
+  g_last_detail = -1;
+  if (!out) return HYB_E_ARG;
+  *out = nullptr;
+  if (opt && opt->precision != HYB_FP64) return HYB_E_ARG;
+  hyb_plan* p = new (std::nothrow) hyb_plan;
+  if (!p) return HYB_E_NOMEM;
+  int64_t detail = -1;
+  int rc = hyb::build_plan(mesh, k, p->P, detail);
+  if (rc != HYB_OK) {
+    g_last_detail = detail;
+    delete p;
+    return rc;
+  }
+  if (opt) p->P.opts = *opt;
+  hyb::Plan& P = p->P;
+  int64_t nblk = (P.m + hyb::kPcgThreads * 4 - 1) / (hyb::kPcgThreads * 4);
+  if (nblk < 1) nblk = 1;
+  if (nblk > 2048) nblk = 2048;
+  P.work_blocks = int(nblk);
+  if (sizes) {
+    sizes->ne = P.ne;
+    sizes->k = k;
+    sizes->n_local = P.ord.n;
+    sizes->n_interior = P.ord.ni;
+    sizes->n_face_dofs = P.ord.K2;
+    sizes->n_faces = P.nfaces;
+    sizes->n_boundary_faces = P.nbfaces;
+    sizes->m = P.m;
+    sizes->nnz = P.nnz;
+    sizes->factor_len = P.factor_len;
+    sizes->bytes_maps = int64_t(P.lay.total);
+    sizes->bytes_factor = 8 * P.ne * P.factor_len;
+    sizes->bytes_y = 8 * P.ne * P.ord.n;
+    sizes->bytes_work = work_bytes(P.m, P.work_blocks);
+  }
+  *out = p;
+  return HYB_OK;
+}
+
+int hyb_plan_topology(const hyb_plan_t* plan, int32_t* elem_face, uint8_t* elem_pi, int32_t* face_owner,
+                      int32_t* face_nbr, int64_t* row_ptr, int32_t* col) {
+  if (!plan) return HYB_E_ARG;
+  const hyb::Plan& P = plan->P;
+  if (elem_face) std::memcpy(elem_face, P.elem_face.data(), sizeof(int32_t) * P.elem_face.size());
+  if (elem_pi)
+    for (int64_t e = 0; e < P.ne; ++e)
+      for (int f = 0; f < 6; ++f) elem_pi[6 * e + f] = P.elem_pi[size_t(8 * e + f)];
+  if (face_owner) std::memcpy(face_owner, P.face_owner.data(), sizeof(int32_t) * P.face_owner.size());
+  if (face_nbr) std::memcpy(face_nbr, P.face_nbr.data(), sizeof(int32_t) * P.face_nbr.size());
+  if (row_ptr) std::memcpy(row_ptr, P.row_ptr.data(), sizeof(int64_t) * P.row_ptr.size());
+  if (col) std::memcpy(col, P.col.data(), sizeof(int32_t) * P.col.size());
+  return HYB_OK;
+}
+
+int hyb_bind(hyb_plan_t* plan, const hyb_buffers* buf) {
+  if (!plan || !buf) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  if (!buf->maps || !buf->factor || !buf->y || !buf->val || !buf->r || !buf->work || !buf->status ||
+      (P.m > 0 && (!buf->row_ptr || !buf->col)))
+    return HYB_E_NOMEM;
+  P.buf = *buf;
+  hipStream_t s = stream_of(P);
+  std::vector<uint8_t> host(P.lay.total, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(host.data() + off, src, bytes);
+  };
+  const auto& L = P.lay;
+  put(L.e2v, P.e2v.data(), 4 * P.e2v.size());
+  put(L.xyz, P.xyz.data(), 8 * P.xyz.size());
+  put(L.elem_face, P.elem_face.data(), 4 * P.elem_face.size());
+  put(L.elem_pi, P.elem_pi.data(), P.elem_pi.size());
+  put(L.elem_slot, P.elem_slot.data(), P.elem_slot.size());
+  put(L.face_rowbase, P.face_rowbase.data(), 8 * P.face_rowbase.size());
+  put(L.face_nslots, P.face_nslots.data(), 4 * P.face_nslots.size());
+  put(L.tab_s, P.tab_s.data(), 8 * P.tab_s.size());
+  put(L.tab_d, P.tab_d.data(), 8 * P.tab_d.size());
+  put(L.tab_w, P.tab_w.data(), 8 * P.tab_w.size());
+  put(L.tab_ref, P.tab_ref.data(), 8 * P.tab_ref.size());
+  put(L.tab_x, P.tab_x.data(), 8 * P.tab_x.size());
+  HYB_HIP(hipMemcpyAsync(buf->maps, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  if (P.m > 0) {
+    HYB_HIP(hipMemcpyAsync(buf->row_ptr, P.row_ptr.data(), 8 * P.row_ptr.size(), hipMemcpyHostToDevice, s));
+    HYB_HIP(hipMemcpyAsync(buf->col, P.col.data(), 4 * P.col.size(), hipMemcpyHostToDevice, s));
+  }
+  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, s, buf->status, int64_t(4), 0);
+  HYB_HIP(hipGetLastError());
+  HYB_HIP(hipStreamSynchronize(s));  // host staging goes out of scope
+  P.bound = true;
+  P.have_setup = P.have_rhs = false;
+  return HYB_OK;
+}
+
+int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta, const double* f, const double* g) {
+  if (!plan || !alpha || !beta) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  if (!P.bound) return HYB_E_STATE;
+  hipStream_t s = stream_of(P);
+  int rc = fill(s, P.buf.val, P.nnz, 0.0);
+  if (rc) return rc;
+  if (f && (rc = fill(s, P.buf.r, P.m, 0.0))) return rc;
+  hyb::SetupArgs a{};
+  a.mp = device_maps(P);
+  a.ne = P.ne;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.f = f;
+  a.g = f ? g : nullptr;
+  a.factor = P.buf.factor;
+  a.y = P.buf.y;
+  a.Hval = P.buf.val;
+  a.r = P.buf.r;
+  a.status = P.buf.status;
+  a.mode = hyb::MODE_MATRIX | (f ? hyb::MODE_RHS : 0);
+  mark(P, P.ev_setup);
+  rc = dispatch_setup(P.ord.k, a, s);
+  mark(P, P.ev_setup);
+  if (rc) return rc;
+  P.have_setup = true;
+  P.have_rhs = f != nullptr;
+  P.alpha_d = alpha;
+  P.beta_d = beta;
+  return HYB_OK;
+}
+
+int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g) {
+  if (!plan || !f) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  if (!P.have_setup) return HYB_E_STATE;
+  hipStream_t s = stream_of(P);
+  int rc = fill(s, P.buf.r, P.m, 0.0);
+  if (rc) return rc;
+  hyb::SetupArgs a{};
+  a.mp = device_maps(P);
+  a.ne = P.ne;
+  // the boundary correction -M_re g_e reassembles M_T from setup's coefficients
+  a.alpha = P.alpha_d;
+  a.beta = P.beta_d;
+  a.f = f;
+  a.g = g;
+  a.factor = P.buf.factor;
+  a.y = P.buf.y;
+  a.Hval = P.buf.val;
+  a.r = P.buf.r;
+  a.status = P.buf.status;
+  a.mode = hyb::MODE_RHS;
+  rc = dispatch_setup(P.ord.k, a, s);
+  if (rc) return rc;
+  P.have_rhs = true;
+  return HYB_OK;
+}
+
+int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solve_info* info) {
+  if (!plan || !lambda || maxit < 0) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  if (!P.have_rhs) return HYB_E_STATE;
+  hipStream_t s = stream_of(P);
+  const int64_t m = P.m;
+  const int nblk = P.work_blocks;
+  double* w = P.buf.work;
+  double* r = w;
+  double* z = r + m;
+  double* p = z + m;
+  double* q = p + m;
+  double* dinv = q + m;
+  double* part = dinv + m;
+  auto* sc = reinterpret_cast<hyb::PcgScalars*>(
+      reinterpret_cast<uint8_t*>(part) + ((8 * 2 * size_t(nblk) + 63) & ~size_t(63)));
+  if (info) *info = hyb_solve_info{0, 0, 0.0};
+  if (m == 0) {
+    if (info) info->converged = 1;
+    return HYB_OK;
+  }
+  const dim3 grid{unsigned(nblk), 1, 1};
+  const dim3 blk{unsigned(hyb::kPcgThreads), 1, 1};
+  hipLaunchKernelGGL(hyb::k_pcg_init, grid, blk, 0, s, m, P.buf.row_ptr, P.buf.col, P.buf.val, P.buf.r, lambda, r,
+                     z, p, dinv, part, nblk);
+  hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part, nblk, sc, 0);
+  HYB_HIP(hipGetLastError());
+  hyb::PcgScalars hs{};
+  HYB_HIP(hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HYB_HIP(hipStreamSynchronize(s));
+  const double rr0 = hs.rr0;
+  const double tol2 = rtol * rtol * rr0;
+  int it = 0;
+  bool conv = rr0 <= tol2 || rr0 == 0.0;
+  double rr = rr0;
+  const int check = 8;
+  while (!conv && it < maxit) {
+    const int batch = (maxit - it) < check ? (maxit - it) : check;
+    for (int b = 0; b < batch; ++b) {
+      hipLaunchKernelGGL(hyb::k_pcg_spmv, grid, blk, 0, s, m, P.buf.row_ptr, P.buf.col, P.buf.val, p, q, part, nblk);
+      hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part, nblk, sc, 1);
+      hipLaunchKernelGGL(hyb::k_pcg_update, grid, blk, 0, s, m, sc, p, q, dinv, lambda, r, z, part, nblk);
+      hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part, nblk, sc, 2);
+      hipLaunchKernelGGL(hyb::k_pcg_direction, grid, blk, 0, s, m, sc, z, p);
+    }
+    HYB_HIP(hipGetLastError());
+    it += batch;
+    HYB_HIP(hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HYB_HIP(hipStreamSynchronize(s));
+    rr = hs.rr;
+    conv = rr <= tol2;
+  }
+  if (info) {
+    info->iters = it;
+    info->converged = conv ? 1 : 0;
+    info->rel_res = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
+  }
+  return conv ? HYB_OK : HYB_E_NOCONV;
+}
+
+int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u) {
+  if (!plan || !lambda || !u) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  if (!P.have_rhs) return HYB_E_STATE;
+  hyb::RecoverArgs a{};
+  a.mp = device_maps(P);
+  a.ne = P.ne;
+  a.factor = P.buf.factor;
+  a.y = P.buf.y;
+  a.lambda = lambda;
+  a.u = u;
+  mark(P, P.ev_recover);
+  int rc = dispatch_recover(P.ord.k, a, stream_of(P));
+  mark(P, P.ev_recover);
+  return rc;
+}
+
+int hyb_timing_enable(hyb_plan_t* plan, int on) {
+  if (!plan) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  for (void* e : P.ev_setup) P.ev_pool.push_back(e);
+  for (void* e : P.ev_recover) P.ev_pool.push_back(e);
+  P.ev_setup.clear();
+  P.ev_recover.clear();
+  P.timing = on != 0;
+  return HYB_OK;
+}
+
+int hyb_timing_read(hyb_plan_t* plan, double* ms_setup, int* n_setup, double* ms_recover, int* n_recover) {
+  if (!plan) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  HYB_HIP(hipStreamSynchronize(stream_of(P)));
+  auto sum = [&](std::vector<void*>& L, double* ms, int* cnt) -> int {
+    double tot = 0.0;
+    int c = 0;
+    for (size_t i = 0; i + 1 < L.size(); i += 2) {
+      float t = 0.0f;
+      hipError_t err = hipEventElapsedTime(&t, reinterpret_cast<hipEvent_t>(L[i]), reinterpret_cast<hipEvent_t>(L[i + 1]));
+      if (err != hipSuccess) return hip_fail(err);
+      tot += t;
+      ++c;
+    }
+    for (void* e : L) P.ev_pool.push_back(e);
+    L.clear();
+    if (ms) *ms = tot;
+    if (cnt) *cnt = c;
+    return HYB_OK;
+  };
+  int rc = sum(P.ev_setup, ms_setup, n_setup);
+  if (rc) return rc;
+  return sum(P.ev_recover, ms_recover, n_recover);
+}
+
+int hyb_status(hyb_plan_t* plan, int64_t* detail) {
+  if (!plan) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  if (!P.bound) return HYB_E_STATE;
+  hipStream_t s = stream_of(P);
+  int32_t st[4] = {0, 0, 0, 0};
+  HYB_HIP(hipMemcpyAsync(st, P.buf.status, sizeof(st), hipMemcpyDeviceToHost, s));
+  HYB_HIP(hipStreamSynchronize(s));
+  if (detail) *detail = st[0] ? int64_t(st[1]) : -1;
+  return st[0];
+}
+
+void hyb_destroy(hyb_plan_t* plan) {
+  if (!plan) return;
+  hyb::Plan& P = plan->P;
+  for (auto* L : {&P.ev_setup, &P.ev_recover, &P.ev_pool})
+    for (void* e : *L) hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
+  delete plan;
+}
+
+}  // extern "C"

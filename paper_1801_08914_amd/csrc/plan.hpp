@@ -1,0 +1,81 @@
+// Host-side plan of the hybridization library: mesh copy, topology of the
+// constraint matrix C (faces, owners, neighbour frame codes, multiplier ids),
+// the CSR pattern of H with per-element scatter slots, reference basis tables
+// at the quadrature points, and the layout of the caller-owned device buffers.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hyb.h"
+
+namespace hyb {
+
+// Per-order constants of RT_k on hexahedra.
+struct Order {
+  int k = 0;
+  int K1 = 1;     // k + 1 open (Gauss-Legendre) points per tangential axis
+  int K2 = 1;     // (k+1)^2 dofs per face
+  int n = 6;      // 3 (k+1)^2 (k+2) broken dofs per element
+  int ni = 0;     // 3 k (k+1)^2 interior dofs
+  int nb = 6;     // 6 (k+1)^2 face dofs
+  int q1 = 2;     // Gauss points per direction (k + 2)
+  int Q = 8;      // q1^3
+  explicit Order(int k_ = 0);
+};
+
+// Byte offsets of every array inside the device "maps" buffer.
+struct MapLayout {
+  size_t e2v = 0, xyz = 0, elem_face = 0, elem_pi = 0, elem_slot = 0,
+         face_rowbase = 0, face_nslots = 0, tab_s = 0, tab_d = 0, tab_w = 0,
+         tab_ref = 0, tab_x = 0, total = 0;
+};
+
+struct Plan {
+  Order ord;
+  int64_t ne = 0, nv = 0;
+  std::vector<double> xyz;          // nv x 3
+  std::vector<int32_t> e2v;         // ne x 8
+  // topology
+  int64_t nfaces = 0, nbfaces = 0;  // interior / boundary faces
+  std::vector<int32_t> elem_face;   // ne x 6, interior face id or -1
+  std::vector<uint8_t> elem_pi;     // ne x 8 (6 used), neighbour frame code
+  std::vector<int32_t> face_owner;  // nfaces x 2 (element, local face)
+  std::vector<int32_t> face_nbr;    // nfaces x 2
+  // CSR of H and scatter slots
+  int64_t m = 0, nnz = 0;
+  std::vector<int64_t> row_ptr;     // m + 1
+  std::vector<int32_t> col;         // nnz
+  std::vector<int64_t> face_rowbase;  // nfaces: row_ptr of the face's first row
+  std::vector<int32_t> face_nslots;   // nfaces: faces in the face's rows
+  std::vector<uint8_t> elem_slot;     // ne x 36: slot of face b in face a's rows
+  // reference tables at the Gauss points (axis 0 fastest)
+  std::vector<double> tab_s;        // Q x n: basis value (its only nonzero component)
+  std::vector<double> tab_d;        // Q x n: reference divergence
+  std::vector<double> tab_w;        // Q: weights
+  std::vector<double> tab_ref;      // affine reference integrals (see plan.cpp)
+  std::vector<double> tab_x;        // q1 Gauss points on [0,1]
+  MapLayout lay;
+  int64_t factor_len = 0;
+  // device state
+  hyb_opts opts{};
+  hyb_buffers buf{};
+  bool bound = false, have_setup = false, have_rhs = false;
+  const double* alpha_d = nullptr;  // coefficients of the last setup (caller-owned)
+  const double* beta_d = nullptr;
+  int work_blocks = 0;
+  // optional HIP-event timing of the main kernels (hipEvent_t kept as void*)
+  bool timing = false;
+  std::vector<void*> ev_setup, ev_recover;  // start/stop pairs, in launch order
+  std::vector<void*> ev_pool;
+};
+
+int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail);
+
+// 1D rules written for this library (Newton on Legendre polynomials).
+void gauss_legendre_01(int q, std::vector<double>& x, std::vector<double>& w);
+void gauss_lobatto_01(int npts, std::vector<double>& x);
+
+}  // namespace hyb

@@ -1,0 +1,349 @@
+// Generic per-element setup / rhs / recovery kernels: one team of threads per
+// element, the element matrix packed in LDS.  Used for every order whose
+// packed FP64 matrix fits in LDS; faster order-specific kernels may replace
+// it for particular k.
+#pragma once
+
+#include "kernels_common.hpp"
+
+namespace hyb {
+
+enum : int { MODE_MATRIX = 1, MODE_RHS = 2 };
+
+struct SetupArgs {
+  DeviceMaps mp;
+  int64_t ne;
+  const double* alpha;
+  const double* beta;
+  const double* f;       // ne x 3 or null
+  const double* g;       // ne x nb or null
+  double* factor;        // ne x npk
+  double* y;             // ne x n
+  double* Hval;
+  double* r;
+  int32_t* status;
+  int mode;
+};
+
+struct RecoverArgs {
+  DeviceMaps mp;
+  int64_t ne;
+  const double* factor;
+  const double* y;
+  const double* lambda;
+  double* u;
+};
+
+// index of the symmetric 3x3 pair (d, e) in (00, 01, 02, 11, 12, 22)
+__device__ __forceinline__ int gidx(int d, int e) {
+  int lo = d < e ? d : e, hi = d < e ? e : d;
+  return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+}
+
+template <int K, int TEAM, int EPB>
+struct GenericLayout {
+  using R = RT<K>;
+  static constexpr int QD = 10;  // per-qp: 6 weighted metric terms, div weight, 3 load weights
+  static constexpr int per = R::npk + R::nbpk + R::Q * QD + R::n + 24 + R::nb;
+};
+
+// Local assembly (Gauss quadrature), essential-face masking, packed
+// Cholesky in i-first order, inversion of the face block, H_T scatter, and
+// the right-hand side y = L^{-1} f_hat, r_T = D L_bb^{-T} y_b.
+template <int K, int TEAM, int EPB>
+__global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
+  using R = RT<K>;
+  using Lay = GenericLayout<K, TEAM, EPB>;
+  constexpr int n = R::n, ni = R::ni, nb = R::nb, K1 = R::K1, K2 = R::K2, Q = R::Q, q1 = R::q1;
+  constexpr int QD = Lay::QD;
+  __shared__ double smem[EPB * Lay::per];
+  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  const int64_t e = int64_t(blockIdx.x) * EPB + team;
+  const bool live = e < a.ne;
+  const int64_t es = live ? e : 0;  // safe index for loads of padding teams
+  double* A = smem + team * Lay::per;
+  double* Li = A + R::npk;
+  double* qd = Li + R::nbpk;
+  double* fh = qd + Q * QD;
+  double* xe = fh + n;
+  double* tb = xe + 24;
+  const DeviceMaps& mp = a.mp;
+
+  int fid[6], pic[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    fid[f] = mp.elem_face[es * 6 + f];
+    pic[f] = mp.elem_pi[es * 8 + f];
+  }
+  auto is_ess = [&](int i) { return i >= ni && fid[(i - ni) / K2] < 0; };
+
+  for (int t = lane; t < 24; t += TEAM) xe[t] = mp.xyz[3 * int64_t(mp.e2v[es * 8 + t / 3]) + t % 3];
+  __syncthreads();
+
+  const double al = a.alpha ? a.alpha[es] : 0.0, be = a.beta ? a.beta[es] : 0.0;
+  double fv[3] = {0.0, 0.0, 0.0};
+  if (a.mode & MODE_RHS) {
+    fv[0] = a.f[es * 3 + 0]; fv[1] = a.f[es * 3 + 1]; fv[2] = a.f[es * 3 + 2];
+  }
+  const bool need_matrix = (a.mode & MODE_MATRIX) || ((a.mode & MODE_RHS) && a.g);
+  for (int q = lane; q < Q; q += TEAM) {
+    double xi[3] = {mp.gauss_x[q % q1], mp.gauss_x[(q / q1) % q1], mp.gauss_x[q / (q1 * q1)]};
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      double fa[3], ga[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int bit = (v >> c) & 1;
+        fa[c] = bit ? xi[c] : 1.0 - xi[c];
+        ga[c] = bit ? 1.0 : -1.0;
+      }
+      const double dN[3] = {ga[0] * fa[1] * fa[2], fa[0] * ga[1] * fa[2], fa[0] * fa[1] * ga[2]};
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) J[r][c] += xe[3 * v + r] * dN[c];
+    }
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (live && !(det > 0.0)) report_error(a.status, HYB_E_JACOBIAN, e);
+    const double w = mp.tab_w[q];
+    if (need_matrix) {
+      const double s = w * al / det;
+      double G[6];
+      int t = 0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = d; c < 3; ++c) G[t++] = J[0][d] * J[0][c] + J[1][d] * J[1][c] + J[2][d] * J[2][c];
+#pragma unroll
+      for (int t2 = 0; t2 < 6; ++t2) qd[q * QD + t2] = s * G[t2];
+      qd[q * QD + 6] = w * be / det;
+    }
+    if (a.mode & MODE_RHS) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) qd[q * QD + 7 + d] = w * (fv[0] * J[0][d] + fv[1] * J[1][d] + fv[2] * J[2][d]);
+    }
+  }
+  __syncthreads();
+
+  if (need_matrix) {
+    for (int p = lane; p < R::npk; p += TEAM) {
+      int i, j;
+      unpk(p, i, j);
+      const int gi = gidx(R::comp(i), R::comp(j));
+      double s = 0.0;
+      for (int q = 0; q < Q; ++q)
+        s += qd[q * QD + gi] * mp.tab_s[q * n + i] * mp.tab_s[q * n + j] +
+             qd[q * QD + 6] * mp.tab_d[q * n + i] * mp.tab_d[q * n + j];
+      A[p] = s;
+    }
+    __syncthreads();
+  }
+  if (a.mode & MODE_RHS) {
+    for (int i = lane; i < n; i += TEAM) {
+      const int d = R::comp(i);
+      double s = 0.0;
+      for (int q = 0; q < Q; ++q) s += mp.tab_s[q * n + i] * qd[q * QD + 7 + d];
+      if (is_ess(i)) {
+        s = a.g ? a.g[es * nb + (i - ni)] : 0.0;
+      } else if (a.g) {
+        // f_r -= M_re g_e (unmasked matrix)
+        for (int j = ni; j < n; ++j)
+          if (is_ess(j)) s -= A[i > j ? pk(i, j) : pk(j, i)] * a.g[es * nb + (j - ni)];
+      }
+      fh[i] = s;
+    }
+    __syncthreads();
+  }
+
+  if (a.mode & MODE_MATRIX) {
+    // boundary faces are essential: identity rows/columns
+    for (int p = lane; p < R::npk; p += TEAM) {
+      int i, j;
+      unpk(p, i, j);
+      if (is_ess(i) || is_ess(j)) A[p] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // Right-looking Cholesky, one barrier per column: the trailing update
+    // uses the unscaled column; the column is scaled afterwards (it is never
+    // read again by later steps).
+    for (int c = 0; c < n; ++c) {
+      double d = A[pk(c, c)];
+      if (!(d > 0.0)) {
+        if (live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
+        d = 1.0;
+      }
+      const double inv = 1.0 / d;
+      const int m1 = n - c - 1;
+      const int tri = m1 * (m1 + 1) / 2;
+      for (int t = lane; t < tri; t += TEAM) {
+        int ii, jj;
+        unpk(t, ii, jj);
+        const int i = c + 1 + ii, j = c + 1 + jj;
+        A[pk(i, j)] -= A[pk(i, c)] * (A[pk(j, c)] * inv);
+      }
+      __syncthreads();
+      const double sq = sqrt(d), is = 1.0 / sq;
+      for (int i = c + 1 + lane; i < n; i += TEAM) A[pk(i, c)] *= is;
+      if (lane == 0) A[pk(c, c)] = sq;
+    }
+    __syncthreads();
+    // Inverse of the face block L_bb, one column per thread.
+    for (int col = lane; col < nb; col += TEAM) {
+      Li[pk(col, col)] = 1.0 / A[pk(ni + col, ni + col)];
+      for (int i = col + 1; i < nb; ++i) {
+        double s = 0.0;
+        for (int c = col; c < i; ++c) s += A[pk(ni + i, ni + c)] * Li[pk(c, col)];
+        Li[pk(i, col)] = -s / A[pk(ni + i, ni + i)];
+      }
+    }
+    __syncthreads();
+    // H_T = D L_bb^{-T} L_bb^{-1} D, scattered into H (lower triangle computed,
+    // mirrored; same-face blocks receive two element terms by atomic add).
+    if (live) {
+      for (int t = lane; t < R::nbpk; t += TEAM) {
+        int aa, bb;
+        unpk(t, aa, bb);
+        const int fa = aa / K2, fb = bb / K2;
+        if (fid[fa] < 0 || fid[fb] < 0) continue;
+        double h = 0.0;
+        for (int c = aa; c < nb; ++c) h += Li[pk(c, aa)] * Li[pk(c, bb)];
+        const double v = ((fa ^ fb) & 1) ? -h : h;
+        int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
+        frame_map(pic[fa], K, a0, a1);
+        frame_map(pic[fb], K, b0, b1);
+        const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
+        const int Fa = fid[fa], Fb = fid[fb];
+        const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
+                            mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
+        const int64_t pba = mp.face_rowbase[Fb] + int64_t(jb) * mp.face_nslots[Fb] * K2 +
+                            mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
+        if (fa == fb) {
+          atomicAdd(&a.Hval[pab], v);
+          if (aa != bb) atomicAdd(&a.Hval[pba], v);
+        } else {
+          a.Hval[pab] = v;
+          a.Hval[pba] = v;
+        }
+      }
+    }
+  } else if (a.mode & MODE_RHS) {
+    // rhs only: bring the stored factor back (face block holds L_bb^{-1})
+    for (int p = lane; p < R::npk; p += TEAM) {
+      int i, j;
+      unpk(p, i, j);
+      const double v = a.factor[es * R::npk + p];
+      if (i >= ni && j >= ni) Li[pk(i - ni, j - ni)] = v; else A[p] = v;
+    }
+    __syncthreads();
+  }
+
+  if (a.mode & MODE_RHS) {
+    // y_i = L_ii^{-1} f_i (column-oriented, one barrier per column)
+    for (int c = 0; c < ni; ++c) {
+      const double yc = fh[c] / A[pk(c, c)];
+      for (int i = c + 1 + lane; i < ni; i += TEAM) fh[i] -= A[pk(i, c)] * yc;
+      __syncthreads();
+      if (lane == 0) fh[c] = yc;
+    }
+    __syncthreads();
+    // y_b = L_bb^{-1} (f_b - L_bi y_i)
+    for (int b = lane; b < nb; b += TEAM) {
+      double s = fh[ni + b];
+      for (int j = 0; j < ni; ++j) s -= A[pk(ni + b, j)] * fh[j];
+      tb[b] = s;
+    }
+    __syncthreads();
+    for (int b = lane; b < nb; b += TEAM) {
+      double s = 0.0;
+      for (int c = 0; c <= b; ++c) s += Li[pk(b, c)] * tb[c];
+      fh[ni + b] = s;
+    }
+    __syncthreads();
+    if (live) {
+      for (int i = lane; i < n; i += TEAM) a.y[e * n + i] = fh[i];
+      // r_T = D L_bb^{-T} y_b
+      for (int b = lane; b < nb; b += TEAM) {
+        const int fb = b / K2;
+        if (fid[fb] < 0) continue;
+        double s = 0.0;
+        for (int c = b; c < nb; ++c) s += Li[pk(c, b)] * fh[ni + c];
+        if (!(fb & 1)) s = -s;
+        int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
+        frame_map(pic[fb], K, b0, b1);
+        atomicAdd(&a.r[int64_t(fid[fb]) * K2 + b0 + K1 * b1], s);
+      }
+    }
+  }
+
+  if ((a.mode & MODE_MATRIX) && live) {
+    for (int p = lane; p < R::npk; p += TEAM) {
+      int i, j;
+      unpk(p, i, j);
+      a.factor[e * R::npk + p] = (i >= ni && j >= ni) ? Li[pk(i - ni, j - ni)] : A[p];
+    }
+  }
+}
+
+// u_T = L^{-T} (y - [0; L_bb^{-1} D lambda_b]) from the stored factor.
+template <int K, int TEAM, int EPB>
+__global__ __launch_bounds__(TEAM* EPB) void k_recover_generic(RecoverArgs a) {
+  using R = RT<K>;
+  constexpr int n = R::n, ni = R::ni, nb = R::nb, K1 = R::K1, K2 = R::K2;
+  constexpr int per = 2 * n + nb;
+  __shared__ double smem[EPB * per];
+  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  const int64_t e = int64_t(blockIdx.x) * EPB + team;
+  const bool live = e < a.ne;
+  const int64_t es = live ? e : 0;
+  double* yv = smem + team * per;   // y, then v / u
+  double* zb = yv + n;              // z_b, then u_b
+  double* tl = zb + n;              // D lambda_b
+  const double* F = a.factor + es * R::npk;
+  const DeviceMaps& mp = a.mp;
+  for (int i = lane; i < n; i += TEAM) yv[i] = a.y[es * n + i];
+  for (int b = lane; b < nb; b += TEAM) {
+    const int fb = b / K2;
+    const int F_ = mp.elem_face[es * 6 + fb];
+    double v = 0.0;
+    if (F_ >= 0) {
+      int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
+      frame_map(mp.elem_pi[es * 8 + fb], K, b0, b1);
+      v = a.lambda[int64_t(F_) * K2 + b0 + K1 * b1];
+      if (!(fb & 1)) v = -v;
+    }
+    tl[b] = v;
+  }
+  __syncthreads();
+  for (int b = lane; b < nb; b += TEAM) {
+    double s = yv[ni + b];
+    for (int c = 0; c <= b; ++c) s -= F[pk(ni + b, ni + c)] * tl[c];
+    zb[b] = s;
+  }
+  __syncthreads();
+  for (int b = lane; b < nb; b += TEAM) {
+    double s = 0.0;
+    for (int c = b; c < nb; ++c) s += F[pk(ni + c, ni + b)] * zb[c];
+    tl[b] = s;  // u_b
+  }
+  __syncthreads();
+  for (int j = lane; j < ni; j += TEAM) {
+    double s = yv[j];
+    for (int b = 0; b < nb; ++b) s -= F[pk(ni + b, j)] * tl[b];
+    zb[j] = s;
+  }
+  __syncthreads();
+  for (int c = ni - 1; c >= 0; --c) {
+    const double uc = zb[c] / F[pk(c, c)];
+    for (int j = lane; j < c; j += TEAM) zb[j] -= F[pk(c, j)] * uc;
+    __syncthreads();
+    if (lane == 0) zb[c] = uc;
+  }
+  __syncthreads();
+  if (live)
+    for (int i = lane; i < n; i += TEAM) a.u[e * n + i] = i < ni ? zb[i] : tl[i - ni];
+}
+
+}  // namespace hyb

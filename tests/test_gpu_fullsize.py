@@ -1,0 +1,88 @@
+"""GPU parity at full workload sizes, on sampled outputs the oracle computes
+one by one: complete rows of H and r for sampled faces (both elements of
+each face are computed by the oracle), and u of sampled elements for a seeded
+multiplier vector.  Same tolerances as test_gpu_parity: against the
+long-double reference, the GPU is at least as accurate as the FP64 oracle
+(floor 1e-12)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg  # noqa: F401  (sp.linalg.norm)
+
+import synth
+from oracle import extended as oext
+from oracle import hybrid as ohyb
+from oracle import topology as otopo
+from tests.gpu_common import accuracy_bound, gpu_setup, ld_row_errors, norm_rel, rel_inf, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _sampled_parity(prob, nface=24, nel=24, seed=0):
+    torch = require_gpu()
+    k, mesh = prob.k, prob.mesh
+    print(f"workload {prob.name}: {mesh.ne} elements, k={k}", flush=True)
+    plan = gpu_setup(mesh, k, prob.alpha, prob.beta, prob.f)
+    rng = np.random.default_rng(seed)
+    topo = otopo.build_topology(mesh.e2v)
+    faces = np.sort(rng.choice(topo.nfaces, size=nface, replace=False))
+    els = np.unique(np.concatenate([topo.face_owner[faces, 0], topo.face_nbr[faces, 0],
+                                    rng.choice(mesh.ne, size=nel, replace=False)]))
+    K2 = (k + 1) ** 2
+    rows = (faces[:, None] * K2 + np.arange(K2)[None, :]).ravel()
+    # GPU rows of H and r
+    rp_d, ci_d, val_d = plan.csr()
+    rp = rp_d.cpu().numpy()
+    rg = plan.r().cpu().numpy()
+    data, indices, indptr = [], [], [0]
+    # a CSR holding only the sampled rows (others empty)
+    want = set(rows.tolist())
+    for mu in range(plan.m):
+        if mu in want:
+            a, b = int(rp[mu]), int(rp[mu + 1])
+            data.append(val_d[a:b].cpu().numpy())
+            indices.append(ci_d[a:b].cpu().numpy())
+            indptr.append(indptr[-1] + b - a)
+        else:
+            indptr.append(indptr[-1])
+    Hg = sp.csr_matrix((np.concatenate(data), np.concatenate(indices), np.array(indptr)), shape=(plan.m, plan.m))
+    args = (k, mesh.xyz, mesh.e2v, prob.alpha, prob.beta, prob.f)
+    ref = ohyb.hybridize(*args, topo=topo, elements=els)
+    lam = np.random.default_rng(seed + 1).standard_normal(plan.m)
+    Hld, rld, U = oext.hybridize_ld(*args, topo, els, lam)
+    # normwise over the sampled rows against the FP64 oracle
+    nH = sp.linalg.norm(ref.H[rows] - Hg[rows]) / sp.linalg.norm(ref.H[rows])
+    nr = norm_rel(ref.r[rows], rg[rows])
+    eg, erg = ld_row_errors(Hld, rld, rows, Hg, rg)
+    eo, ero = ld_row_errors(Hld, rld, rows, ref.H, ref.r)
+    u = plan.recover(torch.as_tensor(lam, device="cuda")).cpu().numpy()[els]
+    uref = ohyb.recover(ref, mesh.xyz, mesh.e2v, prob.alpha, prob.beta, prob.f, lam, elements=els)
+    ul = np.array([U[e].astype(float) for e in els])
+    nu = norm_rel(uref, u)
+    eug, euo = rel_inf(ul, u), rel_inf(ul, uref)
+    print(f"  {len(rows)} rows / {len(els)} elements: normwise vs oracle H {nH:.1e} r {nr:.1e} u {nu:.1e}; "
+          f"vs long double GPU H {eg:.1e} r {erg:.1e} u {eug:.1e}, FP64 oracle H {eo:.1e} r {ero:.1e} "
+          f"u {euo:.1e}", flush=True)
+    assert eg <= accuracy_bound(eo) and erg <= accuracy_bound(ero) and eug <= accuracy_bound(euo)
+    # normwise over the sampled rows / elements, against long double
+    rowpos = {int(mu): i for i, mu in enumerate(rows)}
+    ri, cj, vv = [], [], []
+    for (mu, nu), v in Hld.items():
+        if mu in rowpos:
+            ri.append(rowpos[mu]); cj.append(nu); vv.append(float(v))
+    Hl = sp.csr_matrix((vv, (ri, cj)), shape=(len(rows), plan.m))
+    nHg = sp.linalg.norm(Hl - Hg[rows]) / sp.linalg.norm(Hl)
+    nHo = sp.linalg.norm(Hl - ref.H[rows]) / sp.linalg.norm(Hl)
+    rl = np.array([float(rld[mu]) for mu in rows])
+    print(f"  normwise vs long double, GPU / oracle: H {nHg:.1e} / {nHo:.1e}", flush=True)
+    assert nHg <= accuracy_bound(nHo)
+    assert norm_rel(rl, rg[rows]) <= accuracy_bound(norm_rel(rl, ref.r[rows]))
+    assert norm_rel(ul, u) <= accuracy_bound(norm_rel(ul, uref))
+
+
+def test_c2_rt1_32cubed_sampled():
+    _sampled_parity(synth.config_c2())
+
+
+def test_c3_rt2_48cubed_jittered_sampled():
+    _sampled_parity(synth.config_c3(), nface=12, nel=12)
