@@ -80,6 +80,8 @@ typedef struct hyb_mesh {
 typedef struct hyb_opts {
   int precision;          /* HYB_FP64 */
   void* stream;           /* hipStream_t for every device call; NULL = null stream */
+  int kernel_variant;     /* 0: automatic (order- and geometry-specific kernels
+                             where they apply), 1: the generic kernels only */
 } hyb_opts;
 
 /* Sizes of the caller-owned device buffers, filled by hyb_plan_create. */
@@ -95,8 +97,9 @@ typedef struct hyb_sizes {
   int64_t nnz;            /* nonzeros of H */
   int64_t factor_len;     /* doubles per element in the factor buffer */
   int64_t bytes_maps;     /* device map buffer (topology, geometry, tables) */
-  int64_t bytes_factor;   /* ne * factor_len * 8 */
-  int64_t bytes_y;        /* ne * n_local * 8 (cached L^{-1} f_hat) */
+  int64_t bytes_factor;   /* factor buffer bytes (>= ne * factor_len * 8; the
+                             element-interleaved layouts round ne up to 64) */
+  int64_t bytes_y;        /* cached L^{-1} f_hat buffer bytes (>= ne * n_local * 8) */
   int64_t bytes_work;     /* PCG work vectors and reductions */
 } hyb_sizes;
 

@@ -36,7 +36,7 @@ def _dptr(t):
 class Plan:
     """One hybridization problem: mesh + order, its topology and device buffers."""
 
-    def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None):
+    def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None, generic: bool = False):
         lib = load_library()
         self._lib = lib
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -46,7 +46,7 @@ class Plan:
                             self.xyz.ctypes.data_as(ctypes.c_void_p),
                             self.e2v.ctypes.data_as(ctypes.c_void_p))
         self._stream_obj = stream
-        opts = _abi.HybOpts(0, ctypes.c_void_p(self._stream_handle()))
+        opts = _abi.HybOpts(0, ctypes.c_void_p(self._stream_handle()), 1 if generic else 0)
         self._plan = ctypes.c_void_p()
         sz = _abi.HybSizes()
         rc = lib.hyb_plan_create(ctypes.byref(mesh), self.k, ctypes.byref(opts), ctypes.byref(self._plan),
@@ -177,5 +177,6 @@ class Plan:
     def r(self):
         return self.bufs["r"][: self.m]
 
-    def y(self):
-        return self.bufs["y"][: self.ne * self.n].view(self.ne, self.n)
+    def y_raw(self):
+        """The cached L^{-1} f_hat buffer in the library's internal layout."""
+        return self.bufs["y"]

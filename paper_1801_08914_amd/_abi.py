@@ -37,7 +37,7 @@ class HybMesh(ctypes.Structure):
 
 
 class HybOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p)]
+    _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("kernel_variant", ctypes.c_int)]
 
 
 class HybSizes(ctypes.Structure):

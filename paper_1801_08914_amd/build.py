@@ -18,6 +18,8 @@ FLAGS = [
     # packed FP32 instructions are disabled for every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # the RT_1 setup kernel fully unrolls its 24-step factorization loops
+    "-mllvm", "-pragma-unroll-threshold=200000",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

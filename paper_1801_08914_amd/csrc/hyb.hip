@@ -10,6 +10,7 @@
 #include "../../include/hyb.h"
 #include "pcg.hpp"
 #include "plan.hpp"
+#include "k1_fast.hpp"
 #include "setup_generic.hpp"
 
 struct hyb_plan {
@@ -38,6 +39,7 @@ hyb::DeviceMaps device_maps(const hyb::Plan& P) {
   m.tab_w = reinterpret_cast<const double*>(base + L.tab_w);
   m.tab_ref = reinterpret_cast<const double*>(base + L.tab_ref);
   m.gauss_x = reinterpret_cast<const double*>(base + L.tab_x);
+  m.face_selfslot = reinterpret_cast<const int32_t*>(base + L.face_selfslot);
   return m;
 }
 
@@ -113,8 +115,32 @@ void mark(hyb::Plan& P, std::vector<void*>& list) {
   if (!P.timing) return;
   hipEvent_t e = take_event(P);
   if (!e) return;
-  hipEventRecord(e, stream_of(P));
+  (void)hipEventRecord(e, stream_of(P));
   list.push_back(e);
+}
+
+int zero_diag(const hyb::Plan& P, hipStream_t s) {
+  const int64_t tot = P.nfaces * P.ord.K2 * P.ord.K2;
+  if (tot == 0) return HYB_OK;
+  int64_t blocks = (tot + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  const hyb::DeviceMaps m = device_maps(P);
+  hipLaunchKernelGGL(hyb::k_zero_diag_blocks, dim3(unsigned(blocks)), dim3(256), 0, s, P.nfaces, P.ord.K2,
+                     m.face_rowbase, m.face_nslots, m.face_selfslot, P.buf.val);
+  HYB_HIP(hipGetLastError());
+  return HYB_OK;
+}
+
+hyb::k1::SimtArgs simt_args(const hyb::Plan& P) {
+  hyb::k1::SimtArgs a{};
+  a.mp = device_maps(P);
+  a.ne = P.ne;
+  a.alpha = P.alpha_d;
+  a.beta = P.beta_d;
+  a.factor = P.buf.factor;
+  a.y = P.buf.y;
+  a.r = P.buf.r;
+  return a;
 }
 
 int64_t work_bytes(int64_t m, int nblk) { return 8 * (5 * m + 2 * int64_t(nblk)) + 256; }
@@ -156,6 +182,8 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   }
   if (opt) p->P.opts = *opt;
   hyb::Plan& P = p->P;
+  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0;
+  P.ne_pad = (P.ne + 63) / 64 * 64;
   int64_t nblk = (P.m + hyb::kPcgThreads * 4 - 1) / (hyb::kPcgThreads * 4);
   if (nblk < 1) nblk = 1;
   if (nblk > 2048) nblk = 2048;
@@ -172,8 +200,8 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
     sizes->nnz = P.nnz;
     sizes->factor_len = P.factor_len;
     sizes->bytes_maps = int64_t(P.lay.total);
-    sizes->bytes_factor = 8 * P.ne * P.factor_len;
-    sizes->bytes_y = 8 * P.ne * P.ord.n;
+    sizes->bytes_factor = 8 * (P.fast_k1 ? P.ne_pad : P.ne) * P.factor_len;
+    sizes->bytes_y = 8 * (P.fast_k1 ? P.ne_pad : P.ne) * P.ord.n;
     sizes->bytes_work = work_bytes(P.m, P.work_blocks);
   }
   *out = p;
@@ -220,6 +248,7 @@ int hyb_bind(hyb_plan_t* plan, const hyb_buffers* buf) {
   put(L.tab_w, P.tab_w.data(), 8 * P.tab_w.size());
   put(L.tab_ref, P.tab_ref.data(), 8 * P.tab_ref.size());
   put(L.tab_x, P.tab_x.data(), 8 * P.tab_x.size());
+  put(L.face_selfslot, P.face_selfslot.data(), 4 * P.face_selfslot.size());
   HYB_HIP(hipMemcpyAsync(buf->maps, host.data(), host.size(), hipMemcpyHostToDevice, s));
   if (P.m > 0) {
     HYB_HIP(hipMemcpyAsync(buf->row_ptr, P.row_ptr.data(), 8 * P.row_ptr.size(), hipMemcpyHostToDevice, s));
@@ -238,7 +267,7 @@ int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta, const d
   hyb::Plan& P = plan->P;
   if (!P.bound) return HYB_E_STATE;
   hipStream_t s = stream_of(P);
-  int rc = fill(s, P.buf.val, P.nnz, 0.0);
+  int rc = zero_diag(P, s);
   if (rc) return rc;
   if (f && (rc = fill(s, P.buf.r, P.m, 0.0))) return rc;
   hyb::SetupArgs a{};
@@ -255,7 +284,14 @@ int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta, const d
   a.status = P.buf.status;
   a.mode = hyb::MODE_MATRIX | (f ? hyb::MODE_RHS : 0);
   mark(P, P.ev_setup);
-  rc = dispatch_setup(P.ord.k, a, s);
+  if (P.fast_k1) {
+    if (P.ne > 0) {
+      hipLaunchKernelGGL(hyb::k1::k_setup_k1, dim3(unsigned((P.ne + 7) / 8)), dim3(64), 0, s, a);
+      HYB_HIP(hipGetLastError());
+    }
+  } else {
+    rc = dispatch_setup(P.ord.k, a, s);
+  }
   mark(P, P.ev_setup);
   if (rc) return rc;
   P.have_setup = true;
@@ -286,7 +322,17 @@ int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g) {
   a.r = P.buf.r;
   a.status = P.buf.status;
   a.mode = hyb::MODE_RHS;
-  rc = dispatch_setup(P.ord.k, a, s);
+  if (P.fast_k1) {
+    hyb::k1::SimtArgs b = simt_args(P);
+    b.f = f;
+    b.g = g;
+    if (P.ne > 0) {
+      hipLaunchKernelGGL(hyb::k1::k_rhs_k1, dim3(unsigned((P.ne + 63) / 64)), dim3(64), 0, s, b);
+      HYB_HIP(hipGetLastError());
+    }
+  } else {
+    rc = dispatch_setup(P.ord.k, a, s);
+  }
   if (rc) return rc;
   P.have_rhs = true;
   return HYB_OK;
@@ -364,7 +410,18 @@ int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u) {
   a.lambda = lambda;
   a.u = u;
   mark(P, P.ev_recover);
-  int rc = dispatch_recover(P.ord.k, a, stream_of(P));
+  int rc = HYB_OK;
+  if (P.fast_k1) {
+    hyb::k1::SimtArgs b = simt_args(P);
+    b.lambda = lambda;
+    b.u = u;
+    if (P.ne > 0) {
+      hipLaunchKernelGGL(hyb::k1::k_recover_k1, dim3(unsigned((P.ne + 63) / 64)), dim3(64), 0, stream_of(P), b);
+      HYB_HIP(hipGetLastError());
+    }
+  } else {
+    rc = dispatch_recover(P.ord.k, a, stream_of(P));
+  }
   mark(P, P.ev_recover);
   return rc;
 }
@@ -421,7 +478,7 @@ void hyb_destroy(hyb_plan_t* plan) {
   if (!plan) return;
   hyb::Plan& P = plan->P;
   for (auto* L : {&P.ev_setup, &P.ev_recover, &P.ev_pool})
-    for (void* e : *L) hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
+    for (void* e : *L) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
   delete plan;
 }
 

@@ -57,6 +57,7 @@ struct DeviceMaps {
   const double* tab_w;         // Q
   const double* tab_ref;       // 2 n^2 + n
   const double* gauss_x;       // q1 points on [0,1]
+  const int32_t* face_selfslot;
 };
 
 // Sticky device error: the first (code, element) pair wins.

@@ -162,6 +162,18 @@ __global__ void k_fill(double* x, int64_t n, double v) {
     x[i] = v;
 }
 
+// Zero the same-face (diagonal) blocks of H, the only entries that receive
+// two element terms (added atomically by the setup kernels).
+__global__ void k_zero_diag_blocks(int64_t nfaces, int K2, const int64_t* rowbase, const int32_t* nslots,
+                                   const int32_t* selfslot, double* val) {
+  const int64_t tot = nfaces * K2 * K2;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < tot; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t F = i / (K2 * K2);
+    const int rem = int(i - F * K2 * K2), j = rem / K2, jj = rem % K2;
+    val[rowbase[F] + int64_t(j) * nslots[F] * K2 + selfslot[F] * K2 + jj] = 0.0;
+  }
+}
+
 __global__ void k_fill_i32(int32_t* x, int64_t n, int32_t v) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     x[i] = v;

@@ -149,6 +149,27 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
     }
   }
 
+  // Parallelepipeds: x_v = x_0 + a E_0 + b E_1 + c E_2 at every vertex, up
+  // to rounding of the coordinates themselves.
+  P.all_affine = true;
+  for (int64_t e = 0; e < ne && P.all_affine; ++e) {
+    const int32_t* ev = &P.e2v[8 * e];
+    double E[3][3], scale = 0.0;
+    for (int d = 0; d < 3; ++d)
+      for (int r = 0; r < 3; ++r) {
+        E[d][r] = P.xyz[3 * ev[1 << d] + r] - P.xyz[3 * ev[0] + r];
+        scale = std::max(scale, std::fabs(P.xyz[3 * ev[1 << d] + r]) + std::fabs(P.xyz[3 * ev[0] + r]));
+      }
+    for (int v = 3; v < 8 && P.all_affine; ++v) {
+      for (int r = 0; r < 3; ++r) {
+        double pred = P.xyz[3 * ev[0] + r];
+        for (int d = 0; d < 3; ++d)
+          if ((v >> d) & 1) pred += E[d][r];
+        if (std::fabs(P.xyz[3 * ev[v] + r] - pred) > 1e-13 * (scale + 1e-300)) P.all_affine = false;
+      }
+    }
+  }
+
   // Faces: sort (sorted vertex quadruple, element, local face) records.
   struct Rec { std::array<int32_t, 4> key; int32_t e; int32_t f; };
   std::vector<Rec> recs(size_t(6 * ne));
@@ -260,6 +281,12 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
     }
   }
   P.row_ptr[size_t(P.m)] = P.nnz;
+  P.face_selfslot.assign(size_t(nf), 0);
+  for (int64_t F = 0; F < nf; ++F) {
+    const auto& L = slots[size_t(F)];
+    int cnt = P.face_nslots[size_t(F)];
+    P.face_selfslot[size_t(F)] = int32_t(std::lower_bound(L.begin(), L.begin() + cnt, int32_t(F)) - L.begin());
+  }
   P.elem_slot.assign(size_t(36 * ne), 255);
   for (int64_t e = 0; e < ne; ++e)
     for (int a = 0; a < 6; ++a) {
@@ -343,6 +370,7 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
   L.tab_w = off;        off = align256(off + sizeof(double) * P.tab_w.size());
   L.tab_ref = off;      off = align256(off + sizeof(double) * P.tab_ref.size());
   L.tab_x = off;        off = align256(off + sizeof(double) * P.tab_x.size());
+  L.face_selfslot = off; off = align256(off + sizeof(int32_t) * size_t(nf));
   L.total = off;
   P.factor_len = int64_t(o.n) * (o.n + 1) / 2;
   return HYB_OK;

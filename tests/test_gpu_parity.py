@@ -33,9 +33,11 @@ def _mesh_problem(k, N, jitter, seed, rotate=False):
     return mesh, synth.lognormal(rng, ne), synth.lognormal(rng, ne, 0.5), synth.element_loads(rng, ne)
 
 
+# (k, N, jitter, rotated frames); unjittered RT_1 meshes take the affine
+# RT_1 kernels, the others the generic ones
 SMALL = [
     (0, 4, 0.0, False), (0, 5, 0.2, True),
-    (1, 3, 0.0, False), (1, 4, 0.2, True), (1, 5, 0.2, False),
+    (1, 3, 0.0, False), (1, 4, 0.0, True), (1, 4, 0.2, True), (1, 5, 0.2, False),
     (2, 2, 0.2, True), (2, 3, 0.2, False),
 ]
 
@@ -175,3 +177,38 @@ def test_not_spd_reported():
     plan.setup(a, b * 1e-3, f)
     rc, det = plan.status()
     assert rc == _abi.HYB_E_NOT_SPD and det == 13
+
+
+@pytest.mark.parametrize("rot", [False, True])
+def test_affine_rt1_fast_and_generic_kernels_agree_with_oracle(rot):
+    """The affine RT_1 kernels and the generic kernels on the same input:
+    both as accurate as the FP64 oracle (long-double reference), and the
+    rhs-only and recovery paths of both."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Plan
+    mesh, a, b, f = _mesh_problem(1, 5, 0.0, 77, rot)
+    f2 = np.random.default_rng(3).standard_normal(f.shape)
+    ref = ohyb.hybridize(1, mesh.xyz, mesh.e2v, a, b, f2)
+    lam = np.random.default_rng(4).standard_normal(ref.H.shape[0])
+    uref = ohyb.recover(ref, mesh.xyz, mesh.e2v, a, b, f2, lam)
+    Hld, rld, U = oext.hybridize_ld(1, mesh.xyz, mesh.e2v, a, b, f2, ref.topo, np.arange(mesh.ne), lam)
+    Hl, rl = ld_dense(Hld, rld, ref.H.shape[0])
+    ul = np.array([U[e].astype(float) for e in range(mesh.ne)])
+    for generic in (False, True):
+        plan = Plan(mesh.xyz, mesh.e2v, 1, generic=generic).bind()
+        plan.setup(a, b, f)
+        plan.rhs(f2)
+        u = plan.recover(torch.as_tensor(lam, device="cuda")).cpu().numpy()
+        rc, det = plan.status()
+        assert rc == 0, (rc, det)
+        rp, ci, val = [t.cpu().numpy() for t in plan.csr()]
+        import scipy.sparse as sp
+        Hg = sp.csr_matrix((val, ci, rp), shape=ref.H.shape).toarray()
+        rg = plan.r().cpu().numpy()
+        eH, eHo = norm_rel(Hl, Hg), norm_rel(Hl, ref.H.toarray())
+        er, ero = norm_rel(rl, rg), norm_rel(rl, ref.r)
+        eu, euo = norm_rel(ul, u), norm_rel(ul, uref)
+        print(f"generic={generic}: vs long double GPU/oracle H {eH:.1e}/{eHo:.1e} r {er:.1e}/{ero:.1e} "
+              f"u {eu:.1e}/{euo:.1e}", flush=True)
+        assert eH <= accuracy_bound(eHo) and er <= accuracy_bound(ero) and eu <= accuracy_bound(euo)
+        assert (sp.csr_matrix(Hg) - sp.csr_matrix(Hg).T).count_nonzero() == 0
