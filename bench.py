@@ -112,6 +112,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--skip-solve", action="store_true",
+                    help="recover from a seeded random lambda instead of the PCG solution (profiling runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -136,9 +140,19 @@ def main():
     plan.setup(alpha, beta, f)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lam, info = plan.solve(1e-12, 20000)
+    if args.skip_solve:
+        lam = torch.as_tensor(np.random.default_rng(0).standard_normal(plan.m), device=dev)
+        info = {"iters": 0, "rel_res": None}
+    else:
+        lam, info = plan.solve(1e-12, 20000)
     torch.cuda.synchronize()
     pcg_ms = (time.perf_counter() - t0) * 1e3
+    if args.copy_calib:
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     rc, det = plan.status()
     assert rc == 0, (rc, det)
 
