@@ -97,10 +97,10 @@ typedef struct hyb_sizes {
   int64_t nnz;            /* nonzeros of H */
   int64_t factor_len;     /* doubles per element in the factor buffer */
   int64_t bytes_maps;     /* device map buffer (topology, geometry, tables) */
-  int64_t bytes_factor;   /* factor buffer bytes (>= ne * factor_len * 8; the
-                             element-interleaved layouts round ne up to 64) */
+  int64_t bytes_factor;   /* factor buffer bytes (ne * factor_len * 8) */
   int64_t bytes_y;        /* cached L^{-1} f_hat buffer bytes (>= ne * n_local * 8) */
-  int64_t bytes_work;     /* PCG work vectors and reductions */
+  int64_t bytes_work;     /* PCG work vectors and reductions; setup and rhs
+                             also use it as scratch (contents not kept) */
 } hyb_sizes;
 
 /* Caller-allocated device buffers (e.g. torch tensors' data pointers). */

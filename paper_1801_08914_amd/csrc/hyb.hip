@@ -40,6 +40,7 @@ hyb::DeviceMaps device_maps(const hyb::Plan& P) {
   m.tab_ref = reinterpret_cast<const double*>(base + L.tab_ref);
   m.gauss_x = reinterpret_cast<const double*>(base + L.tab_x);
   m.face_selfslot = reinterpret_cast<const int32_t*>(base + L.face_selfslot);
+  m.face_owner = reinterpret_cast<const int32_t*>(base + L.face_owner);
   return m;
 }
 
@@ -140,10 +141,38 @@ hyb::k1::SimtArgs simt_args(const hyb::Plan& P) {
   a.factor = P.buf.factor;
   a.y = P.buf.y;
   a.r = P.buf.r;
+  a.side = P.buf.work;
+  a.nfaces = P.nfaces;
   return a;
 }
 
-int64_t work_bytes(int64_t m, int nblk) { return 8 * (5 * m + 2 * int64_t(nblk)) + 256; }
+// Add the neighbour terms of the same-face blocks of H and of r.
+int finalize_k1(const hyb::Plan& P, hipStream_t s, bool matrix, bool rhs) {
+  const int64_t tot = P.nfaces * ((matrix ? 16 : 0) + (rhs ? 4 : 0));
+  if (tot == 0) return HYB_OK;
+  const hyb::DeviceMaps m = device_maps(P);
+  hyb::k1::FinalArgs f{};
+  f.nfaces = P.nfaces;
+  f.rowbase = m.face_rowbase;
+  f.nslots = m.face_nslots;
+  f.selfslot = m.face_selfslot;
+  f.Hval = matrix ? P.buf.val : nullptr;
+  f.r = rhs ? P.buf.r : nullptr;
+  f.side = P.buf.work;
+  int64_t blocks = (tot + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(hyb::k1::k_finalize_k1, dim3(unsigned(blocks)), dim3(256), 0, s, f);
+  HYB_HIP(hipGetLastError());
+  return HYB_OK;
+}
+
+// PCG vectors and partial sums; the RT_1 setup also uses the buffer for the
+// neighbour terms of the same-face blocks of H and of r (20 per face).
+int64_t work_bytes(int64_t m, int nblk, int64_t nfaces) {
+  const int64_t pcg = 8 * (5 * m + 2 * int64_t(nblk)) + 256;
+  const int64_t side = 8 * 20 * nfaces;
+  return pcg > side ? pcg : side;
+}
 
 }  // namespace
 
@@ -183,7 +212,7 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   if (opt) p->P.opts = *opt;
   hyb::Plan& P = p->P;
   P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0;
-  P.ne_pad = (P.ne + 63) / 64 * 64;
+  if (P.fast_k1) P.factor_len = hyb::k1::REC;
   int64_t nblk = (P.m + hyb::kPcgThreads * 4 - 1) / (hyb::kPcgThreads * 4);
   if (nblk < 1) nblk = 1;
   if (nblk > 2048) nblk = 2048;
@@ -200,9 +229,9 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
     sizes->nnz = P.nnz;
     sizes->factor_len = P.factor_len;
     sizes->bytes_maps = int64_t(P.lay.total);
-    sizes->bytes_factor = 8 * (P.fast_k1 ? P.ne_pad : P.ne) * P.factor_len;
-    sizes->bytes_y = 8 * (P.fast_k1 ? P.ne_pad : P.ne) * P.ord.n;
-    sizes->bytes_work = work_bytes(P.m, P.work_blocks);
+    sizes->bytes_factor = 8 * P.ne * P.factor_len;
+    sizes->bytes_y = 8 * P.ne * P.ord.n;
+    sizes->bytes_work = work_bytes(P.m, P.work_blocks, P.nfaces);
   }
   *out = p;
   return HYB_OK;
@@ -249,6 +278,11 @@ int hyb_bind(hyb_plan_t* plan, const hyb_buffers* buf) {
   put(L.tab_ref, P.tab_ref.data(), 8 * P.tab_ref.size());
   put(L.tab_x, P.tab_x.data(), 8 * P.tab_x.size());
   put(L.face_selfslot, P.face_selfslot.data(), 4 * P.face_selfslot.size());
+  {
+    std::vector<int32_t> owner_elem(size_t(P.nfaces));
+    for (int64_t F = 0; F < P.nfaces; ++F) owner_elem[size_t(F)] = P.face_owner[size_t(2 * F)];
+    put(L.face_owner, owner_elem.data(), 4 * owner_elem.size());
+  }
   HYB_HIP(hipMemcpyAsync(buf->maps, host.data(), host.size(), hipMemcpyHostToDevice, s));
   if (P.m > 0) {
     HYB_HIP(hipMemcpyAsync(buf->row_ptr, P.row_ptr.data(), 8 * P.row_ptr.size(), hipMemcpyHostToDevice, s));
@@ -267,9 +301,6 @@ int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta, const d
   hyb::Plan& P = plan->P;
   if (!P.bound) return HYB_E_STATE;
   hipStream_t s = stream_of(P);
-  int rc = zero_diag(P, s);
-  if (rc) return rc;
-  if (f && (rc = fill(s, P.buf.r, P.m, 0.0))) return rc;
   hyb::SetupArgs a{};
   a.mp = device_maps(P);
   a.ne = P.ne;
@@ -284,13 +315,20 @@ int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta, const d
   a.status = P.buf.status;
   a.mode = hyb::MODE_MATRIX | (f ? hyb::MODE_RHS : 0);
   mark(P, P.ev_setup);
+  int rc = HYB_OK;
   if (P.fast_k1) {
     if (P.ne > 0) {
-      hipLaunchKernelGGL(hyb::k1::k_setup_k1, dim3(unsigned((P.ne + 7) / 8)), dim3(64), 0, s, a);
+      constexpr int per_block = hyb::k1::SETUP_EPW * hyb::k1::SETUP_WAVES;
+      const unsigned blocks = unsigned((P.ne + per_block - 1) / per_block);
+      hipLaunchKernelGGL(hyb::k1::k_setup_k1, dim3(blocks), dim3(64 * hyb::k1::SETUP_WAVES), 0, s, a, P.buf.work,
+                         P.nfaces);
       HYB_HIP(hipGetLastError());
+      rc = finalize_k1(P, s, true, f != nullptr);
     }
   } else {
-    rc = dispatch_setup(P.ord.k, a, s);
+    rc = zero_diag(P, s);
+    if (!rc && f) rc = fill(s, P.buf.r, P.m, 0.0);
+    if (!rc) rc = dispatch_setup(P.ord.k, a, s);
   }
   mark(P, P.ev_setup);
   if (rc) return rc;
@@ -306,31 +344,34 @@ int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g) {
   hyb::Plan& P = plan->P;
   if (!P.have_setup) return HYB_E_STATE;
   hipStream_t s = stream_of(P);
-  int rc = fill(s, P.buf.r, P.m, 0.0);
-  if (rc) return rc;
-  hyb::SetupArgs a{};
-  a.mp = device_maps(P);
-  a.ne = P.ne;
-  // the boundary correction -M_re g_e reassembles M_T from setup's coefficients
-  a.alpha = P.alpha_d;
-  a.beta = P.beta_d;
-  a.f = f;
-  a.g = g;
-  a.factor = P.buf.factor;
-  a.y = P.buf.y;
-  a.Hval = P.buf.val;
-  a.r = P.buf.r;
-  a.status = P.buf.status;
-  a.mode = hyb::MODE_RHS;
+  int rc = HYB_OK;
   if (P.fast_k1) {
     hyb::k1::SimtArgs b = simt_args(P);
     b.f = f;
     b.g = g;
     if (P.ne > 0) {
-      hipLaunchKernelGGL(hyb::k1::k_rhs_k1, dim3(unsigned((P.ne + 63) / 64)), dim3(64), 0, s, b);
+      const unsigned blocks = unsigned((P.ne + hyb::k1::SOLVE_EPW - 1) / hyb::k1::SOLVE_EPW);
+      hipLaunchKernelGGL(hyb::k1::k_rhs_k1, dim3(blocks), dim3(64), 0, s, b);
       HYB_HIP(hipGetLastError());
+      rc = finalize_k1(P, s, false, true);
     }
   } else {
+    rc = fill(s, P.buf.r, P.m, 0.0);
+    if (rc) return rc;
+    hyb::SetupArgs a{};
+    a.mp = device_maps(P);
+    a.ne = P.ne;
+    // the boundary correction -M_re g_e reassembles M_T from setup's coefficients
+    a.alpha = P.alpha_d;
+    a.beta = P.beta_d;
+    a.f = f;
+    a.g = g;
+    a.factor = P.buf.factor;
+    a.y = P.buf.y;
+    a.Hval = P.buf.val;
+    a.r = P.buf.r;
+    a.status = P.buf.status;
+    a.mode = hyb::MODE_RHS;
     rc = dispatch_setup(P.ord.k, a, s);
   }
   if (rc) return rc;
@@ -416,7 +457,7 @@ int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u) {
     b.lambda = lambda;
     b.u = u;
     if (P.ne > 0) {
-      hipLaunchKernelGGL(hyb::k1::k_recover_k1, dim3(unsigned((P.ne + 63) / 64)), dim3(64), 0, stream_of(P), b);
+      hipLaunchKernelGGL(hyb::k1::k_recover_k1, dim3(unsigned((P.ne + hyb::k1::SOLVE_EPW - 1) / hyb::k1::SOLVE_EPW)), dim3(64), 0, stream_of(P), b);
       HYB_HIP(hipGetLastError());
     }
   } else {

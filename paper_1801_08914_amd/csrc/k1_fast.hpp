@@ -1,25 +1,47 @@
-// RT_1 kernels for affine hexahedra (n = 36 broken dofs, 12 interior, 24 on
-// faces).  Setup: a team of 8 lanes per element, 8 elements per wave, every
-// matrix row set held in registers, one LDS barrier per eliminated column.
-// Right-hand side and recovery: one element per lane.
+// RT_1 kernels for affine hexahedra (n = 36 broken dofs: 12 interior, 24 on
+// faces).
 //
-// Per element the setup computes, in the i-first order of Sec. 5:
-//   M_T (affine: alpha G[d_i][d_j] T_ij + beta/detJ Dv_ij with the reference
-//        integrals T_ij = int s_i s_j and Dv_ij = int div_i div_j, exact for
-//        a constant Jacobian),
-//   the upper Cholesky rows of the interior block, U_ii, and W = U_ii^{-T} A_ib
-//        (interior elimination, column-cyclic over the team),
-//   S = A_bb - W^T W, its Cholesky factor L and L^{-1} (in place),
-//   H_T = D L^{-T} L^{-1} D in 4x4 face blocks, scattered into CSR H,
-//   y = (U_ii^{-T} f_i, L^{-1}(f_b - W^T y_i)) and r_T = D L^{-T} y_b.
+// Setup: one element per 16-lane row of the wave (4 elements per wave; lanes
+// 12..15 of each row shadow lane 0 and store nothing).  Lane t holds three
+// rows of the element matrix in registers: interior row t and face rows t and
+// 12 + t, each with all 36 columns and the right-hand side.
+//  1. Assembly (affine: M = alpha G[d_i][d_j] T_ij + beta/detJ Dv_ij with the
+//     reference integrals T_ij = int s_i s_j, Dv_ij = int div_i div_j, exact
+//     for a constant Jacobian); boundary-face rows and columns become
+//     identity, their values move to the right-hand side.
+//  2. Exact power-of-two diagonal scaling, so every pivot lies in (0, 2).
+//  3. Gauss-Jordan sweep of the 12 interior pivots: the interior block
+//     becomes -A_ii^{-1}, the interior-face block E = A_ii^{-1} A_ib, the face
+//     block S = A_bb - A_bi A_ii^{-1} A_ib and the right-hand side
+//     (A_ii^{-1} f_i, f_b - E^T f_i): the static condensation of the interior
+//     dofs (Sec. 5) in sweep form.
+//  4. Gauss-Jordan sweep of the 24 face pivots over the face rows:
+//     S -> -S^{-1}, t -> S^{-1} t.  H_T = D S^{-1} D and r_T = D S^{-1} t
+//     (Theorem 2.1 with the interior dofs condensed).
+// The pivot row k of a step lives in one lane; its entries reach the other
+// lanes of the row by DPP row broadcast, fused into no memory traffic.  Row r
+// is updated as r_j -= (r_k / d) p_j.  The pivot lane uses the multiplier
+// 1 - 1/d and every lane substitutes d - 1 for the pivot entry p_k, which
+// leaves p / d in the pivot row and r_k / d in the pivot column without
+// indexing a register by k; the swept diagonal entry then holds 2 - 1/d
+// instead of -1/d (corrected on output).  With pivots below 2 the
+// cancellation in these updates costs at most a few ulps.
 //
-// Factor layout in HBM ("64-interleaved"): entry x of element e at
-//   ((e / 64) * 666 + x) * 64 + e % 64, with x in
-//   [0, 78)    U_ii, upper triangle packed by rows,
-//   [78, 366)  W, 12 x 24 row-major,
-//   [366, 666) L^{-1}, lower triangle packed by rows.
-// y uses the same interleaving with 36 entries per element (local order).
+// Per-element record in HBM (672 doubles, 128-byte aligned):
+//   [0, 78)    A_ii^{-1}, lower triangle packed by rows,
+//   [78, 366)  E, 12 x 24 row-major,
+//   [366, 666) S^{-1}, lower triangle packed by rows.
+// y (36 per element): (A_ii^{-1} f_i, S^{-1} t).
+// Recovery: u_b = y_b - S^{-1} D lambda, u_i = y_i - E u_b.
+//
+// The same-face blocks of H and the entries of r receive one term from each
+// of the face's two elements: the owner stores its term in place, the
+// neighbour into a side buffer, and k_finalize_k1 adds the two, so H and r
+// are bitwise reproducible and no atomics are used.
 #pragma once
+
+#include <type_traits>
+#include <utility>
 
 #include "kernels_common.hpp"
 #include "setup_generic.hpp"
@@ -27,408 +49,466 @@
 namespace hyb {
 namespace k1 {
 
-constexpr int N = 36, NI = 12, NB = 24, FLEN = 666, OFF_W = 78, OFF_LI = 366;
+constexpr int N = 36, NB = 24, OFF_E = 78, OFF_SI = 366, REC = 672;
+constexpr int TEAM = 12;       // rows per element handled by 12 lanes
+constexpr int SETUP_EPW = 4;   // setup: one element per 16-lane DPP row
+constexpr int SOLVE_EPW = 5;   // right-hand side and recovery: 5 teams of 12
 
-__device__ __forceinline__ int64_t fidx(int64_t e, int x) { return ((e >> 6) * FLEN + x) * 64 + (e & 63); }
-__device__ __forceinline__ int64_t yidx(int64_t e, int i) { return ((e >> 6) * N + i) * 64 + (e & 63); }
-// start of row c of the packed upper interior factor
-__device__ __host__ constexpr int uoff(int c) { return c * 12 - c * (c - 1) / 2; }
-// component of local dof i (interior: i / 4, face dof 12 + a: a / 8)
+// component (axis) of local dof i: interior i / 4, face dof 12 + a: a / 8
 __device__ __host__ constexpr int comp(int i) { return i < 12 ? i / 4 : (i - 12) / 8; }
+// packed lower index of a symmetric pair
+__device__ __forceinline__ int spk(int a, int b) { return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a; }
 
-// Affine geometry of one element from vertices 0, 1, 2 and 4: J columns are
-// the edge vectors.  Returns det J and fills G = J^T J / det J (symmetric).
-__device__ __forceinline__ double affine_geometry(const DeviceMaps& mp, int64_t e, double J[3][3], double G[3][3]) {
-  const int32_t* ev = mp.e2v + e * 8;
-  const int v0 = ev[0];
-  const int vs[3] = {ev[1], ev[2], ev[4]};
-  double x0[3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) x0[r] = mp.xyz[3 * int64_t(v0) + r];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) J[r][c] = mp.xyz[3 * int64_t(vs[c]) + r] - x0[r];
-  const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-  const double id = 1.0 / det;
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) G[d][c] = (J[0][d] * J[0][c] + J[1][d] * J[1][c] + J[2][d] * J[2][c]) * id;
-  return det;
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of elements so that face neighbours share an L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned q = nb / 8, rem = nb % 8, x = b % 8, i = b / 8;
+  return int64_t(x) * q + (x < rem ? x : rem) + i;
 }
 
-// Static assignment of the 21 lower 4x4 face blocks (fa >= fb) of H_T to the
-// 8 lanes of a team, balanced by the length of their row loops (24 - 4 fa).
-// Entry = fa * 8 + fb, terminated by 255.
-__constant__ uint8_t c_blocks[8][4] = {
-    {0 * 8 + 0, 5 * 8 + 5, 3 * 8 + 3, 255},
-    {1 * 8 + 0, 5 * 8 + 4, 4 * 8 + 4, 255},
-    {1 * 8 + 1, 5 * 8 + 3, 4 * 8 + 3, 255},
-    {2 * 8 + 0, 5 * 8 + 2, 4 * 8 + 2, 255},
-    {2 * 8 + 1, 5 * 8 + 1, 4 * 8 + 1, 255},
-    {2 * 8 + 2, 5 * 8 + 0, 4 * 8 + 0, 255},
-    {3 * 8 + 0, 3 * 8 + 2, 255, 255},
-    {3 * 8 + 1, 255, 255, 255},
+// Owner-frame index of face dof i (0..3) of a face with frame code pi.
+__device__ __forceinline__ int own_idx(int pi, int i) {
+  int p0 = i & 1, p1 = i >> 1;
+  frame_map(pi, 1, p0, p1);
+  return p0 + 2 * p1;
+}
+
+// Lane L of each 16-lane row, broadcast to the whole row (DPP row_newbcast).
+template <int L>
+__device__ __forceinline__ double row_bcast(double x) {
+  return __builtin_amdgcn_update_dpp(x, x, 0x150 + L, 0xF, 0xF, true);
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Per-element affine data shared by the three kernels.
+struct Elem {
+  double g00, g01, g02, g11, g12, g22;   // G = J^T J / det J
+  double jtf[3];                         // J^T f
+  double al, bd;                         // alpha, beta / det J
+  double det;
+  unsigned ess;                          // bit f: face f is on the boundary
+
+  __device__ __forceinline__ void load(const DeviceMaps& mp, int64_t e, const double* alpha, const double* beta,
+                                       const double* f, bool need_matrix) {
+    const int32_t* ev = mp.e2v + e * 8;
+    const int v0 = ev[0];
+    const int vs[3] = {ev[1], ev[2], ev[4]};
+    double J[3][3], x0[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) x0[r] = mp.xyz[3 * int64_t(v0) + r];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) J[r][c] = mp.xyz[3 * int64_t(vs[c]) + r] - x0[r];
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    const double id = 1.0 / det;
+    auto gg = [&](int d, int c) { return (J[0][d] * J[0][c] + J[1][d] * J[1][c] + J[2][d] * J[2][c]) * id; };
+    g00 = gg(0, 0); g01 = gg(0, 1); g02 = gg(0, 2); g11 = gg(1, 1); g12 = gg(1, 2); g22 = gg(2, 2);
+    if (f) {
+      const double f0 = f[e * 3], f1 = f[e * 3 + 1], f2 = f[e * 3 + 2];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) jtf[d] = J[0][d] * f0 + J[1][d] * f1 + J[2][d] * f2;
+    } else {
+      jtf[0] = jtf[1] = jtf[2] = 0.0;
+    }
+    al = need_matrix ? alpha[e] : 0.0;
+    bd = need_matrix ? beta[e] / det : 0.0;
+    ess = 0;
+#pragma unroll
+    for (int fc = 0; fc < 6; ++fc)
+      if (mp.elem_face[e * 6 + fc] < 0) ess |= 1u << fc;
+  }
+  __device__ __forceinline__ bool ess_dof(int i) const { return i >= 12 && ((ess >> ((i - 12) >> 2)) & 1u); }
+  // alpha G[c][0..2] for a lane-varying component c, blended with exact 0/1
+  // weights (a select chain over an array would become scratch memory)
+  __device__ __forceinline__ void arow(int c, double (&ag)[3]) const {
+    const double w0 = c == 0 ? 1.0 : 0.0, w1 = c == 1 ? 1.0 : 0.0, w2 = c == 2 ? 1.0 : 0.0;
+    ag[0] = al * (w0 * g00 + w1 * g01 + w2 * g02);
+    ag[1] = al * (w0 * g01 + w1 * g11 + w2 * g12);
+    ag[2] = al * (w0 * g02 + w1 * g12 + w2 * g22);
+  }
+  __device__ __forceinline__ double jsel(int c) const {
+    const double w0 = c == 0 ? 1.0 : 0.0, w1 = c == 1 ? 1.0 : 0.0, w2 = c == 2 ? 1.0 : 0.0;
+    return w0 * jtf[0] + w1 * jtf[1] + w2 * jtf[2];
+  }
 };
 
-// per team: [0, 96) row/column broadcast buffers, [96, 400) W + y_i, then
-// L^{-1} (packed rows + pad), [400, 424) y_b
-constexpr int LDS_PER_TEAM = 424;
+// Unscaled right-hand side entry of local dof i: the load term (J^T f)_d s_i
+// minus the boundary correction sum_j M_ij g_j over boundary dofs j, or g_i
+// on a boundary dof.  The setup kernel accumulates the same terms in the same
+// order, so both paths agree bitwise.
+__device__ __forceinline__ double rhs_entry(const Elem& el, const DeviceMaps& mp, int i, const double* gb) {
+  const double2* TD = reinterpret_cast<const double2*>(mp.tab_ref);
+  const double* sr = mp.tab_ref + 2 * N * N;
+  if (el.ess_dof(i)) return gb ? gb[i - 12] : 0.0;
+  double corr = 0.0;
+  if (gb && el.ess) {
+    double ag[3];
+    el.arow(comp(i), ag);
+#pragma unroll
+    for (int j = 12; j < 36; ++j) {
+      const double2 td = TD[j * N + i];
+      const double v = fma(ag[comp(j)], td.x, el.bd * td.y);
+      corr = fma(el.ess_dof(j) ? v : 0.0, gb[j - 12], corr);
+    }
+  }
+  return el.jsel(comp(i)) * sr[i] - corr;
+}
 
-__global__ __launch_bounds__(64) void k_setup_k1(SetupArgs a) {
-  __shared__ double lds[8][LDS_PER_TEAM];
-  const int lane = threadIdx.x, tau = lane >> 3, t = lane & 7;
-  const int64_t e = int64_t(blockIdx.x) * 8 + tau;
-  const bool live = e < a.ne;
-  const int64_t es = live ? e : 0;
-  double* bcast = lds[tau];             // 2 x 48
-  double* wbuf = bcast + 96;            // W (12 x 24) then y_i (12)
-  double* lin = wbuf;                   // L^{-1} packed rows, after W is consumed
-  double* ybuf = bcast + 400;           // y_b (24)
+// Power-of-two scale 2^-floor(E/2) for a diagonal entry d = m 2^E, so that
+// the scaled diagonal lies in [0.5, 2).
+__device__ __forceinline__ double pow2_scale(double d) {
+  if (!(d > 0.0) || !isfinite(d)) return 1.0;
+  int E;
+  (void)frexp(d, &E);
+  return ldexp(1.0, -(E >> 1));
+}
+
+// LDS strides put the element slots of a wave in different banks: 370 and 36
+// doubles are 4 and 8 dwords apart modulo 32 banks.
+constexpr int SSTRIDE = 370;   // staging of up to 366 outputs per element
+
+// Per-element face data for the H scatter.
+struct HMeta {
+  int64_t rb[6];     // first CSR entry of the face's row block
+  int32_t fid[6];    // face index, -1 on the boundary
+  int32_t pi[6];     // frame code
+  int32_t ns[6];     // column blocks per row of the face
+  int32_t own[6];    // this element owns the face
+  int32_t slot[36];  // slot of face fb in the rows of face fa
+};
+
+constexpr int SETUP_WAVES = 4;   // waves per setup workgroup (16 elements)
+
+// Per-wave LDS of the setup kernel.
+struct SetupWaveLds {
+  double stage[SETUP_EPW][SSTRIDE];   // outputs on their way to HBM
+  HMeta meta[SETUP_EPW];
+};
+struct alignas(16) SetupLds {
+  double2 td[N * N];   // reference integrals {T_ij, Dv_ij}, shared by the workgroup
+  double sr[N];
+  SetupWaveLds w[SETUP_WAVES];
+};
+
+// Order the LDS accesses of the lanes of one wave (a wave executes its LDS
+// instructions in order, so no wait is needed).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Copy the first len doubles of each element slot's staging area to the
+// records of elements e0 .. e0 + EPW - 1 at offset off, as coalesced 16-byte
+// stores.
+template <int EPW>
+__device__ __forceinline__ void write_records(double* factor, const double (*stage)[SSTRIDE], int64_t e0, int64_t ne,
+                                              int off, int len) {
+  const int h2 = len / 2;
+  for (int c = threadIdx.x & 63; c < EPW * h2; c += 64) {
+    const int tm = c / h2, p = c - tm * h2;
+    if (e0 + tm < ne)
+      *reinterpret_cast<double2*>(factor + (e0 + tm) * REC + off + 2 * p) =
+          *reinterpret_cast<const double2*>(&stage[tm][2 * p]);
+  }
+}
+
+// One Gauss-Jordan step on interior pivot C (held by lane C).
+template <int C>
+__device__ __forceinline__ void interior_step(double (&R)[37], double (&A)[37], double (&B)[37], int t, bool live,
+                                              int32_t* status, int64_t e) {
+  double d = row_bcast<C>(R[C]);
+  if (!(d > 0.0)) {
+    if (live && t == C) report_error(status, HYB_E_NOT_SPD, e);
+    d = 1.0;
+  }
+  const double inv = 1.0 / d;
+  const double mi = t == C ? 1.0 - inv : R[C] * inv;
+  const double ma = A[C] * inv, mb = B[C] * inv;
+  const double pc = d - 1.0;
+#pragma unroll
+  for (int j = 0; j < 37; ++j) {
+    const double p = j == C ? pc : row_bcast<C>(R[j]);
+    if (j > C) {   // face rows: interior columns still to be pivoted, face columns, rhs
+      A[j] = fma(-ma, p, A[j]);
+      B[j] = fma(-mb, p, B[j]);
+      // (the updates must not sink towards their first use in the face sweep)
+      __asm__ volatile("" : "+v"(A[j]), "+v"(B[j]));
+    }
+    R[j] = fma(-mi, p, R[j]);
+    __asm__ volatile("" : "+v"(R[j]));
+  }
+}
+
+// One Gauss-Jordan step on face pivot K (face row K: rows A of lane K for
+// K < 12, rows B of lane K - 12 otherwise); only face columns and rhs.
+template <int K>
+__device__ __forceinline__ void face_step(double (&A)[37], double (&B)[37], int t, bool live, int32_t* status,
+                                          int64_t e) {
+  constexpr int L = K % 12;
+  constexpr bool HI = K >= 12;
+  constexpr int PC = 12 + K;
+  double d;
+  if constexpr (HI) d = row_bcast<L>(B[PC]);
+  else d = row_bcast<L>(A[PC]);
+  if (!(d > 0.0)) {
+    if (live && t == L) report_error(status, HYB_E_NOT_SPD, e);
+    d = 1.0;
+  }
+  const double inv = 1.0 / d;
+  const bool own = t == L;
+  const double ma = (!HI && own) ? 1.0 - inv : A[PC] * inv;
+  const double mb = (HI && own) ? 1.0 - inv : B[PC] * inv;
+  const double pc = d - 1.0;
+#pragma unroll
+  for (int j = 12; j < 37; ++j) {
+    double p;
+    if (j == PC) p = pc;
+    else if constexpr (HI) p = row_bcast<L>(B[j]);
+    else p = row_bcast<L>(A[j]);
+    A[j] = fma(-ma, p, A[j]);
+    B[j] = fma(-mb, p, B[j]);
+    __asm__ volatile("" : "+v"(A[j]), "+v"(B[j]));
+  }
+}
+
+template <int... Cs>
+__device__ __forceinline__ void interior_sweep(std::integer_sequence<int, Cs...>, double (&R)[37], double (&A)[37],
+                                               double (&B)[37], int t, bool live, int32_t* status, int64_t e) {
+  (interior_step<Cs>(R, A, B, t, live, status, e), ...);
+}
+template <int... Ks>
+__device__ __forceinline__ void face_sweep(std::integer_sequence<int, Ks...>, double (&A)[37], double (&B)[37], int t,
+                                           bool live, int32_t* status, int64_t e) {
+  (face_step<Ks>(A, B, t, live, status, e), ...);
+}
+
+struct FinalArgs {
+  int64_t nfaces;
+  const int64_t* rowbase;
+  const int32_t* nslots;
+  const int32_t* selfslot;
+  double* Hval;     // null: leave H alone
+  double* r;        // null: leave r alone
+  const double* side;
+};
+
+__global__ __launch_bounds__(64 * SETUP_WAVES) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_setup_k1(
+    SetupArgs a, double* side, int64_t nf) {
+  __shared__ SetupLds L;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tau = lane >> 4, t16 = lane & 15;
+  const int t = t16 < 12 ? t16 : 0;   // lanes 12..15 shadow lane 0
+  const int64_t e0 = (xcd_block() * SETUP_WAVES + wave) * SETUP_EPW;   // first element of this wave
+  const int64_t e = e0 + tau;
+  const bool valid = e < a.ne;
+  const bool live = valid && t16 < 12;
+  const int64_t es = valid ? e : 0;
   const DeviceMaps& mp = a.mp;
   const bool rhs = (a.mode & MODE_RHS) != 0;
-
-  double J[3][3], G[3][3];
-  const double det = affine_geometry(mp, es, J, G);
-  if (live && t == 0 && !(det > 0.0)) report_error(a.status, HYB_E_JACOBIAN, e);
-  const double al = a.alpha[es], bd = a.beta[es] / det;
-  double jtf[3] = {0.0, 0.0, 0.0};
-  if (rhs) {
-    const double f0 = a.f[es * 3], f1 = a.f[es * 3 + 1], f2 = a.f[es * 3 + 2];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) jtf[d] = J[0][d] * f0 + J[1][d] * f1 + J[2][d] * f2;
-  }
-  unsigned ess = 0;
-#pragma unroll
-  for (int f = 0; f < 6; ++f)
-    if (mp.elem_face[es * 6 + f] < 0) ess |= 1u << f;
-  const double* Tr = mp.tab_ref;           // T (symmetric, 36 x 36)
-  const double* Dr = mp.tab_ref + N * N;   // Dv (symmetric)
-  const double* sr = mp.tab_ref + 2 * N * N;
   const double* gb = (rhs && a.g) ? a.g + es * NB : nullptr;
-  // unmasked M_T[i][j] for dofs of components di, dj (di compile-time)
-  auto entry = [&](int i, int j, double gij) -> double {
-    return al * gij * Tr[j * N + i] + bd * Dr[j * N + i];
-  };
-  auto gsel = [&](int di, int dj) -> double {   // G[di][dj] with a runtime dj
-    return dj == 0 ? G[di][0] : (dj == 1 ? G[di][1] : G[di][2]);
-  };
-  auto ess_dof = [&](int j) -> bool { return j >= 12 && ((ess >> ((j - 12) >> 2)) & 1u); };
+  SetupWaveLds& W = L.w[wave];
 
-  // ======== pass 1: interior rows, column-cyclic (lane t owns the columns
-  // j = base + 8 m, m = 0..4, j = 36 being the right-hand side) ========
+  // reference integrals into LDS (the table and sr are contiguous)
   {
-    const int base = (t + 4) & 7;
-    double R[12][5];
-#pragma unroll
-    for (int r = 0; r < 12; ++r)
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        const int j = base + 8 * m;
-        R[r][m] = (j < 36 && !ess_dof(j)) ? entry(r, j, gsel(r / 4, comp(j))) : 0.0;
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    if (rhs) {
-#pragma unroll
-      for (int r = 0; r < 12; ++r) {
-        double corr = 0.0;
-        if (gb) {
-#pragma unroll
-          for (int m = 0; m < 5; ++m) {
-            const int j = base + 8 * m;
-            if (j < 36 && ess_dof(j)) corr += entry(r, j, gsel(r / 4, comp(j))) * gb[j - 12];
-          }
-          corr += __shfl_xor(corr, 1, 8);
-          corr += __shfl_xor(corr, 2, 8);
-          corr += __shfl_xor(corr, 4, 8);
-        }
-        if (t == 0) R[r][4] = jtf[r / 4] * sr[r] - corr;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      double* buf = bcast + 48 * (c & 1);
-#pragma unroll
-      for (int m = 0; m < 5; ++m)
-        if (base + 8 * m <= 36) buf[base + 8 * m] = R[c][m];
-      __syncthreads();
-      double d = buf[c];
-      if (!(d > 0.0)) {
-        if (live && t == 0) report_error(a.status, HYB_E_NOT_SPD, e);
-        d = 1.0;
-      }
-      const double sq = sqrt(d), is = 1.0 / sq;
-#pragma unroll
-      for (int m = 0; m < 5; ++m) R[c][m] = (base + 8 * m == c) ? sq : R[c][m] * is;
-#pragma unroll
-      for (int r = 0; r < 12; ++r) {
-        if (r <= c) continue;
-        const double ur = buf[r] * is;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) R[r][m] -= ur * R[c][m];
-      }
-#pragma unroll
-      for (int r = 0; r < 12; ++r)
-#pragma unroll
-        for (int m = 0; m < 5; ++m) __asm__ volatile("" : "+v"(R[r][m]));
-      // finished row c: U_ii and W to HBM, W and y_c to LDS for pass 2
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        const int j = base + 8 * m;
-        if (j < c || j > 36) continue;
-        const double v = R[c][m];
-        if (j < 12) {
-          if (live) a.factor[fidx(e, uoff(c) + (j - c))] = v;
-        } else if (j < 36) {
-          wbuf[24 * c + (j - 12)] = v;
-          if (live) a.factor[fidx(e, OFF_W + 24 * c + (j - 12))] = v;
-        } else {
-          wbuf[288 + c] = v;
-          if (rhs && live) a.y[yidx(e, c)] = v;
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // ======== pass 2: face rows a = 8 s + t (component s), lower part
-  // b <= 8 s + 7: S = A_bb - W^T W and t = f_b - W^T y_i ========
-  // rows of the three slots stored back to back: slot s starts at 4 s (s + 1)
-  double Sr[48], ts[3];
-#define SROW(s, b) Sr[4 * (s) * ((s) + 1) + (b)]
-  // Keep every row value materialized here: without it the compiler sinks
-  // each row's chain of updates down to its first reader and keeps all the
-  // operands alive meanwhile.
-#define PIN_ROWS()                                         \
-  do {                                                     \
-    _Pragma("unroll") for (int q_ = 0; q_ < 48; ++q_)      \
-      __asm__ volatile("" : "+v"(Sr[q_]));                 \
-    __asm__ volatile("" : "+v"(ts[0]), "+v"(ts[1]), "+v"(ts[2])); \
-  } while (0)
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const int arow = 8 * s + t, ia = 12 + arow;
-    const bool ess_a = ess_dof(ia);
-#pragma unroll
-    for (int b = 0; b < 24; ++b) {
-      if (b > 8 * s + 7) break;
-      double v;
-      if (ess_a || ess_dof(12 + b)) v = (b == arow) ? 1.0 : 0.0;
-      else v = entry(ia, 12 + b, G[s][b >> 3]);
-      SROW(s, b) = v;
-    }
-    double tv = 0.0;
-    if (rhs) {
-      if (ess_a) {
-        tv = gb ? gb[arow] : 0.0;
-      } else {
-        tv = jtf[s] * sr[ia];
-        if (gb) {
-#pragma unroll
-          for (int b = 0; b < 24; ++b)
-            if (ess_dof(12 + b)) tv -= entry(ia, 12 + b, G[s][b >> 3]) * gb[b];
-        }
-      }
-    }
-    ts[s] = tv;
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // S -= W^T W and t -= W^T y_i, one interior row c at a time (W entries of
-  // boundary faces are zero, so identity rows stay identity)
-#pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const double w0 = wbuf[24 * c + t], w1 = wbuf[24 * c + 8 + t], w2 = wbuf[24 * c + 16 + t];
-    const double yc = wbuf[288 + c];
-#pragma unroll
-    for (int b = 0; b < 24; ++b) {
-      const double u = wbuf[24 * c + b];
-      if (b < 8) SROW(0, b) -= w0 * u;
-      if (b < 16) SROW(1, b) -= w1 * u;
-      SROW(2, b) -= w2 * u;
-    }
-    if (rhs) {
-      ts[0] -= w0 * yc;
-      ts[1] -= w1 * yc;
-      ts[2] -= w2 * yc;
-    }
-    PIN_ROWS();
+    const double2* src = reinterpret_cast<const double2*>(mp.tab_ref);
+    double2* dst = L.td;
+    for (int p = threadIdx.x; p < N * N + N / 2; p += 64 * SETUP_WAVES) dst[p] = src[p];
   }
 
-  // ======== Cholesky of S (lower rows in registers), forward solve y_b ========
-#pragma unroll
-  for (int c = 0; c < 24; ++c) {
-    double* buf = bcast + 48 * (c & 1);
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      if (c <= 8 * s + 7) buf[8 * s + t] = SROW(s, c);
-      buf[24 + 8 * s + t] = ts[s];
-    }
-    __syncthreads();
-    double d = buf[c];
-    if (!(d > 0.0)) {
-      if (live && t == 0) report_error(a.status, HYB_E_NOT_SPD, e);
-      d = 1.0;
-    }
-    const double sq = sqrt(d), is = 1.0 / sq, inv = 1.0 / d;
-    const double yc = buf[24 + c] * is;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int arow = 8 * s + t;
-      if (c < 8 * s + 7) {
-        const double la = SROW(s, c);
-        const double lai = la * inv;
-#pragma unroll
-        for (int j = 0; j < 24; ++j)
-          if (j > c && j <= 8 * s + 7) SROW(s, j) -= lai * buf[j];
-        if (rhs) ts[s] -= (arow > c ? la * is : 0.0) * yc;
-      }
-      if (c <= 8 * s + 7) {
-        const double v = SROW(s, c);
-        SROW(s, c) = (arow == c) ? sq : (arow > c ? v * is : v);
-      }
-    }
-    if (t == (c & 7)) {
-      ybuf[c] = yc;
-      if (rhs && live) a.y[yidx(e, 12 + c)] = yc;
-    }
-    PIN_ROWS();
-  }
-  // clear the upper parts of the rows (the in-place inversion sums over them)
-#pragma unroll
-  for (int s = 0; s < 3; ++s)
-#pragma unroll
-    for (int b = 0; b < 24; ++b)
-      if (b <= 8 * s + 7 && b > 8 * s + t) SROW(s, b) = 0.0;
+  Elem el;
+  el.load(mp, es, a.alpha, a.beta, rhs ? a.f : nullptr, true);
+  if (live && t == 0 && !(el.det > 0.0)) report_error(a.status, HYB_E_JACOBIAN, e);
 
-  // ======== in-place inversion L -> L^{-1}, columns right to left ========
-#pragma unroll
-  for (int j = 23; j >= 0; --j) {
-    double* buf = bcast + 48 * (j & 1);
-#pragma unroll
-    for (int s = 0; s < 3; ++s)
-      if (j <= 8 * s + 7) buf[8 * s + t] = SROW(s, j);
-    __syncthreads();
-    const double rinv = 1.0 / buf[j];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      if (j > 8 * s + 7) continue;
-      const int arow = 8 * s + t;
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < 24; ++k)
-        if (k > j && k <= 8 * s + 7) acc += SROW(s, k) * buf[k];
-      const double v = SROW(s, j);
-      SROW(s, j) = (arow > j) ? -rinv * acc : (arow == j ? rinv : v);
-    }
-    PIN_ROWS();
+  // face data of the element for the H scatter (used at the end)
+  if (t16 < 6) {
+    HMeta& hm = W.meta[tau];
+    const int F = mp.elem_face[es * 6 + t16];
+    hm.fid[t16] = F;
+    hm.pi[t16] = mp.elem_pi[es * 8 + t16];
+    hm.rb[t16] = F >= 0 ? mp.face_rowbase[F] : 0;
+    hm.ns[t16] = F >= 0 ? mp.face_nslots[F] : 0;
+    hm.own[t16] = F >= 0 ? int(mp.face_owner[F] == es) : 0;
   }
-  // L^{-1} rows to LDS (packed lower rows; W is no longer needed)
+  if (t16 < 12) {
 #pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const int arow = 8 * s + t;
-#pragma unroll
-    for (int b = 0; b < 24; ++b)
-      if (b <= 8 * s + 7 && b <= arow) lin[arow * (arow + 1) / 2 + b] = SROW(s, b);
+    for (int q = 0; q < 3; ++q) W.meta[tau].slot[t16 + 12 * q] = mp.elem_slot[es * 36 + t16 + 12 * q];
   }
-  if (t < 4) lin[300 + t] = 0.0;
-  __syncthreads();
+  __syncthreads();   // table in LDS
 
-  if (!live) return;
-  // face ids and frame codes, indexed by runtime face numbers below
-  const int* fid = mp.elem_face + e * 6;
-  const uint8_t* pic = mp.elem_pi + e * 8;
-  // L^{-1} to HBM, team-cooperative
-  for (int p = t; p < 300; p += 8) a.factor[fidx(e, OFF_LI + p)] = lin[p];
-#undef SROW
-#undef PIN_ROWS
-  // H_T = D L^{-T} L^{-1} D in 4x4 face blocks
-  for (int q = 0; q < 4; ++q) {
-    const int code = c_blocks[t][q];
-    if (code == 255) break;
-    const int fa = code >> 3, fb = code & 7;
-    if (fid[fa] < 0 || fid[fb] < 0) continue;
-    double h[4][4];
+  const double2* TD = L.td;
+  const double* sr = L.sr;
+  const int ia = 12 + t, ib = 24 + t;   // local dofs of the two face rows
+  const int ci = t >> 2, ca = t >> 3, cb = (12 + t) >> 3;
+  double agi[3], aga[3], agb[3];
+  el.arow(ci, agi);
+  el.arow(ca, aga);
+  el.arow(cb, agb);
+
+  // ---- scales of the three rows, from their diagonal entries ----
+  // (same operations as the corresponding entries of the assembled rows)
+  auto diag_of = [&](int i, const double (&ag)[3], int c) {
+    const double2 td = TD[i * N + i];
+    const double w0 = c == 0 ? 1.0 : 0.0, w1 = c == 1 ? 1.0 : 0.0, w2 = c == 2 ? 1.0 : 0.0;
+    return fma(w0 * ag[0] + w1 * ag[1] + w2 * ag[2], td.x, el.bd * td.y);
+  };
+  const double si = pow2_scale(diag_of(t, agi, ci));
+  const double sa = el.ess_dof(ia) ? 1.0 : pow2_scale(diag_of(ia, aga, ca));
+  const double sb = el.ess_dof(ib) ? 1.0 : pow2_scale(diag_of(ib, agb, cb));
+  // scale of local dof j, from the lane that holds its row
+  auto sig = [&](auto jc) -> double {
+    constexpr int j = decltype(jc)::value;
+    if constexpr (j < 12) return row_bcast<j>(si);
+    else if constexpr (j < 24) return row_bcast<j - 12>(sa);
+    else return row_bcast<j - 24>(sb);
+  };
+
+  // ---- assembly of the three scaled rows ----
+  // The boundary correction of the right-hand side is accumulated from the
+  // unscaled entries in the order rhs_entry uses.
+  auto gval = [&](int j) { return gb ? gb[j - 12] : 0.0; };
+  double R[37], A[37], B[37];
+  double cri = 0.0, cra = 0.0, crb = 0.0;
+  const bool ei = false, ea = el.ess_dof(ia), eb = el.ess_dof(ib);
+  auto entry = [&](int i, int j, bool erow, const double (&ag)[3], double& cr) {
+    const double2 td = TD[j * N + i];
+    const double v = fma(ag[comp(j)], td.x, el.bd * td.y);
+    const bool ej = el.ess_dof(j);
+    if (j >= 12 && rhs) cr = fma(ej ? v : 0.0, gval(j), cr);
+    return (erow || ej) ? (i == j ? 1.0 : 0.0) : v;
+  };
+  static_for<0, 36>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    const double sj = sig(jc);
+    R[j] = entry(t, j, ei, agi, cri) * (si * sj);
+    A[j] = entry(ia, j, ea, aga, cra) * (sa * sj);
+    B[j] = entry(ib, j, eb, agb, crb) * (sb * sj);
+    __asm__ volatile("" : "+v"(R[j]), "+v"(A[j]), "+v"(B[j]));   // keep the entries computed here
+  });
+  R[36] = rhs ? si * (el.jsel(ci) * sr[t] - cri) : 0.0;
+  A[36] = rhs ? sa * (ea ? gval(ia) : el.jsel(ca) * sr[ia] - cra) : 0.0;
+  B[36] = rhs ? sb * (eb ? gval(ib) : el.jsel(cb) * sr[ib] - crb) : 0.0;
+
+  // ---- sweep of the interior pivots over all rows ----
+  interior_sweep(std::make_integer_sequence<int, 12>{}, R, A, B, t, live, a.status, e);
+
+  // ---- interior outputs: A_ii^{-1} row t, E row t, y_i ----
+  // A_ii^{-1}[t][j] = -s_t s_j (R[j] - 2 delta_tj), E[t][b] = s_t / s_b R[12 + b]
+  {
+    double* st = W.stage[tau];
+    static_for<0, 12>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      const double v = -(R[j] - (j == t ? 2.0 : 0.0)) * (si * sig(jc));
+      if (t16 < 12 && j <= t) st[t * (t + 1) / 2 + j] = v;
+    });
+    static_for<12, 36>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      const double v = R[j] * (si / sig(jc));
+      if (t16 < 12) st[OFF_E + 24 * t + (j - 12)] = v;
+    });
+  }
+  if (live && rhs) a.y[e * N + t] = R[36] * si;
+  wave_sync();
+  write_records<SETUP_EPW>(a.factor, W.stage, e0, a.ne, 0, OFF_SI);
+
+  // ---- sweep of the face pivots over the face rows ----
+  face_sweep(std::make_integer_sequence<int, 24>{}, A, B, t, live, a.status, e);
+
+  // ---- face outputs: S^{-1} rows, y_b, r_T; then the record and H_T ----
+  // S^{-1}[a][b] = -s_a s_b (S[a][b] - 2 delta_ab), lower triangle staged by rows
+  wave_sync();   // the record copy above has read the staging area
+  auto face_out = [&](const double (&S)[37], int arow, double s_a) {
+    double* st = W.stage[tau];
+    static_for<12, 36>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      constexpr int b = j - 12;
+      const double v = -(S[j] - (b == arow ? 2.0 : 0.0)) * (s_a * sig(jc));
+      if (t16 < 12 && b <= arow) st[arow * (arow + 1) / 2 + b] = v;
+    });
+    if (!live || !rhs) return;
+    const double z = S[36] * s_a;
+    a.y[e * N + 12 + arow] = z;
+    const HMeta& hm = W.meta[tau];
+    const int fa = arow >> 2;
+    const int Fa = hm.fid[fa];
+    if (Fa < 0) return;
+    const int ja = own_idx(hm.pi[fa], arow & 3);
+    const double v = (fa & 1) ? z : -z;
+    if (hm.own[fa]) a.r[int64_t(Fa) * 4 + ja] = v;
+    else side[nf * 16 + int64_t(Fa) * 4 + ja] = v;
+  };
+  face_out(A, t, sa);
+  face_out(B, 12 + t, sb);
+  wave_sync();
+  write_records<SETUP_EPW>(a.factor, W.stage, e0, a.ne, OFF_SI, 300);
+  // H_T = D S^{-1} D into the CSR rows: every 4-entry row segment (one face
+  // row against the 4 dofs of one face) is written as two 16-byte halves by
+  // two adjacent lanes.  A same-face block goes in place from the face's
+  // owner and to the side buffer from its neighbour.
+  for (int c = lane; c < SETUP_EPW * 288; c += 64) {
+    const int tm = c / 288, rem = c - tm * 288;
+    const int arow = rem / 12, fb = (rem >> 1) % 6, half = rem & 1;
+    if (e0 + tm >= a.ne) continue;
+    const HMeta& hq = W.meta[tm];
+    const int fa = arow >> 2;
+    const int Fa = hq.fid[fa], Fb = hq.fid[fb];
+    if (Fa < 0 || Fb < 0) continue;
+    const int ja = own_idx(hq.pi[fa], arow & 3);
+    // element-frame dofs of the owner-frame positions 2 half and 2 half + 1
+    const int pb = hq.pi[fb];
+    int i2[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) h[i][jj] = 0.0;
-    const int a0 = 4 * fa, b0 = 4 * fb;
-    for (int c = a0; c < 24; ++c) {
-      const double* row = lin + c * (c + 1) / 2;
-      double va[4], vb[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        va[i] = (a0 + i <= c) ? row[a0 + i] : 0.0;
-        vb[i] = (b0 + i <= c) ? row[b0 + i] : 0.0;
+    for (int q = 0; q < 2; ++q) {
+      int p0 = q, p1 = half;
+      if (pb & 2) p0 = 1 - p0;
+      if (pb & 4) p1 = 1 - p1;
+      if (pb & 1) {
+        const int tq = p0;
+        p0 = p1;
+        p1 = tq;
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) h[i][jj] += va[i] * vb[jj];
+      i2[q] = p0 + 2 * p1;
     }
-    const double sgn = ((fa ^ fb) & 1) ? -1.0 : 1.0;
-    const int Fa = fid[fa], Fb = fid[fb];
-    const int64_t rba = mp.face_rowbase[Fa], rbb = mp.face_rowbase[Fb];
-    const int lena = mp.face_nslots[Fa] * 4, lenb = mp.face_nslots[Fb] * 4;
-    const int sab = mp.elem_slot[e * 36 + fa * 6 + fb] * 4, sba = mp.elem_slot[e * 36 + fb * 6 + fa] * 4;
-    // owner-frame index of each local face dof
-    int pa[4], pb[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int x0 = i & 1, x1 = i >> 1;
-      frame_map(pic[fa], 1, x0, x1);
-      pa[i] = x0 + 2 * x1;
-      int y0 = i & 1, y1 = i >> 1;
-      frame_map(pic[fb], 1, y0, y1);
-      pb[i] = y0 + 2 * y1;
-    }
-    if (fa == fb) {
-      // same face: the neighbour element adds its own term
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-          atomicAdd(&a.Hval[rba + int64_t(pa[i]) * lena + sab + pb[jj]], sgn * h[i][jj]);
-    } else if (pic[fa] == 0 && pic[fb] == 0) {
-      // both faces in the owner's frame: contiguous row segments
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        double* dst = a.Hval + rba + int64_t(i) * lena + sab;
-        dst[0] = sgn * h[i][0]; dst[1] = sgn * h[i][1]; dst[2] = sgn * h[i][2]; dst[3] = sgn * h[i][3];
-        double* dst2 = a.Hval + rbb + int64_t(i) * lenb + sba;
-        dst2[0] = sgn * h[0][i]; dst2[1] = sgn * h[1][i]; dst2[2] = sgn * h[2][i]; dst2[3] = sgn * h[3][i];
-      }
+    const double sg = ((fa ^ fb) & 1) ? -1.0 : 1.0;   // eps_a eps_b
+    const double* st = W.stage[tm];
+    const double2 v = make_double2(sg * st[spk(arow, 4 * fb + i2[0])], sg * st[spk(arow, 4 * fb + i2[1])]);
+    double* dst;
+    if (fb == fa && !hq.own[fa]) dst = side + int64_t(Fa) * 16 + ja * 4 + 2 * half;
+    else dst = a.Hval + hq.rb[fa] + int64_t(ja) * hq.ns[fa] * 4 + int64_t(hq.slot[fa * 6 + fb]) * 4 + 2 * half;
+    *reinterpret_cast<double2*>(dst) = v;
+  }
+}
+
+// Add the neighbours' terms of the same-face blocks of H (16 per face, owner
+// frame, row-major) and of r (4 per face) from the side buffer.
+__global__ void k_finalize_k1(FinalArgs a) {
+  const int64_t nh = a.Hval ? a.nfaces * 16 : 0;
+  const int64_t tot = nh + (a.r ? a.nfaces * 4 : 0);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < tot; i += int64_t(gridDim.x) * blockDim.x) {
+    if (i < nh) {
+      const int64_t F = i >> 4;
+      const int q = int(i & 15), ja = q >> 2, jb = q & 3;
+      a.Hval[a.rowbase[F] + int64_t(ja) * a.nslots[F] * 4 + int64_t(a.selfslot[F]) * 4 + jb] += a.side[i];
     } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          a.Hval[rba + int64_t(pa[i]) * lena + sab + pb[jj]] = sgn * h[i][jj];
-          a.Hval[rbb + int64_t(pb[jj]) * lenb + sba + pa[i]] = sgn * h[i][jj];
-        }
-    }
-  }
-  // r_T = D L^{-T} y_b
-  if (rhs) {
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int arow = 8 * s + t, fa = arow >> 2;
-      if (fid[fa] < 0) continue;
-      double acc = 0.0;
-      for (int c = arow; c < 24; ++c) acc += lin[c * (c + 1) / 2 + arow] * ybuf[c];
-      if (!(fa & 1)) acc = -acc;
-      int x0 = arow & 1, x1 = (arow >> 1) & 1;
-      frame_map(pic[fa], 1, x0, x1);
-      atomicAdd(&a.r[int64_t(fid[fa]) * 4 + x0 + 2 * x1], acc);
+      const int64_t j = i - nh;
+      a.r[j] += a.side[a.nfaces * 16 + j];
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// One element per lane: right-hand side on stored factors.
+// Right-hand side on stored factors, and recovery.  The wave stages the
+// records of its five elements (contiguous in HBM) in LDS with coalesced
+// 16-byte loads, then each team works on its element.
 struct SimtArgs {
   DeviceMaps mp;
   int64_t ne;
@@ -441,136 +521,131 @@ struct SimtArgs {
   double* r;
   const double* lambda;
   double* u;
+  double* side;     // neighbour terms of r (4 per face after 16 per face of H)
+  int64_t nfaces;
 };
 
-// Per-lane vectors live in LDS columns (v[i * 64 + lane]) so every loop can
-// run with a runtime index without spilling registers.
-__global__ __launch_bounds__(64) void k_rhs_k1(SimtArgs a) {
-  __shared__ double vec[60 * 64];   // y (36) then r_T accumulators (24)
-  const int L = threadIdx.x;
-  const int64_t e = int64_t(blockIdx.x) * 64 + L;
-  if (e >= a.ne) return;
-  const DeviceMaps& mp = a.mp;
-  double J[3][3], G[3][3];
-  const double det = affine_geometry(mp, e, J, G);
-  const double f0 = a.f[e * 3], f1 = a.f[e * 3 + 1], f2 = a.f[e * 3 + 2];
-  double jtf[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) jtf[d] = J[0][d] * f0 + J[1][d] * f1 + J[2][d] * f2;
-  unsigned ess = 0;
-#pragma unroll
-  for (int f = 0; f < 6; ++f)
-    if (mp.elem_face[e * 6 + f] < 0) ess |= 1u << f;
-  const double* Tr = mp.tab_ref;
-  const double* Dr = mp.tab_ref + N * N;
-  const double* sr = mp.tab_ref + 2 * N * N;
-  const double* gb = a.g ? a.g + e * NB : nullptr;
-  const double al = gb ? a.alpha[e] : 0.0, bd = gb ? a.beta[e] / det : 0.0;
-  double* y = vec;
-  double* rt = vec + 36 * 64;
-  for (int i = 0; i < 36; ++i) {
-    const int ci = comp(i);
-    double v = (ci == 0 ? jtf[0] : (ci == 1 ? jtf[1] : jtf[2])) * sr[i];
-    const bool ei = i >= 12 && ((ess >> ((i - 12) >> 2)) & 1u);
-    if (ei) {
-      v = gb ? gb[i - 12] : 0.0;
-    } else if (gb) {
-      for (int j = 12; j < 36; ++j)
-        if ((ess >> ((j - 12) >> 2)) & 1u)
-          v -= (al * G[ci][comp(j)] * Tr[j * N + i] + bd * Dr[j * N + i]) * gb[j - 12];
-    }
-    y[i * 64 + L] = v;
-  }
-  // y_i = U_ii^{-T} f_i
-  for (int c = 0; c < 12; ++c) {
-    double v = y[c * 64 + L];
-    for (int k = 0; k < c; ++k) v -= a.factor[fidx(e, uoff(k) + (c - k))] * y[k * 64 + L];
-    y[c * 64 + L] = v / a.factor[fidx(e, uoff(c))];
-  }
-  // t_b = f_b - W^T y_i
-  for (int c = 0; c < 12; ++c) {
-    const double yc = y[c * 64 + L];
-#pragma unroll 8
-    for (int b = 0; b < 24; ++b) y[(12 + b) * 64 + L] -= a.factor[fidx(e, OFF_W + 24 * c + b)] * yc;
-  }
-  // y_b = L^{-1} t_b, from the bottom row up so t_b is overwritten in place
-  for (int b = 23; b >= 0; --b) {
-    double v = 0.0;
-    for (int c = 0; c <= b; ++c) v += a.factor[fidx(e, OFF_LI + b * (b + 1) / 2 + c)] * y[(12 + c) * 64 + L];
-    y[(12 + b) * 64 + L] = v;
-  }
-  for (int i = 0; i < 36; ++i) a.y[yidx(e, i)] = y[i * 64 + L];
-  // r_T = D L^{-T} y_b
-  for (int b = 0; b < 24; ++b) rt[b * 64 + L] = 0.0;
-  for (int c = 0; c < 24; ++c) {
-    const double yc = y[(12 + c) * 64 + L];
-    for (int b = 0; b <= c; ++b) rt[b * 64 + L] += a.factor[fidx(e, OFF_LI + c * (c + 1) / 2 + b)] * yc;
-  }
-  for (int f = 0; f < 6; ++f) {
-    const int F = mp.elem_face[e * 6 + f];
-    if (F < 0) continue;
-    const int pi = mp.elem_pi[e * 8 + f];
-    for (int i = 0; i < 4; ++i) {
-      int x0 = i & 1, x1 = i >> 1;
-      frame_map(pi, 1, x0, x1);
-      const double v = rt[(4 * f + i) * 64 + L];
-      atomicAdd(&a.r[int64_t(F) * 4 + x0 + 2 * x1], (f & 1) ? v : -v);
-    }
+constexpr int RSTRIDE = REC + 2;   // team stride 4 dwords apart modulo 32 banks
+
+struct alignas(16) SolveLds {
+  double rec[SOLVE_EPW * RSTRIDE];
+  double v[SOLVE_EPW + 1][49];   // per-team exchange vectors
+};
+
+// Copy the records of elements e0 .. e0 + 4 (contiguous in HBM) into LDS
+// with coalesced 16-byte loads.
+__device__ __forceinline__ void stage_records(double* dst, const double* factor, int64_t e0, int64_t ne) {
+  const int cnt = (ne - e0) < SOLVE_EPW ? int(ne - e0) : SOLVE_EPW;
+  constexpr int H2 = REC / 2;
+  const double2* src = reinterpret_cast<const double2*>(factor + e0 * REC);
+  for (int p = threadIdx.x; p < cnt * H2; p += 64) {
+    const int tm = p / H2;
+    *reinterpret_cast<double2*>(dst + tm * RSTRIDE + 2 * (p - tm * H2)) = src[p];
   }
 }
 
-// One element per lane: u_b = L^{-T}(y_b - L^{-1} D lambda_b),
-// u_i = U_ii^{-1}(y_i - W u_b).  The per-lane vector (36 entries, the local
-// order of u) stays in an LDS column and is written out coalesced.
-__global__ __launch_bounds__(64) void k_recover_k1(SimtArgs a) {
-  __shared__ double vec[36 * 64 + 64];
-  const int L = threadIdx.x;
-  const int64_t e0 = int64_t(blockIdx.x) * 64;
-  const int64_t e = e0 + L;
+__global__ __launch_bounds__(64) void k_rhs_k1(SimtArgs a) {
+  __shared__ SolveLds L;
+  const int lane = threadIdx.x, tau = lane / TEAM, t = lane - tau * TEAM;
+  const int64_t e0 = xcd_block() * SOLVE_EPW;
+  const int64_t e = e0 + tau;
+  const bool live = tau < SOLVE_EPW && e < a.ne;
+  const int64_t es = live ? e : 0;
   const DeviceMaps& mp = a.mp;
-  double* v = vec;   // v[i * 64 + L]: [0,12) interior, [12,36) face block
-  if (e < a.ne) {
-    for (int f = 0; f < 6; ++f) {
-      const int F = mp.elem_face[e * 6 + f];
-      const int pi = mp.elem_pi[e * 8 + f];
-      for (int i = 0; i < 4; ++i) {
-        double x = 0.0;
-        if (F >= 0) {
-          int x0 = i & 1, x1 = i >> 1;
-          frame_map(pi, 1, x0, x1);
-          x = a.lambda[int64_t(F) * 4 + x0 + 2 * x1];
-          if (!(f & 1)) x = -x;
-        }
-        v[(12 + 4 * f + i) * 64 + L] = x;
-      }
-    }
-    // z_b = y_b - L^{-1} t, bottom row first (in place over t)
-    for (int b = 23; b >= 0; --b) {
-      double s = a.y[yidx(e, 12 + b)];
-      for (int c = 0; c <= b; ++c) s -= a.factor[fidx(e, OFF_LI + b * (b + 1) / 2 + c)] * v[(12 + c) * 64 + L];
-      v[(12 + b) * 64 + L] = s;
-    }
-    // u_b = L^{-T} z_b, top row first (in place over z)
-    for (int b = 0; b < 24; ++b) {
-      double s = 0.0;
-      for (int c = b; c < 24; ++c) s += a.factor[fidx(e, OFF_LI + c * (c + 1) / 2 + b)] * v[(12 + c) * 64 + L];
-      v[(12 + b) * 64 + L] = s;
-    }
-    // u_i = U_ii^{-1} (y_i - W u_b), backward
-    for (int c = 11; c >= 0; --c) {
-      double s = a.y[yidx(e, c)];
-#pragma unroll 8
-      for (int b = 0; b < 24; ++b) s -= a.factor[fidx(e, OFF_W + 24 * c + b)] * v[(12 + b) * 64 + L];
-      for (int k = c + 1; k < 12; ++k) s -= a.factor[fidx(e, uoff(c) + (k - c))] * v[k * 64 + L];
-      v[c * 64 + L] = s / a.factor[fidx(e, uoff(c))];
-    }
-  }
+  stage_records(L.rec, a.factor, e0, a.ne);
+  const double* gb = a.g ? a.g + es * NB : nullptr;
+  Elem el;
+  el.load(mp, es, a.alpha, a.beta, a.f, gb != nullptr);
+  const double fi = rhs_entry(el, mp, t, gb);
+  const double fa = rhs_entry(el, mp, 12 + t, gb);
+  const double fb = rhs_entry(el, mp, 24 + t, gb);
+  double* v = L.v[tau];
+  v[t] = fi;
   __syncthreads();
-  const int64_t cnt = (a.ne - e0) < 64 ? (a.ne - e0) : 64;
-  for (int p = L; p < cnt * 36; p += 64) {
-    const int el = p / 36, i = p % 36;
-    a.u[e0 * 36 + p] = v[i * 64 + el];
+  const double* rec = L.rec + (live ? tau : 0) * RSTRIDE;
+  // y_i = A_ii^{-1} f_i; t_b = f_b - E^T f_i
+  double yi = 0.0, ta = fa, tb = fb;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const double fc = v[c];
+    yi = fma(rec[spk(t, c)], fc, yi);
+    ta = fma(-rec[OFF_E + 24 * c + t], fc, ta);
+    tb = fma(-rec[OFF_E + 24 * c + 12 + t], fc, tb);
   }
+  v[12 + t] = ta;
+  v[24 + t] = tb;
+  __syncthreads();
+  // z = S^{-1} t_b
+  double za = 0.0, zb = 0.0;
+#pragma unroll
+  for (int b = 0; b < 24; ++b) {
+    const double tv = v[12 + b];
+    za = fma(rec[OFF_SI + spk(t, b)], tv, za);
+    zb = fma(rec[OFF_SI + spk(12 + t, b)], tv, zb);
+  }
+  if (!live) return;
+  a.y[e * N + t] = yi;
+  a.y[e * N + 12 + t] = za;
+  a.y[e * N + 24 + t] = zb;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int arow = 12 * h + t;
+    const int fc = arow >> 2;
+    const int F = mp.elem_face[e * 6 + fc];
+    if (F < 0) continue;
+    const int ja = own_idx(mp.elem_pi[e * 8 + fc], arow & 3);
+    const double z = h ? zb : za;
+    const double v = (fc & 1) ? z : -z;
+    if (mp.face_owner[F] == e) a.r[int64_t(F) * 4 + ja] = v;
+    else a.side[a.nfaces * 16 + int64_t(F) * 4 + ja] = v;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_recover_k1(SimtArgs a) {
+  __shared__ SolveLds L;
+  const int lane = threadIdx.x, tau = lane / TEAM, t = lane - tau * TEAM;
+  const int64_t e0 = xcd_block() * SOLVE_EPW;
+  const int64_t e = e0 + tau;
+  const bool live = tau < SOLVE_EPW && e < a.ne;
+  const int64_t es = live ? e : 0;
+  const DeviceMaps& mp = a.mp;
+  stage_records(L.rec, a.factor, e0, a.ne);
+  // D lambda on the two face rows of this lane
+  double* v = L.v[tau];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int arow = 12 * h + t;
+    const int fc = arow >> 2;
+    const int F = mp.elem_face[es * 6 + fc];
+    double x = 0.0;
+    if (F >= 0) {
+      x = a.lambda[int64_t(F) * 4 + own_idx(mp.elem_pi[es * 8 + fc], arow & 3)];
+      if (!(fc & 1)) x = -x;
+    }
+    v[arow] = x;
+  }
+  const double yi = a.y[es * N + t], ya = a.y[es * N + 12 + t], yb = a.y[es * N + 24 + t];
+  __syncthreads();
+  const double* rec = L.rec + (live ? tau : 0) * RSTRIDE;
+  // u_b = y_b - S^{-1} D lambda
+  double ua = ya, ub = yb;
+#pragma unroll
+  for (int b = 0; b < 24; ++b) {
+    const double tl = v[b];
+    ua = fma(-rec[OFF_SI + spk(t, b)], tl, ua);
+    ub = fma(-rec[OFF_SI + spk(12 + t, b)], tl, ub);
+  }
+  v[24 + t] = ua;
+  v[36 + t] = ub;
+  __syncthreads();
+  // u_i = y_i - E u_b
+  double ui = yi;
+#pragma unroll
+  for (int b = 0; b < 24; ++b) ui = fma(-rec[OFF_E + 24 * t + b], v[24 + b], ui);
+  if (!live) return;
+  a.u[e * N + t] = ui;
+  a.u[e * N + 12 + t] = ua;
+  a.u[e * N + 24 + t] = ub;
 }
 
 }  // namespace k1

@@ -58,6 +58,7 @@ struct DeviceMaps {
   const double* tab_ref;       // 2 n^2 + n
   const double* gauss_x;       // q1 points on [0,1]
   const int32_t* face_selfslot;
+  const int32_t* face_owner;   // owner element of every interior face
 };
 
 // Sticky device error: the first (code, element) pair wins.

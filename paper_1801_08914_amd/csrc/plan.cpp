@@ -340,20 +340,27 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
           P.tab_d[size_t(q * o.n + i)] = dLc[qa[d]][size_t(ic)] * tang;
         }
       }
-  // Affine reference integrals: T[i][j] = sum_q w s_i s_j, Dr[i][j] =
-  // sum_q w div_i div_j (both n x n), sr[i] = sum_q w s_i.
+  // Affine reference integrals, computed for j <= i and mirrored so the table
+  // is exactly symmetric: {T[i][j], Dr[i][j]} pairs at 2 (n i + j) with
+  // T[i][j] = sum_q w s_i s_j and Dr[i][j] = sum_q w div_i div_j; then
+  // sr[i] = sum_q w s_i at 2 n^2.
   P.tab_ref.assign(size_t(2 * o.n * o.n + o.n), 0.0);
   for (int q = 0; q < o.Q; ++q) {
     double w = P.tab_w[size_t(q)];
     for (int i = 0; i < o.n; ++i) {
       double si = P.tab_s[size_t(q * o.n + i)], di = P.tab_d[size_t(q * o.n + i)];
       P.tab_ref[size_t(2 * o.n * o.n + i)] += w * si;
-      for (int j = 0; j < o.n; ++j) {
-        P.tab_ref[size_t(i * o.n + j)] += w * si * P.tab_s[size_t(q * o.n + j)];
-        P.tab_ref[size_t(o.n * o.n + i * o.n + j)] += w * di * P.tab_d[size_t(q * o.n + j)];
+      for (int j = 0; j <= i; ++j) {
+        P.tab_ref[size_t(2 * (i * o.n + j))] += w * si * P.tab_s[size_t(q * o.n + j)];
+        P.tab_ref[size_t(2 * (i * o.n + j) + 1)] += w * di * P.tab_d[size_t(q * o.n + j)];
       }
     }
   }
+  for (int i = 0; i < o.n; ++i)
+    for (int j = 0; j < i; ++j) {
+      P.tab_ref[size_t(2 * (j * o.n + i))] = P.tab_ref[size_t(2 * (i * o.n + j))];
+      P.tab_ref[size_t(2 * (j * o.n + i) + 1)] = P.tab_ref[size_t(2 * (i * o.n + j) + 1)];
+    }
 
   // Device map layout.
   MapLayout& L = P.lay;
@@ -371,6 +378,7 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
   L.tab_ref = off;      off = align256(off + sizeof(double) * P.tab_ref.size());
   L.tab_x = off;        off = align256(off + sizeof(double) * P.tab_x.size());
   L.face_selfslot = off; off = align256(off + sizeof(int32_t) * size_t(nf));
+  L.face_owner = off;   off = align256(off + sizeof(int32_t) * size_t(nf));
   L.total = off;
   P.factor_len = int64_t(o.n) * (o.n + 1) / 2;
   return HYB_OK;

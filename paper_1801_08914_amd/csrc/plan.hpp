@@ -30,7 +30,7 @@ struct Order {
 struct MapLayout {
   size_t e2v = 0, xyz = 0, elem_face = 0, elem_pi = 0, elem_slot = 0,
          face_rowbase = 0, face_nslots = 0, tab_s = 0, tab_d = 0, tab_w = 0,
-         tab_ref = 0, tab_x = 0, face_selfslot = 0, total = 0;
+         tab_ref = 0, tab_x = 0, face_selfslot = 0, face_owner = 0, total = 0;
 };
 
 struct Plan {
@@ -53,7 +53,7 @@ struct Plan {
   std::vector<uint8_t> elem_slot;     // ne x 36: slot of face b in face a's rows
   std::vector<int32_t> face_selfslot; // nfaces: slot of the face in its own rows
   bool all_affine = false;            // every element is a parallelepiped
-  bool fast_k1 = false;               // RT_1 affine kernels (64-interleaved factors)
+  bool fast_k1 = false;               // RT_1 affine kernels (own factor record layout)
   // reference tables at the Gauss points (axis 0 fastest)
   std::vector<double> tab_s;        // Q x n: basis value (its only nonzero component)
   std::vector<double> tab_d;        // Q x n: reference divergence
@@ -64,7 +64,6 @@ struct Plan {
   int64_t factor_len = 0;
   // device state
   hyb_opts opts{};
-  int64_t ne_pad = 0;                 // ne rounded up to 64 (interleaved layouts)
   hyb_buffers buf{};
   bool bound = false, have_setup = false, have_rhs = false;
   const double* alpha_d = nullptr;  // coefficients of the last setup (caller-owned)
