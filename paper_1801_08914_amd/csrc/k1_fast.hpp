@@ -223,74 +223,88 @@ __device__ __forceinline__ void write_records(double* factor, const double (*sta
   }
 }
 
-// One Gauss-Jordan step on interior pivot C (held by lane C).
-template <int C>
-__device__ __forceinline__ void interior_step(double (&R)[37], double (&A)[37], double (&B)[37], int t, bool live,
-                                              int32_t* status, int64_t e) {
-  double d = row_bcast<C>(R[C]);
-  if (!(d > 0.0)) {
-    if (live && t == C) report_error(status, HYB_E_NOT_SPD, e);
-    d = 1.0;
+// Pivot data of one Gauss-Jordan step: 1/d and d - 1 (the value the pivot
+// entry takes in the update).  A pivot that is not positive is recorded in
+// bad and replaced by 1.
+struct Pivot {
+  double inv, pc;
+};
+__device__ __forceinline__ Pivot make_pivot(double d, unsigned& bad) {
+  const bool ok = d > 0.0;
+  bad |= ok ? 0u : 1u;
+  d = ok ? d : 1.0;
+  return {1.0 / d, d - 1.0};
+}
+
+// Pivot S of the sweep as seen by every lane of the element's row: interior
+// pivot S (S < 12) is R[S] of lane S, face pivot K = S - 12 is column S of the
+// face row K, i.e. A of lane K (K < 12) or B of lane K - 12.
+template <int S>
+__device__ __forceinline__ double pivot_value(const double (&R)[37], const double (&A)[37], const double (&B)[37]) {
+  if constexpr (S < 12) return row_bcast<S>(R[S]);
+  else if constexpr (S < 24) return row_bcast<S - 12>(A[S]);
+  else return row_bcast<S - 24>(B[S]);
+}
+
+// Step S of the sweep (S < 12: interior pivot S over all three rows; S >= 12:
+// face pivot S - 12 over the face rows, face columns and rhs).  Column S + 1
+// holds the next pivot: it is updated first, so that the next division
+// overlaps the rest of this step.
+template <int S>
+__device__ __forceinline__ Pivot sweep_step(double (&R)[37], double (&A)[37], double (&B)[37], int t, Pivot pv,
+                                            unsigned& bad) {
+  constexpr bool INT = S < 12;
+  constexpr int L = S < 12 ? S : (S - 12) % 12;   // lane holding the pivot row
+  const bool own = t == L;
+  double mi = 0.0, ma, mb;
+  if constexpr (INT) {
+    mi = own ? 1.0 - pv.inv : R[S] * pv.inv;
+    ma = A[S] * pv.inv;
+    mb = B[S] * pv.inv;
+  } else {
+    ma = (S < 24 && own) ? 1.0 - pv.inv : A[S] * pv.inv;
+    mb = (S >= 24 && own) ? 1.0 - pv.inv : B[S] * pv.inv;
   }
-  const double inv = 1.0 / d;
-  const double mi = t == C ? 1.0 - inv : R[C] * inv;
-  const double ma = A[C] * inv, mb = B[C] * inv;
-  const double pc = d - 1.0;
-#pragma unroll
-  for (int j = 0; j < 37; ++j) {
-    const double p = j == C ? pc : row_bcast<C>(R[j]);
-    if (j > C) {   // face rows: interior columns still to be pivoted, face columns, rhs
+  auto col = [&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    double p;
+    if constexpr (j == S) p = pv.pc;
+    else if constexpr (INT) p = row_bcast<L>(R[j]);
+    else if constexpr (S < 24) p = row_bcast<L>(A[j]);
+    else p = row_bcast<L>(B[j]);
+    if constexpr (j > S || (!INT && j >= 12)) {
+      // face rows: interior columns still to be pivoted, face columns, rhs
       A[j] = fma(-ma, p, A[j]);
       B[j] = fma(-mb, p, B[j]);
-      // (the updates must not sink towards their first use in the face sweep)
+      // (the updates must not sink towards their first use)
       __asm__ volatile("" : "+v"(A[j]), "+v"(B[j]));
     }
-    R[j] = fma(-mi, p, R[j]);
-    __asm__ volatile("" : "+v"(R[j]));
+    if constexpr (INT) {
+      R[j] = fma(-mi, p, R[j]);
+      __asm__ volatile("" : "+v"(R[j]));
+    }
+  };
+  constexpr int J0 = INT ? 0 : 12;
+  Pivot next{1.0, 0.0};
+  if constexpr (S + 1 < 36) {
+    col(std::integral_constant<int, S + 1>{});
+    next = make_pivot(pivot_value<S + 1>(R, A, B), bad);
   }
+  static_for<J0, 37>([&](auto jc) {
+    if constexpr (decltype(jc)::value != S + 1 || S + 1 == 36) col(jc);
+  });
+  return next;
 }
 
-// One Gauss-Jordan step on face pivot K (face row K: rows A of lane K for
-// K < 12, rows B of lane K - 12 otherwise); only face columns and rhs.
-template <int K>
-__device__ __forceinline__ void face_step(double (&A)[37], double (&B)[37], int t, bool live, int32_t* status,
-                                          int64_t e) {
-  constexpr int L = K % 12;
-  constexpr bool HI = K >= 12;
-  constexpr int PC = 12 + K;
-  double d;
-  if constexpr (HI) d = row_bcast<L>(B[PC]);
-  else d = row_bcast<L>(A[PC]);
-  if (!(d > 0.0)) {
-    if (live && t == L) report_error(status, HYB_E_NOT_SPD, e);
-    d = 1.0;
+template <int S0, int S1>
+__device__ __forceinline__ Pivot sweep(double (&R)[37], double (&A)[37], double (&B)[37], int t, Pivot pv,
+                                       unsigned& bad) {
+  if constexpr (S0 < S1) {
+    const Pivot nx = sweep_step<S0>(R, A, B, t, pv, bad);
+    return sweep<S0 + 1, S1>(R, A, B, t, nx, bad);
+  } else {
+    return pv;
   }
-  const double inv = 1.0 / d;
-  const bool own = t == L;
-  const double ma = (!HI && own) ? 1.0 - inv : A[PC] * inv;
-  const double mb = (HI && own) ? 1.0 - inv : B[PC] * inv;
-  const double pc = d - 1.0;
-#pragma unroll
-  for (int j = 12; j < 37; ++j) {
-    double p;
-    if (j == PC) p = pc;
-    else if constexpr (HI) p = row_bcast<L>(B[j]);
-    else p = row_bcast<L>(A[j]);
-    A[j] = fma(-ma, p, A[j]);
-    B[j] = fma(-mb, p, B[j]);
-    __asm__ volatile("" : "+v"(A[j]), "+v"(B[j]));
-  }
-}
-
-template <int... Cs>
-__device__ __forceinline__ void interior_sweep(std::integer_sequence<int, Cs...>, double (&R)[37], double (&A)[37],
-                                               double (&B)[37], int t, bool live, int32_t* status, int64_t e) {
-  (interior_step<Cs>(R, A, B, t, live, status, e), ...);
-}
-template <int... Ks>
-__device__ __forceinline__ void face_sweep(std::integer_sequence<int, Ks...>, double (&A)[37], double (&B)[37], int t,
-                                           bool live, int32_t* status, int64_t e) {
-  (face_step<Ks>(A, B, t, live, status, e), ...);
 }
 
 struct FinalArgs {
@@ -399,7 +413,9 @@ __global__ __launch_bounds__(64 * SETUP_WAVES) __attribute__((amdgpu_waves_per_e
   B[36] = rhs ? sb * (eb ? gval(ib) : el.jsel(cb) * sr[ib] - crb) : 0.0;
 
   // ---- sweep of the interior pivots over all rows ----
-  interior_sweep(std::make_integer_sequence<int, 12>{}, R, A, B, t, live, a.status, e);
+  unsigned bad = 0;
+  Pivot pv = make_pivot(pivot_value<0>(R, A, B), bad);
+  pv = sweep<0, 12>(R, A, B, t, pv, bad);
 
   // ---- interior outputs: A_ii^{-1} row t, E row t, y_i ----
   // A_ii^{-1}[t][j] = -s_t s_j (R[j] - 2 delta_tj), E[t][b] = s_t / s_b R[12 + b]
@@ -421,7 +437,8 @@ __global__ __launch_bounds__(64 * SETUP_WAVES) __attribute__((amdgpu_waves_per_e
   write_records<SETUP_EPW>(a.factor, W.stage, e0, a.ne, 0, OFF_SI);
 
   // ---- sweep of the face pivots over the face rows ----
-  face_sweep(std::make_integer_sequence<int, 24>{}, A, B, t, live, a.status, e);
+  sweep<12, 36>(R, A, B, t, pv, bad);
+  if (live && t == 0 && bad) report_error(a.status, HYB_E_NOT_SPD, e);
 
   // ---- face outputs: S^{-1} rows, y_b, r_T; then the record and H_T ----
   // S^{-1}[a][b] = -s_a s_b (S[a][b] - 2 delta_ab), lower triangle staged by rows
@@ -525,23 +542,33 @@ struct SimtArgs {
   int64_t nfaces;
 };
 
-constexpr int RSTRIDE = REC + 2;   // team stride 4 dwords apart modulo 32 banks
+// Records of the SOLVE_EPW elements of a wave, copied HBM -> LDS by the
+// direct-to-LDS loads of gfx950 (1 KB per instruction, no registers).
+constexpr int STAGE_CHUNKS = (SOLVE_EPW * REC * 8 + 1023) / 1024;
 
 struct alignas(16) SolveLds {
-  double rec[SOLVE_EPW * RSTRIDE];
+  double rec[STAGE_CHUNKS * 128];
   double v[SOLVE_EPW + 1][49];   // per-team exchange vectors
 };
 
-// Copy the records of elements e0 .. e0 + 4 (contiguous in HBM) into LDS
-// with coalesced 16-byte loads.
+// Element records e0 .. e0 + cnt - 1 are contiguous in HBM; lane i of chunk
+// q moves bytes q KB + 16 i.  Source offsets past the last record are clamped
+// to its final 16 bytes (their LDS copies are never read).
 __device__ __forceinline__ void stage_records(double* dst, const double* factor, int64_t e0, int64_t ne) {
   const int cnt = (ne - e0) < SOLVE_EPW ? int(ne - e0) : SOLVE_EPW;
-  constexpr int H2 = REC / 2;
-  const double2* src = reinterpret_cast<const double2*>(factor + e0 * REC);
-  for (int p = threadIdx.x; p < cnt * H2; p += 64) {
-    const int tm = p / H2;
-    *reinterpret_cast<double2*>(dst + tm * RSTRIDE + 2 * (p - tm * H2)) = src[p];
+  const int nbytes = cnt * REC * 8;
+  const char* base = reinterpret_cast<const char*>(factor + e0 * REC);
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < STAGE_CHUNKS; ++q) {
+    if (q * 1024 < nbytes) {
+      int off = q * 1024 + 16 * lane;
+      off = off < nbytes - 16 ? off : nbytes - 16;
+      __builtin_amdgcn_global_load_lds(base + off, (__attribute__((address_space(3))) void*)(dst + 128 * q), 16, 0,
+                                       0);
+    }
   }
+  __builtin_amdgcn_s_waitcnt(0);   // all counters: the LDS copies have landed
 }
 
 __global__ __launch_bounds__(64) void k_rhs_k1(SimtArgs a) {
@@ -562,7 +589,7 @@ __global__ __launch_bounds__(64) void k_rhs_k1(SimtArgs a) {
   double* v = L.v[tau];
   v[t] = fi;
   __syncthreads();
-  const double* rec = L.rec + (live ? tau : 0) * RSTRIDE;
+  const double* rec = L.rec + (live ? tau : 0) * REC;
   // y_i = A_ii^{-1} f_i; t_b = f_b - E^T f_i
   double yi = 0.0, ta = fa, tb = fb;
 #pragma unroll
@@ -626,7 +653,7 @@ __global__ __launch_bounds__(64) void k_recover_k1(SimtArgs a) {
   }
   const double yi = a.y[es * N + t], ya = a.y[es * N + 12 + t], yb = a.y[es * N + 24 + t];
   __syncthreads();
-  const double* rec = L.rec + (live ? tau : 0) * RSTRIDE;
+  const double* rec = L.rec + (live ? tau : 0) * REC;
   // u_b = y_b - S^{-1} D lambda
   double ua = ya, ub = yb;
 #pragma unroll
