@@ -41,6 +41,8 @@ hyb::DeviceMaps device_maps(const hyb::Plan& P) {
   m.gauss_x = reinterpret_cast<const double*>(base + L.tab_x);
   m.face_selfslot = reinterpret_cast<const int32_t*>(base + L.face_selfslot);
   m.face_owner = reinterpret_cast<const int32_t*>(base + L.face_owner);
+  m.k1_geo = reinterpret_cast<const double*>(base + L.k1_geo);
+  m.k1_meta = base + L.k1_meta;
   return m;
 }
 
@@ -87,6 +89,7 @@ int dispatch_setup(int k, const hyb::SetupArgs& a, hipStream_t s) {
     case 0: return launch_setup<0, 16, 16>(a, s);
     case 1: return launch_setup<1, 64, 4>(a, s);
     case 2: return launch_setup<2, 256, 1>(a, s);
+    case 3: return launch_setup<3, 256, 1>(a, s);
     default: return HYB_E_ARG;
   }
 }
@@ -96,6 +99,7 @@ int dispatch_recover(int k, const hyb::RecoverArgs& a, hipStream_t s) {
     case 0: return launch_recover<0, 16, 16>(a, s);
     case 1: return launch_recover<1, 64, 4>(a, s);
     case 2: return launch_recover<2, 256, 1>(a, s);
+    case 3: return launch_recover<3, 256, 1>(a, s);
     default: return HYB_E_ARG;
   }
 }
@@ -148,7 +152,7 @@ hyb::k1::SimtArgs simt_args(const hyb::Plan& P) {
 
 // Add the neighbour terms of the same-face blocks of H and of r.
 int finalize_k1(const hyb::Plan& P, hipStream_t s, bool matrix, bool rhs) {
-  const int64_t tot = P.nfaces * ((matrix ? 16 : 0) + (rhs ? 4 : 0));
+  const int64_t tot = (matrix || rhs) ? P.nfaces * 4 : 0;
   if (tot == 0) return HYB_OK;
   const hyb::DeviceMaps m = device_maps(P);
   hyb::k1::FinalArgs f{};
@@ -160,7 +164,7 @@ int finalize_k1(const hyb::Plan& P, hipStream_t s, bool matrix, bool rhs) {
   f.r = rhs ? P.buf.r : nullptr;
   f.side = P.buf.work;
   int64_t blocks = (tot + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(hyb::k1::k_finalize_k1, dim3(unsigned(blocks)), dim3(256), 0, s, f);
   HYB_HIP(hipGetLastError());
   return HYB_OK;
@@ -283,6 +287,8 @@ int hyb_bind(hyb_plan_t* plan, const hyb_buffers* buf) {
     for (int64_t F = 0; F < P.nfaces; ++F) owner_elem[size_t(F)] = P.face_owner[size_t(2 * F)];
     put(L.face_owner, owner_elem.data(), 4 * owner_elem.size());
   }
+  put(L.k1_geo, P.k1_geo.data(), 8 * P.k1_geo.size());
+  put(L.k1_meta, P.k1_meta.data(), P.k1_meta.size());
   HYB_HIP(hipMemcpyAsync(buf->maps, host.data(), host.size(), hipMemcpyHostToDevice, s));
   if (P.m > 0) {
     HYB_HIP(hipMemcpyAsync(buf->row_ptr, P.row_ptr.data(), 8 * P.row_ptr.size(), hipMemcpyHostToDevice, s));

@@ -128,6 +128,28 @@ struct Elem {
     for (int fc = 0; fc < 6; ++fc)
       if (mp.elem_face[e * 6 + fc] < 0) ess |= 1u << fc;
   }
+  // from the edge vectors J[r][c] (row-major) and the element's data
+  __device__ __forceinline__ void from(const double* Jr, double alpha, double beta, const double* f, unsigned ess_) {
+    double J[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) J[r][c] = Jr[3 * r + c];
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    const double id = 1.0 / det;
+    auto gg = [&](int d, int c) { return (J[0][d] * J[0][c] + J[1][d] * J[1][c] + J[2][d] * J[2][c]) * id; };
+    g00 = gg(0, 0); g01 = gg(0, 1); g02 = gg(0, 2); g11 = gg(1, 1); g12 = gg(1, 2); g22 = gg(2, 2);
+    if (f) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) jtf[d] = J[0][d] * f[0] + J[1][d] * f[1] + J[2][d] * f[2];
+    } else {
+      jtf[0] = jtf[1] = jtf[2] = 0.0;
+    }
+    al = alpha;
+    bd = beta / det;
+    ess = ess_;
+  }
   __device__ __forceinline__ bool ess_dof(int i) const { return i >= 12 && ((ess >> ((i - 12) >> 2)) & 1u); }
   // alpha G[c][0..2] for a lane-varying component c, blended with exact 0/1
   // weights (a select chain over an array would become scratch memory)
@@ -178,23 +200,46 @@ __device__ __forceinline__ double pow2_scale(double d) {
 // doubles are 4 and 8 dwords apart modulo 32 banks.
 constexpr int SSTRIDE = 370;   // staging of up to 366 outputs per element
 
-// Per-element face data for the H scatter.
-struct HMeta {
-  int64_t rb[6];     // first CSR entry of the face's row block
-  int32_t fid[6];    // face index, -1 on the boundary
-  int32_t pi[6];     // frame code
-  int32_t ns[6];     // column blocks per row of the face
-  int32_t own[6];    // this element owns the face
-  int32_t slot[36];  // slot of face fb in the rows of face fa
-};
-
 constexpr int SETUP_WAVES = 4;   // waves per setup workgroup (16 elements)
 
 // Per-wave LDS of the setup kernel.
+// Per-element inputs of a wave's 4 elements, as one 1 KB block of dwords:
+// [0, 72) edge vectors J (18 per element), [72, 216) K1Meta (36 per element),
+// [216, 224) alpha, [224, 232) beta, [232, 256) f (6 per element).
+constexpr int IN_GEO = 0, IN_META = 72, IN_ALPHA = 216, IN_BETA = 224, IN_F = 232, IN_DWORDS = 256;
+
 struct SetupWaveLds {
-  double stage[SETUP_EPW][SSTRIDE];   // outputs on their way to HBM
-  HMeta meta[SETUP_EPW];
+  double stage[SETUP_EPW][SSTRIDE];      // outputs on their way to HBM
+  alignas(16) uint32_t in[IN_DWORDS];    // inputs of the wave's elements
 };
+
+// Direct-to-LDS copy of the inputs of elements e0 .. e0 + 3 (indices past the
+// last element are clamped to it).  Completion is awaited with vmcnt.
+__device__ __forceinline__ void load_inputs(uint32_t* in, const DeviceMaps& mp, const double* alpha,
+                                            const double* beta, const double* f, int64_t e0, int64_t ne, int lane) {
+#pragma unroll
+  for (int q = 0; q < IN_DWORDS / 64; ++q) {
+    const int w = 64 * q + lane;
+    const uint32_t* base;
+    int per, rel;
+    if (w < IN_META) {
+      base = reinterpret_cast<const uint32_t*>(mp.k1_geo), per = 18, rel = w - IN_GEO;
+    } else if (w < IN_ALPHA) {
+      base = reinterpret_cast<const uint32_t*>(mp.k1_meta), per = 36, rel = w - IN_META;
+    } else if (w < IN_BETA) {
+      base = reinterpret_cast<const uint32_t*>(alpha), per = 2, rel = w - IN_ALPHA;
+    } else if (w < IN_F) {
+      base = reinterpret_cast<const uint32_t*>(beta), per = 2, rel = w - IN_BETA;
+    } else {
+      base = reinterpret_cast<const uint32_t*>(f ? f : alpha), per = f ? 6 : 2, rel = f ? w - IN_F : 0;
+    }
+    const int k = rel / per;
+    int64_t el = e0 + k;
+    el = el < ne ? el : ne - 1;
+    __builtin_amdgcn_global_load_lds(base + el * per + (rel - k * per), (__attribute__((address_space(3))) void*)(in + 64 * q),
+                                     4, 0, 0);
+  }
+}
 struct alignas(16) SetupLds {
   double2 td[N * N];   // reference integrals {T_ij, Dv_ij}, shared by the workgroup
   double sr[N];
@@ -332,32 +377,27 @@ __global__ __launch_bounds__(64 * SETUP_WAVES) __attribute__((amdgpu_waves_per_e
   const double* gb = (rhs && a.g) ? a.g + es * NB : nullptr;
   SetupWaveLds& W = L.w[wave];
 
-  // reference integrals into LDS (the table and sr are contiguous)
+  // inputs of the wave's elements and the reference integrals into LDS
+  load_inputs(W.in, mp, a.alpha, a.beta, rhs ? a.f : nullptr, e0 < a.ne ? e0 : a.ne - 1, a.ne, lane);
   {
     const double2* src = reinterpret_cast<const double2*>(mp.tab_ref);
     double2* dst = L.td;
     for (int p = threadIdx.x; p < N * N + N / 2; p += 64 * SETUP_WAVES) dst[p] = src[p];
   }
-
+  __builtin_amdgcn_s_waitcnt(0);   // the direct-to-LDS copies have landed
+  __syncthreads();
+  const K1Meta& hm = *reinterpret_cast<const K1Meta*>(&W.in[IN_META + 36 * tau]);
   Elem el;
-  el.load(mp, es, a.alpha, a.beta, rhs ? a.f : nullptr, true);
-  if (live && t == 0 && !(el.det > 0.0)) report_error(a.status, HYB_E_JACOBIAN, e);
-
-  // face data of the element for the H scatter (used at the end)
-  if (t16 < 6) {
-    HMeta& hm = W.meta[tau];
-    const int F = mp.elem_face[es * 6 + t16];
-    hm.fid[t16] = F;
-    hm.pi[t16] = mp.elem_pi[es * 8 + t16];
-    hm.rb[t16] = F >= 0 ? mp.face_rowbase[F] : 0;
-    hm.ns[t16] = F >= 0 ? mp.face_nslots[F] : 0;
-    hm.own[t16] = F >= 0 ? int(mp.face_owner[F] == es) : 0;
-  }
-  if (t16 < 12) {
+  {
+    const double* in = reinterpret_cast<const double*>(W.in);
+    unsigned ess = 0;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) W.meta[tau].slot[t16 + 12 * q] = mp.elem_slot[es * 36 + t16 + 12 * q];
+    for (int fc = 0; fc < 6; ++fc)
+      if (hm.fid[fc] < 0) ess |= 1u << fc;
+    el.from(in + (IN_GEO / 2) + 9 * tau, in[IN_ALPHA / 2 + tau], in[IN_BETA / 2 + tau],
+            rhs ? in + IN_F / 2 + 3 * tau : nullptr, ess);
   }
-  __syncthreads();   // table in LDS
+  if (live && t == 0 && !(el.det > 0.0)) report_error(a.status, HYB_E_JACOBIAN, e);
 
   const double2* TD = L.td;
   const double* sr = L.sr;
@@ -454,13 +494,12 @@ __global__ __launch_bounds__(64 * SETUP_WAVES) __attribute__((amdgpu_waves_per_e
     if (!live || !rhs) return;
     const double z = S[36] * s_a;
     a.y[e * N + 12 + arow] = z;
-    const HMeta& hm = W.meta[tau];
     const int fa = arow >> 2;
     const int Fa = hm.fid[fa];
     if (Fa < 0) return;
     const int ja = own_idx(hm.pi[fa], arow & 3);
     const double v = (fa & 1) ? z : -z;
-    if (hm.own[fa]) a.r[int64_t(Fa) * 4 + ja] = v;
+    if ((hm.own >> fa) & 1) a.r[int64_t(Fa) * 4 + ja] = v;
     else side[nf * 16 + int64_t(Fa) * 4 + ja] = v;
   };
   face_out(A, t, sa);
@@ -475,7 +514,7 @@ __global__ __launch_bounds__(64 * SETUP_WAVES) __attribute__((amdgpu_waves_per_e
     const int tm = c / 288, rem = c - tm * 288;
     const int arow = rem / 12, fb = (rem >> 1) % 6, half = rem & 1;
     if (e0 + tm >= a.ne) continue;
-    const HMeta& hq = W.meta[tm];
+    const K1Meta& hq = *reinterpret_cast<const K1Meta*>(&W.in[IN_META + 36 * tm]);
     const int fa = arow >> 2;
     const int Fa = hq.fid[fa], Fb = hq.fid[fb];
     if (Fa < 0 || Fb < 0) continue;
@@ -499,7 +538,7 @@ __global__ __launch_bounds__(64 * SETUP_WAVES) __attribute__((amdgpu_waves_per_e
     const double* st = W.stage[tm];
     const double2 v = make_double2(sg * st[spk(arow, 4 * fb + i2[0])], sg * st[spk(arow, 4 * fb + i2[1])]);
     double* dst;
-    if (fb == fa && !hq.own[fa]) dst = side + int64_t(Fa) * 16 + ja * 4 + 2 * half;
+    if (fb == fa && !((hq.own >> fa) & 1)) dst = side + int64_t(Fa) * 16 + ja * 4 + 2 * half;
     else dst = a.Hval + hq.rb[fa] + int64_t(ja) * hq.ns[fa] * 4 + int64_t(hq.slot[fa * 6 + fb]) * 4 + 2 * half;
     *reinterpret_cast<double2*>(dst) = v;
   }
@@ -507,18 +546,27 @@ __global__ __launch_bounds__(64 * SETUP_WAVES) __attribute__((amdgpu_waves_per_e
 
 // Add the neighbours' terms of the same-face blocks of H (16 per face, owner
 // frame, row-major) and of r (4 per face) from the side buffer.
-__global__ void k_finalize_k1(FinalArgs a) {
-  const int64_t nh = a.Hval ? a.nfaces * 16 : 0;
-  const int64_t tot = nh + (a.r ? a.nfaces * 4 : 0);
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < tot; i += int64_t(gridDim.x) * blockDim.x) {
-    if (i < nh) {
-      const int64_t F = i >> 4;
-      const int q = int(i & 15), ja = q >> 2, jb = q & 3;
-      a.Hval[a.rowbase[F] + int64_t(ja) * a.nslots[F] * 4 + int64_t(a.selfslot[F]) * 4 + jb] += a.side[i];
-    } else {
-      const int64_t j = i - nh;
-      a.r[j] += a.side[a.nfaces * 16 + j];
+// One thread per face row (4 per face): its 4-entry same-face segment of H
+// (two 16-byte halves) and its entry of r.
+__global__ __launch_bounds__(256) void k_finalize_k1(FinalArgs a) {
+  const int64_t nrows = a.nfaces * 4;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nrows; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t F = i >> 2;
+    const int ja = int(i & 3);
+    if (a.Hval) {
+      double2* h = reinterpret_cast<double2*>(a.Hval + a.rowbase[F] + int64_t(ja) * a.nslots[F] * 4 +
+                                              int64_t(a.selfslot[F]) * 4);
+      const double2* sd = reinterpret_cast<const double2*>(a.side + 4 * i);
+      double2 h0 = h[0], h1 = h[1];
+      const double2 s0 = sd[0], s1 = sd[1];
+      h0.x += s0.x;
+      h0.y += s0.y;
+      h1.x += s1.x;
+      h1.y += s1.y;
+      h[0] = h0;
+      h[1] = h1;
     }
+    if (a.r) a.r[i] += a.side[a.nfaces * 16 + i];
   }
 }
 
@@ -543,29 +591,32 @@ struct SimtArgs {
 };
 
 // Records of the SOLVE_EPW elements of a wave, copied HBM -> LDS by the
-// direct-to-LDS loads of gfx950 (1 KB per instruction, no registers).
-constexpr int STAGE_CHUNKS = (SOLVE_EPW * REC * 8 + 1023) / 1024;
+// direct-to-LDS loads of gfx950 (1 KB per instruction, no registers), each
+// into a 6 KB + 16 B slot: the slots are 4 dwords apart modulo the LDS banks
+// and hold the overhang of the last, partial chunk of a record.
+constexpr int REC_CHUNKS = (REC * 8 + 1023) / 1024;   // 6
+constexpr int RSLOT = REC_CHUNKS * 128 + 2;           // doubles per slot
 
 struct alignas(16) SolveLds {
-  double rec[STAGE_CHUNKS * 128];
+  double rec[SOLVE_EPW * RSLOT];
   double v[SOLVE_EPW + 1][49];   // per-team exchange vectors
 };
 
-// Element records e0 .. e0 + cnt - 1 are contiguous in HBM; lane i of chunk
-// q moves bytes q KB + 16 i.  Source offsets past the last record are clamped
-// to its final 16 bytes (their LDS copies are never read).
+// Record of element min(e0 + k, ne - 1) into slot k; lane i of chunk q moves
+// bytes q KB + 16 i of the record, clamped to its last 16 bytes.
 __device__ __forceinline__ void stage_records(double* dst, const double* factor, int64_t e0, int64_t ne) {
-  const int cnt = (ne - e0) < SOLVE_EPW ? int(ne - e0) : SOLVE_EPW;
-  const int nbytes = cnt * REC * 8;
-  const char* base = reinterpret_cast<const char*>(factor + e0 * REC);
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int q = 0; q < STAGE_CHUNKS; ++q) {
-    if (q * 1024 < nbytes) {
+  for (int k = 0; k < SOLVE_EPW; ++k) {
+    int64_t el = e0 + k;
+    el = el < ne ? el : ne - 1;
+    const char* base = reinterpret_cast<const char*>(factor + el * REC);
+#pragma unroll
+    for (int q = 0; q < REC_CHUNKS; ++q) {
       int off = q * 1024 + 16 * lane;
-      off = off < nbytes - 16 ? off : nbytes - 16;
-      __builtin_amdgcn_global_load_lds(base + off, (__attribute__((address_space(3))) void*)(dst + 128 * q), 16, 0,
-                                       0);
+      off = off < REC * 8 - 16 ? off : REC * 8 - 16;
+      __builtin_amdgcn_global_load_lds(base + off,
+                                       (__attribute__((address_space(3))) void*)(dst + k * RSLOT + 128 * q), 16, 0, 0);
     }
   }
   __builtin_amdgcn_s_waitcnt(0);   // all counters: the LDS copies have landed
@@ -589,7 +640,7 @@ __global__ __launch_bounds__(64) void k_rhs_k1(SimtArgs a) {
   double* v = L.v[tau];
   v[t] = fi;
   __syncthreads();
-  const double* rec = L.rec + (live ? tau : 0) * REC;
+  const double* rec = L.rec + (live ? tau : 0) * RSLOT;
   // y_i = A_ii^{-1} f_i; t_b = f_b - E^T f_i
   double yi = 0.0, ta = fa, tb = fb;
 #pragma unroll
@@ -653,7 +704,7 @@ __global__ __launch_bounds__(64) void k_recover_k1(SimtArgs a) {
   }
   const double yi = a.y[es * N + t], ya = a.y[es * N + 12 + t], yb = a.y[es * N + 24 + t];
   __syncthreads();
-  const double* rec = L.rec + (live ? tau : 0) * REC;
+  const double* rec = L.rec + (live ? tau : 0) * RSLOT;
   // u_b = y_b - S^{-1} D lambda
   double ua = ya, ub = yb;
 #pragma unroll

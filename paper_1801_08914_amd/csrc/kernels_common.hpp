@@ -59,6 +59,8 @@ struct DeviceMaps {
   const double* gauss_x;       // q1 points on [0,1]
   const int32_t* face_selfslot;
   const int32_t* face_owner;   // owner element of every interior face
+  const double* k1_geo;        // RT_1 affine: per-element edge vectors (9)
+  const uint8_t* k1_meta;      // RT_1 affine: per-element face data (144 B)
 };
 
 // Sticky device error: the first (code, element) pair wins.

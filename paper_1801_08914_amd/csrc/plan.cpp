@@ -3,6 +3,8 @@
 // built and inspected on a machine without a GPU.
 #include "plan.hpp"
 
+#include <cstring>
+
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -379,6 +381,35 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
   L.tab_x = off;        off = align256(off + sizeof(double) * P.tab_x.size());
   L.face_selfslot = off; off = align256(off + sizeof(int32_t) * size_t(nf));
   L.face_owner = off;   off = align256(off + sizeof(int32_t) * size_t(nf));
+  // per-element inputs of the RT_1 affine kernels (mesh data only)
+  P.k1_geo.clear();
+  P.k1_meta.clear();
+  if (k == 1 && P.all_affine) {
+    P.k1_geo.resize(size_t(9 * ne));
+    P.k1_meta.assign(size_t(K1Meta::kBytes) * size_t(ne), 0);
+    for (int64_t e = 0; e < ne; ++e) {
+      const int32_t* ev = &P.e2v[size_t(8 * e)];
+      const int vs[3] = {ev[1], ev[2], ev[4]};
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          P.k1_geo[size_t(9 * e + 3 * r + c)] = P.xyz[size_t(3 * vs[c] + r)] - P.xyz[size_t(3 * ev[0] + r)];
+      K1Meta m{};
+      for (int f = 0; f < 6; ++f) {
+        const int32_t F = P.elem_face[size_t(6 * e + f)];
+        m.fid[f] = F;
+        m.pi[f] = P.elem_pi[size_t(8 * e + f)];
+        if (F >= 0) {
+          m.rb[f] = P.face_rowbase[size_t(F)];
+          m.ns[f] = P.face_nslots[size_t(F)];
+          if (P.face_owner[size_t(2 * F)] == e) m.own |= uint8_t(1u << f);
+        }
+      }
+      for (int q = 0; q < 36; ++q) m.slot[q] = P.elem_slot[size_t(36 * e + q)];
+      std::memcpy(&P.k1_meta[size_t(K1Meta::kBytes) * size_t(e)], &m, K1Meta::kBytes);
+    }
+  }
+  L.k1_geo = off;       off = align256(off + sizeof(double) * P.k1_geo.size());
+  L.k1_meta = off;      off = align256(off + P.k1_meta.size());
   L.total = off;
   P.factor_len = int64_t(o.n) * (o.n + 1) / 2;
   return HYB_OK;

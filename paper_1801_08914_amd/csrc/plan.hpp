@@ -26,11 +26,25 @@ struct Order {
   explicit Order(int k_ = 0);
 };
 
+// Face data of one element for the RT_1 scatter into H (copied to the
+// device as raw bytes).
+struct K1Meta {
+  static constexpr int kBytes = 144;
+  int64_t rb[6];     // first CSR entry of the face's row block
+  int32_t fid[6];    // face index, -1 on the boundary
+  int32_t ns[6];     // column blocks per row of the face
+  uint8_t slot[36];  // slot of face fb in the rows of face fa
+  uint8_t pi[6];     // frame code
+  uint8_t own;       // bit f: this element owns face f
+  uint8_t pad[5];
+};
+static_assert(sizeof(K1Meta) == K1Meta::kBytes, "K1Meta layout");
+
 // Byte offsets of every array inside the device "maps" buffer.
 struct MapLayout {
   size_t e2v = 0, xyz = 0, elem_face = 0, elem_pi = 0, elem_slot = 0,
          face_rowbase = 0, face_nslots = 0, tab_s = 0, tab_d = 0, tab_w = 0,
-         tab_ref = 0, tab_x = 0, face_selfslot = 0, face_owner = 0, total = 0;
+         tab_ref = 0, tab_x = 0, face_selfslot = 0, face_owner = 0, k1_geo = 0, k1_meta = 0, total = 0;
 };
 
 struct Plan {
@@ -60,6 +74,11 @@ struct Plan {
   std::vector<double> tab_w;        // Q: weights
   std::vector<double> tab_ref;      // affine reference integrals (see plan.cpp)
   std::vector<double> tab_x;        // q1 Gauss points on [0,1]
+  // RT_1 affine kernels: per-element edge vectors J (9 doubles, row-major,
+  // J[r][c] = x_{v_c}[r] - x_0[r] for vertices v = 1, 2, 4) and the element's
+  // face data for the scatter into H (K1Meta, 144 bytes)
+  std::vector<double> k1_geo;
+  std::vector<uint8_t> k1_meta;
   MapLayout lay;
   int64_t factor_len = 0;
   // device state

@@ -40,33 +40,41 @@ __device__ __forceinline__ int gidx(int d, int e) {
   return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
 }
 
+// Per-element LDS layout.  From k = 3 on the packed element matrix (231 KB)
+// does not fit in LDS: it is then assembled and factored in place in its
+// factor record in HBM (L2-resident while the element is processed), and the
+// face block is inverted in place.
 template <int K, int TEAM, int EPB>
 struct GenericLayout {
   using R = RT<K>;
+  static constexpr bool kGlobal = K >= 3;
   static constexpr int QD = 10;  // per-qp: 6 weighted metric terms, div weight, 3 load weights
-  static constexpr int per = R::npk + R::nbpk + R::Q * QD + R::n + 24 + R::nb;
+  static constexpr int per = (kGlobal ? 0 : R::npk + R::nbpk) + R::Q * QD + R::n + 24 + R::nb;
 };
 
 // Local assembly (Gauss quadrature), essential-face masking, packed
 // Cholesky in i-first order, inversion of the face block, H_T scatter, and
 // the right-hand side y = L^{-1} f_hat, r_T = D L_bb^{-T} y_b.
 template <int K, int TEAM, int EPB>
-__global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
+__device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* smem, int64_t blk) {
   using R = RT<K>;
   using Lay = GenericLayout<K, TEAM, EPB>;
   constexpr int n = R::n, ni = R::ni, nb = R::nb, K1 = R::K1, K2 = R::K2, Q = R::Q, q1 = R::q1;
   constexpr int QD = Lay::QD;
-  __shared__ double smem[EPB * Lay::per];
   const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
-  const int64_t e = int64_t(blockIdx.x) * EPB + team;
+  const int64_t e = blk * EPB + team;
   const bool live = e < a.ne;
   const int64_t es = live ? e : 0;  // safe index for loads of padding teams
-  double* A = smem + team * Lay::per;
-  double* Li = A + R::npk;
-  double* qd = Li + R::nbpk;
+  double* base = smem + team * Lay::per;
+  double* A = Lay::kGlobal ? a.factor + es * R::npk : base;
+  double* Li = Lay::kGlobal ? nullptr : base + R::npk;
+  double* qd = Lay::kGlobal ? base : base + R::npk + R::nbpk;
   double* fh = qd + Q * QD;
   double* xe = fh + n;
   double* tb = xe + 24;
+  // packed inverse of the face block: its own LDS array, or (global matrix)
+  // the face block of A, inverted in place
+  auto LI = [&](int i, int j) -> double& { return Lay::kGlobal ? A[pk(ni + i, ni + j)] : Li[pk(i, j)]; };
   const DeviceMaps& mp = a.mp;
 
   int fid[6], pic[6];
@@ -128,16 +136,23 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
   }
   __syncthreads();
 
-  if (need_matrix) {
+  // entry (i, j) of M_T by Gauss quadrature
+  auto mij = [&](int i, int j) {
+    const int gi = gidx(R::comp(i), R::comp(j));
+    double s = 0.0;
+    for (int q = 0; q < Q; ++q)
+      s += qd[q * QD + gi] * mp.tab_s[q * n + i] * mp.tab_s[q * n + j] +
+           qd[q * QD + 6] * mp.tab_d[q * n + i] * mp.tab_d[q * n + j];
+    return s;
+  };
+  // (an HBM-resident matrix is the stored factor: a right-hand side alone
+  // must not overwrite it, and computes the entries it needs directly)
+  const bool store_matrix = need_matrix && (!Lay::kGlobal || (a.mode & MODE_MATRIX));
+  if (store_matrix) {
     for (int p = lane; p < R::npk; p += TEAM) {
       int i, j;
       unpk(p, i, j);
-      const int gi = gidx(R::comp(i), R::comp(j));
-      double s = 0.0;
-      for (int q = 0; q < Q; ++q)
-        s += qd[q * QD + gi] * mp.tab_s[q * n + i] * mp.tab_s[q * n + j] +
-             qd[q * QD + 6] * mp.tab_d[q * n + i] * mp.tab_d[q * n + j];
-      A[p] = s;
+      A[p] = mij(i, j);
     }
     __syncthreads();
   }
@@ -151,7 +166,9 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
       } else if (a.g) {
         // f_r -= M_re g_e (unmasked matrix)
         for (int j = ni; j < n; ++j)
-          if (is_ess(j)) s -= A[i > j ? pk(i, j) : pk(j, i)] * a.g[es * nb + (j - ni)];
+          if (is_ess(j))
+            s -= (store_matrix ? A[i > j ? pk(i, j) : pk(j, i)] : (i > j ? mij(i, j) : mij(j, i))) *
+                 a.g[es * nb + (j - ni)];
       }
       fh[i] = s;
     }
@@ -190,13 +207,33 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
       if (lane == 0) A[pk(c, c)] = sq;
     }
     __syncthreads();
-    // Inverse of the face block L_bb, one column per thread.
-    for (int col = lane; col < nb; col += TEAM) {
-      Li[pk(col, col)] = 1.0 / A[pk(ni + col, ni + col)];
-      for (int i = col + 1; i < nb; ++i) {
-        double s = 0.0;
-        for (int c = col; c < i; ++c) s += A[pk(ni + i, ni + c)] * Li[pk(c, col)];
-        Li[pk(i, col)] = -s / A[pk(ni + i, ni + i)];
+    if constexpr (!Lay::kGlobal) {
+      // Inverse of the face block L_bb, one column per thread.
+      for (int col = lane; col < nb; col += TEAM) {
+        Li[pk(col, col)] = 1.0 / A[pk(ni + col, ni + col)];
+        for (int i = col + 1; i < nb; ++i) {
+          double s = 0.0;
+          for (int c = col; c < i; ++c) s += A[pk(ni + i, ni + c)] * Li[pk(c, col)];
+          Li[pk(i, col)] = -s / A[pk(ni + i, ni + i)];
+        }
+      }
+    } else {
+      // In place, columns right to left: X_ij = -(sum_{c=j+1..i} X_ic L_cj) / L_jj
+      // reads the original column j and the finished columns c > j.
+      for (int j = nb - 1; j >= 0; --j) {
+        const double ljj = A[pk(ni + j, ni + j)];
+        double xs[(nb + TEAM - 1) / TEAM];
+        int q = 0;
+        for (int i = j + 1 + lane; i < nb; i += TEAM, ++q) {
+          double s = 0.0;
+          for (int c = j + 1; c <= i; ++c) s += A[pk(ni + i, ni + c)] * A[pk(ni + c, ni + j)];
+          xs[q] = -s / ljj;
+        }
+        __syncthreads();
+        q = 0;
+        for (int i = j + 1 + lane; i < nb; i += TEAM, ++q) A[pk(ni + i, ni + j)] = xs[q];
+        if (lane == 0) A[pk(ni + j, ni + j)] = 1.0 / ljj;
+        __syncthreads();
       }
     }
     __syncthreads();
@@ -209,7 +246,7 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
         const int fa = aa / K2, fb = bb / K2;
         if (fid[fa] < 0 || fid[fb] < 0) continue;
         double h = 0.0;
-        for (int c = aa; c < nb; ++c) h += Li[pk(c, aa)] * Li[pk(c, bb)];
+        for (int c = aa; c < nb; ++c) h += LI(c, aa) * LI(c, bb);
         const double v = ((fa ^ fb) & 1) ? -h : h;
         int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
         frame_map(pic[fa], K, a0, a1);
@@ -230,14 +267,16 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
       }
     }
   } else if (a.mode & MODE_RHS) {
-    // rhs only: bring the stored factor back (face block holds L_bb^{-1})
-    for (int p = lane; p < R::npk; p += TEAM) {
-      int i, j;
-      unpk(p, i, j);
-      const double v = a.factor[es * R::npk + p];
-      if (i >= ni && j >= ni) Li[pk(i - ni, j - ni)] = v; else A[p] = v;
+    if constexpr (!Lay::kGlobal) {
+      // rhs only: bring the stored factor back (face block holds L_bb^{-1})
+      for (int p = lane; p < R::npk; p += TEAM) {
+        int i, j;
+        unpk(p, i, j);
+        const double v = a.factor[es * R::npk + p];
+        if (i >= ni && j >= ni) Li[pk(i - ni, j - ni)] = v; else A[p] = v;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   if (a.mode & MODE_RHS) {
@@ -258,7 +297,7 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
     __syncthreads();
     for (int b = lane; b < nb; b += TEAM) {
       double s = 0.0;
-      for (int c = 0; c <= b; ++c) s += Li[pk(b, c)] * tb[c];
+      for (int c = 0; c <= b; ++c) s += LI(b, c) * tb[c];
       fh[ni + b] = s;
     }
     __syncthreads();
@@ -269,7 +308,7 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
         const int fb = b / K2;
         if (fid[fb] < 0) continue;
         double s = 0.0;
-        for (int c = b; c < nb; ++c) s += Li[pk(c, b)] * fh[ni + c];
+        for (int c = b; c < nb; ++c) s += LI(c, b) * fh[ni + c];
         if (!(fb & 1)) s = -s;
         int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
         frame_map(pic[fb], K, b0, b1);
@@ -278,24 +317,34 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
     }
   }
 
-  if ((a.mode & MODE_MATRIX) && live) {
-    for (int p = lane; p < R::npk; p += TEAM) {
-      int i, j;
-      unpk(p, i, j);
-      a.factor[e * R::npk + p] = (i >= ni && j >= ni) ? Li[pk(i - ni, j - ni)] : A[p];
+  if constexpr (!Lay::kGlobal) {
+    if ((a.mode & MODE_MATRIX) && live) {
+      for (int p = lane; p < R::npk; p += TEAM) {
+        int i, j;
+        unpk(p, i, j);
+        a.factor[e * R::npk + p] = (i >= ni && j >= ni) ? Li[pk(i - ni, j - ni)] : A[p];
+      }
     }
   }
 }
 
-// u_T = L^{-T} (y - [0; L_bb^{-1} D lambda_b]) from the stored factor.
 template <int K, int TEAM, int EPB>
-__global__ __launch_bounds__(TEAM* EPB) void k_recover_generic(RecoverArgs a) {
+__global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
+  __shared__ double smem[EPB * GenericLayout<K, TEAM, EPB>::per];
+  setup_generic_body<K, TEAM, EPB>(a, smem, blockIdx.x);
+}
+
+// u_T = L^{-T} (y - [0; L_bb^{-1} D lambda_b]) from the stored factor.
+template <int K>
+constexpr int recover_per() { return 2 * RT<K>::n + RT<K>::nb; }
+
+template <int K, int TEAM, int EPB>
+__device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, double* smem, int64_t blk) {
   using R = RT<K>;
   constexpr int n = R::n, ni = R::ni, nb = R::nb, K1 = R::K1, K2 = R::K2;
-  constexpr int per = 2 * n + nb;
-  __shared__ double smem[EPB * per];
+  constexpr int per = recover_per<K>();
   const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
-  const int64_t e = int64_t(blockIdx.x) * EPB + team;
+  const int64_t e = blk * EPB + team;
   const bool live = e < a.ne;
   const int64_t es = live ? e : 0;
   double* yv = smem + team * per;   // y, then v / u
@@ -344,6 +393,12 @@ __global__ __launch_bounds__(TEAM* EPB) void k_recover_generic(RecoverArgs a) {
   __syncthreads();
   if (live)
     for (int i = lane; i < n; i += TEAM) a.u[e * n + i] = i < ni ? zb[i] : tl[i - ni];
+}
+
+template <int K, int TEAM, int EPB>
+__global__ __launch_bounds__(TEAM* EPB) void k_recover_generic(RecoverArgs a) {
+  __shared__ double smem[EPB * recover_per<K>()];
+  recover_generic_body<K, TEAM, EPB>(a, smem, blockIdx.x);
 }
 
 }  // namespace hyb

@@ -34,11 +34,13 @@ def _mesh_problem(k, N, jitter, seed, rotate=False):
 
 
 # (k, N, jitter, rotated frames); unjittered RT_1 meshes take the affine
-# RT_1 kernels, the others the generic ones
+# RT_1 kernels, the others the generic ones (RT_3: element matrix factored in
+# place in its HBM record)
 SMALL = [
     (0, 4, 0.0, False), (0, 5, 0.2, True),
     (1, 3, 0.0, False), (1, 4, 0.0, True), (1, 4, 0.2, True), (1, 5, 0.2, False),
     (2, 2, 0.2, True), (2, 3, 0.2, False),
+    (3, 2, 0.2, True), (3, 3, 0.0, False),
 ]
 
 
@@ -106,7 +108,7 @@ def test_c1_end_to_end():
     assert rel_inf(uref, u) <= 1e-11
 
 
-@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_rhs_reuses_factors(k):
     """A second load through hyb_rhs on the same factors equals a fresh setup."""
     torch = require_gpu()
@@ -121,7 +123,7 @@ def test_rhs_reuses_factors(k):
     assert norm_rel(rl, plan.r().cpu().numpy()) <= accuracy_bound(norm_rel(rl, ref.r))
 
 
-@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_constant_flux_with_boundary_data(k):
     """Essential normal flux g on the boundary: the GPU reproduces the
     interpolant of a constant flux on an affine mesh (and the oracle does)."""
@@ -147,7 +149,7 @@ def test_constant_flux_with_boundary_data(k):
     assert rel_inf(exact, u) <= 1e-10, info
 
 
-@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_setup_deterministic(k):
     """Two setups give bitwise identical H and r (at most two commutative
     terms per entry)."""
