@@ -219,6 +219,65 @@ int hyb_timing_read(hyb_plan_t* plan, double* ms_setup, int* n_setup, double* ms
 /* Free the plan's host state (device buffers stay with the caller). */
 void hyb_destroy(hyb_plan_t* plan);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Batches of independent problems of mixed order and mesh (the uneven batch
+ * of many small hybridization problems; each problem is a bound plan).  The
+ * setup of every element of every problem runs in ONE persistent launch (after
+ * one launch that clears the same-face blocks of every H), the recovery in
+ * another; work items (problem, run of element blocks) are sorted by cost and
+ * dealt round-robin to a grid of blocks_per_cu x (compute units) workgroups.
+ * Every order uses the generic element routines (Gauss quadrature, packed
+ * Cholesky, inverse of the face block), so a batch sets its plans to that
+ * record layout; H, r, y and u of each problem equal those of the plan's own
+ * calls.  With graphs enabled the launch sequences are captured into hipGraphs
+ * on the batch's own stream (ordered after and before the plans' stream by
+ * events) and replayed; descriptors are device copies, so new coefficient
+ * values written into the same buffers need no re-capture.
+ * The batch allocates a few small device arrays itself (descriptors, work
+ * list); the plans' buffers stay caller-owned and must outlive the batch.
+ */
+typedef struct hyb_batch hyb_batch_t;
+
+typedef struct {
+  int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu x CUs (0: 2) */
+  int32_t items_per_block;  /* element blocks per work item (0: 1) */
+} hyb_batch_tiles;
+
+/* plans: count bound plans (the batch keeps pointers, it does not own them),
+ * launched on plans[0]'s stream.  Errors: HYB_E_ARG, HYB_E_STATE (unbound),
+ * HYB_E_NOMEM, HYB_E_HIP. */
+int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out);
+
+/* Device inputs of problem p: alpha, beta (ne), f (ne x 3, NULL: matrix
+ * only), g (boundary data, read with f, NULL = 0), lambda (m) and u (ne x n)
+ * for the recovery (may be NULL until hyb_batch_recover). */
+int hyb_batch_set(hyb_batch_t* b, int32_t p, const double* alpha, const double* beta, const double* f,
+                  const double* g, const double* lambda, double* u);
+
+/* Setup (as hyb_setup of every plan) / recovery (as hyb_recover) of every
+ * problem.  Errors: HYB_E_STATE (inputs missing), HYB_E_HIP; element errors
+ * are recorded in each plan's status. */
+int hyb_batch_setup(hyb_batch_t* b);
+int hyb_batch_recover(hyb_batch_t* b);
+
+/* Work-list tiles (HYB_E_ARG outside 0..64 / 0..1024), and the tiles in use. */
+int hyb_batch_set_tiles(hyb_batch_t* b, const hyb_batch_tiles* tiles);
+int hyb_batch_get_tiles(const hyb_batch_t* b, hyb_batch_tiles* tiles);
+
+/* Capture and replay the launch sequences as hipGraphs (1) or launch
+ * directly (0). */
+int hyb_batch_graph(hyb_batch_t* b, int enable);
+
+/* Autotuner: times reps setup + recovery passes for every candidate tile
+ * pair (blocks_per_cu in {1,2,4,8} x items_per_block in {1,2,4,8}) on the
+ * batch's own inputs (HIP events), keeps the fastest and returns it in best
+ * (may be NULL).  Needs every input of hyb_batch_set; overwrites the
+ * outputs. */
+int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best);
+
+void hyb_batch_destroy(hyb_batch_t* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ import numpy as np
 
 from . import _abi
 
-__all__ = ["Plan", "HybError", "load_library", "LIB_PATH"]
+__all__ = ["Plan", "Batch", "HybError", "load_library", "LIB_PATH"]
 
 LIB_PATH = _abi.LIB_PATH
 HybError = _abi.HybError
@@ -180,3 +180,74 @@ class Plan:
     def y_raw(self):
         """The cached L^{-1} f_hat buffer in the library's internal layout."""
         return self.bufs["y"]
+
+
+class Batch:
+    """Independent problems of mixed order and mesh (bound Plans): setup and
+    recovery of all of them in one persistent launch each, optionally
+    replayed as hipGraphs, with tiles from the library's autotuner."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        lib = self.plans[0]._lib
+        self._lib = lib
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._plan.value for p in self.plans])
+        self._arr = arr
+        self._b = ctypes.c_void_p()
+        _abi.check(lib, lib.hyb_batch_create(arr, len(self.plans), ctypes.byref(self._b)))
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "_b", None) and self._b.value:
+                self._lib.hyb_batch_destroy(self._b)
+                self._b = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def set(self, p: int, alpha, beta, f=None, g=None, lam=None, u=None):
+        """Device inputs of problem p (torch tensors or arrays, copied to the
+        plan's device); u (ne x n) is allocated when not given."""
+        import torch
+        pl = self.plans[p]
+        ne = pl.ne
+        a = pl._dev(alpha, (ne,))
+        b = pl._dev(beta, (ne,))
+        ff = pl._dev(f, (ne, 3))
+        gg = pl._dev(g, (ne, 6 * (pl.k + 1) ** 2))
+        lm = pl._dev(lam, (max(pl.m, 1),))
+        if u is None:
+            u = torch.empty((ne, pl.n), dtype=torch.float64, device=pl.device)
+        self._keep[p] = (a, b, ff, gg, lm, u)
+        _abi.check(self._lib, self._lib.hyb_batch_set(self._b, int(p), _dptr(a), _dptr(b), _dptr(ff), _dptr(gg),
+                                                      _dptr(lm), _dptr(u)))
+
+    def set_lambda(self, p: int, lam):
+        a, b, ff, gg, _, u = self._keep[p]
+        self.set(p, a, b, ff, gg, lam, u)
+
+    def u(self, p: int):
+        return self._keep[p][5]
+
+    def setup(self):
+        _abi.check(self._lib, self._lib.hyb_batch_setup(self._b))
+
+    def recover(self):
+        _abi.check(self._lib, self._lib.hyb_batch_recover(self._b))
+
+    def graph(self, on: bool = True):
+        _abi.check(self._lib, self._lib.hyb_batch_graph(self._b, 1 if on else 0))
+
+    def tiles(self, blocks_per_cu: int | None = None, items_per_block: int | None = None):
+        t = _abi.HybBatchTiles()
+        if blocks_per_cu is not None or items_per_block is not None:
+            t.blocks_per_cu = int(blocks_per_cu or 0)
+            t.items_per_block = int(items_per_block or 0)
+            _abi.check(self._lib, self._lib.hyb_batch_set_tiles(self._b, ctypes.byref(t)))
+        _abi.check(self._lib, self._lib.hyb_batch_get_tiles(self._b, ctypes.byref(t)))
+        return (t.blocks_per_cu, t.items_per_block)
+
+    def autotune(self, reps: int = 3):
+        t = _abi.HybBatchTiles()
+        _abi.check(self._lib, self._lib.hyb_batch_autotune(self._b, int(reps), ctypes.byref(t)))
+        return (t.blocks_per_cu, t.items_per_block)

@@ -21,7 +21,13 @@ EXPORTS = [
     "hyb_plan_create", "hyb_plan_topology", "hyb_last_detail", "hyb_bind", "hyb_setup", "hyb_rhs",
     "hyb_solve", "hyb_recover", "hyb_status", "hyb_strerror", "hyb_destroy",
     "hyb_timing_enable", "hyb_timing_read",
+    "hyb_batch_create", "hyb_batch_set", "hyb_batch_setup", "hyb_batch_recover", "hyb_batch_set_tiles",
+    "hyb_batch_get_tiles", "hyb_batch_graph", "hyb_batch_autotune", "hyb_batch_destroy",
 ]
+
+
+class HybBatchTiles(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("items_per_block", ctypes.c_int32)]
 
 
 class HybError(RuntimeError):
@@ -88,8 +94,18 @@ def load_library():
     lib.hyb_timing_read.argtypes = [vp, vp, vp, vp, vp]
     lib.hyb_destroy.argtypes = [vp]
     lib.hyb_destroy.restype = None
+    lib.hyb_batch_create.argtypes = [vp, ctypes.c_int32, vp]
+    lib.hyb_batch_set.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
+    lib.hyb_batch_setup.argtypes = [vp]
+    lib.hyb_batch_recover.argtypes = [vp]
+    lib.hyb_batch_set_tiles.argtypes = [vp, vp]
+    lib.hyb_batch_get_tiles.argtypes = [vp, vp]
+    lib.hyb_batch_graph.argtypes = [vp, ci]
+    lib.hyb_batch_autotune.argtypes = [vp, ci, vp]
+    lib.hyb_batch_destroy.argtypes = [vp]
+    lib.hyb_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("hyb_destroy", "hyb_last_detail", "hyb_strerror"):
+        if name not in ("hyb_destroy", "hyb_last_detail", "hyb_strerror", "hyb_batch_destroy"):
             getattr(lib, name).restype = ci
     _LIB = lib
     return lib

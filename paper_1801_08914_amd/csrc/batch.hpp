@@ -1,0 +1,105 @@
+// Batches of independent problems of mixed order: one persistent launch
+// walks a cost-sorted list of work items (problem, run of element blocks)
+// and runs the order's generic element routine on each.
+#pragma once
+
+#include "kernels_common.hpp"
+#include "setup_generic.hpp"
+
+namespace hyb {
+
+struct BatchProb {
+  SetupArgs s;       // matrix (and optional right-hand side) of the problem
+  RecoverArgs r;     // recovery of the problem
+  int32_t k;
+  int32_t K2;        // (k+1)^2
+  int64_t nfaces;
+  int64_t m;
+};
+
+struct BatchItem {
+  int32_t prob;
+  int32_t nblk;      // element blocks in this item
+  int64_t blk0;      // first element block (blocks of the order's EPB elements)
+};
+
+// Element blocks per order (teams x lanes = 256 threads for every order).
+__host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 16 : (k == 1 ? 4 : 1); }
+constexpr int kBatchThreads = 256;
+
+// Zero the same-face blocks of H (and r) of every problem: blockIdx.y is the
+// problem.
+__global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
+  const BatchProb& P = probs[blockIdx.y];
+  const int K2 = P.K2;
+  const int64_t nd = P.nfaces * K2 * K2;
+  const int64_t nr = (P.s.mode & MODE_RHS) ? P.m : 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nd + nr; i += int64_t(gridDim.x) * blockDim.x) {
+    if (i < nd) {
+      const int64_t F = i / (K2 * K2);
+      const int rem = int(i - F * K2 * K2), j = rem / K2, jj = rem % K2;
+      P.s.Hval[P.s.mp.face_rowbase[F] + int64_t(j) * P.s.mp.face_nslots[F] * K2 + P.s.mp.face_selfslot[F] * K2 + jj] =
+          0.0;
+    } else {
+      P.s.r[i - nd] = 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* probs, const BatchItem* items,
+                                                               int64_t nitems) {
+  extern __shared__ double smem[];
+  for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const BatchItem it = items[w];
+    const BatchProb& P = probs[it.prob];
+    for (int b = 0; b < it.nblk; ++b) {
+      const int64_t blk = it.blk0 + b;
+      switch (P.k) {
+        case 0: setup_generic_body<0, 16, 16>(P.s, smem, blk); break;
+        case 1: setup_generic_body<1, 64, 4>(P.s, smem, blk); break;
+        case 2: setup_generic_body<2, 256, 1>(P.s, smem, blk); break;
+        default: setup_generic_body<3, 256, 1>(P.s, smem, blk); break;
+      }
+      __syncthreads();   // the next block reuses the LDS
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb* probs, const BatchItem* items,
+                                                                 int64_t nitems) {
+  extern __shared__ double smem[];
+  for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const BatchItem it = items[w];
+    const BatchProb& P = probs[it.prob];
+    for (int b = 0; b < it.nblk; ++b) {
+      const int64_t blk = it.blk0 + b;
+      switch (P.k) {
+        case 0: recover_generic_body<0, 16, 16>(P.r, smem, blk); break;
+        case 1: recover_generic_body<1, 64, 4>(P.r, smem, blk); break;
+        case 2: recover_generic_body<2, 256, 1>(P.r, smem, blk); break;
+        default: recover_generic_body<3, 256, 1>(P.r, smem, blk); break;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// LDS bytes of one block of the batch kernels for order k.
+inline size_t batch_setup_lds(int k) {
+  switch (k) {
+    case 0: return 8 * 16 * size_t(GenericLayout<0, 16, 16>::per);
+    case 1: return 8 * 4 * size_t(GenericLayout<1, 64, 4>::per);
+    case 2: return 8 * size_t(GenericLayout<2, 256, 1>::per);
+    default: return 8 * size_t(GenericLayout<3, 256, 1>::per);
+  }
+}
+inline size_t batch_recover_lds(int k) {
+  switch (k) {
+    case 0: return 8 * 16 * size_t(recover_per<0>());
+    case 1: return 8 * 4 * size_t(recover_per<1>());
+    case 2: return 8 * size_t(recover_per<2>());
+    default: return 8 * size_t(recover_per<3>());
+  }
+}
+
+}  // namespace hyb

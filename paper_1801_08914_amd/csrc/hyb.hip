@@ -12,6 +12,9 @@
 #include "plan.hpp"
 #include "k1_fast.hpp"
 #include "setup_generic.hpp"
+#include "batch.hpp"
+
+#include <algorithm>
 
 struct hyb_plan {
   hyb::Plan P;
@@ -527,6 +530,339 @@ void hyb_destroy(hyb_plan_t* plan) {
   for (auto* L : {&P.ev_setup, &P.ev_recover, &P.ev_pool})
     for (void* e : *L) (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(e));
   delete plan;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: many independent plans, one persistent launch per phase.
+
+}  // extern "C"
+
+struct hyb_batch {
+  std::vector<hyb_plan_t*> plans;
+  hipStream_t stream = nullptr;
+  int cus = 0;
+  hyb_batch_tiles tiles{0, 0};
+  std::vector<hyb::BatchProb> probs;       // host copy of the descriptors
+  std::vector<hyb::BatchItem> items;       // cost-sorted work list
+  hyb::BatchProb* d_probs = nullptr;
+  hyb::BatchItem* d_items = nullptr;
+  size_t cap_items = 0;
+  size_t lds_setup = 0, lds_recover = 0;
+  bool dirty = true;                       // descriptors or items changed since upload
+  bool use_graph = false;
+  hipGraphExec_t g_setup = nullptr, g_recover = nullptr;
+  hipStream_t gstream = nullptr;           // capture/replay stream (graphs need a non-null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+// Relative cost of one element block of order k (flops of assembly and
+// factorization of the batch kernels, per block of batch_epb(k) elements).
+double batch_block_cost(int k) {
+  const double n = 3.0 * (k + 1) * (k + 1) * (k + 2), Q = double((k + 2) * (k + 2) * (k + 2));
+  return hyb::batch_epb(k) * (2.0 * n * n * Q / 2 + n * n * n / 3);
+}
+
+int batch_tiles_effective(const hyb_batch* b, int& bpc, int& ipb) {
+  bpc = b->tiles.blocks_per_cu > 0 ? b->tiles.blocks_per_cu : 2;
+  ipb = b->tiles.items_per_block > 0 ? b->tiles.items_per_block : 1;
+  return HYB_OK;
+}
+
+void batch_build_items(hyb_batch* b) {
+  int bpc, ipb;
+  batch_tiles_effective(b, bpc, ipb);
+  b->items.clear();
+  for (size_t p = 0; p < b->plans.size(); ++p) {
+    const hyb::Plan& P = b->plans[p]->P;
+    const int epb = hyb::batch_epb(P.ord.k);
+    const int64_t nblk = (P.ne + epb - 1) / epb;
+    for (int64_t q = 0; q < nblk; q += ipb) {
+      hyb::BatchItem it{};
+      it.prob = int32_t(p);
+      it.blk0 = q;
+      it.nblk = int32_t(std::min<int64_t>(ipb, nblk - q));
+      b->items.push_back(it);
+    }
+  }
+  // most expensive first (orders descending), stable: deterministic order
+  std::stable_sort(b->items.begin(), b->items.end(), [&](const hyb::BatchItem& x, const hyb::BatchItem& y) {
+    return batch_block_cost(b->plans[x.prob]->P.ord.k) * x.nblk > batch_block_cost(b->plans[y.prob]->P.ord.k) * y.nblk;
+  });
+  b->dirty = true;
+}
+
+int batch_upload(hyb_batch* b) {
+  if (!b->dirty) return HYB_OK;
+  if (b->items.size() > b->cap_items) {
+    if (b->d_items) HYB_HIP(hipFree(b->d_items));
+    b->d_items = nullptr;
+    HYB_HIP(hipMalloc(&b->d_items, sizeof(hyb::BatchItem) * std::max<size_t>(b->items.size(), 1)));
+    b->cap_items = b->items.size();
+  }
+  if (!b->items.empty())
+    HYB_HIP(hipMemcpyAsync(b->d_items, b->items.data(), sizeof(hyb::BatchItem) * b->items.size(),
+                           hipMemcpyHostToDevice, b->stream));
+  HYB_HIP(hipMemcpyAsync(b->d_probs, b->probs.data(), sizeof(hyb::BatchProb) * b->probs.size(),
+                         hipMemcpyHostToDevice, b->stream));
+  HYB_HIP(hipStreamSynchronize(b->stream));
+  b->dirty = false;
+  for (hipGraphExec_t* g : {&b->g_setup, &b->g_recover})
+    if (*g) {
+      (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+  return HYB_OK;
+}
+
+unsigned batch_grid(const hyb_batch* b) {
+  int bpc, ipb;
+  batch_tiles_effective(b, bpc, ipb);
+  const int64_t want = int64_t(bpc) * b->cus;
+  const int64_t n = int64_t(b->items.size());
+  return unsigned(std::max<int64_t>(1, std::min(want, n)));
+}
+
+int batch_launch_setup(hyb_batch* b, hipStream_t st) {
+  int64_t zmax = 1;
+  for (const auto& pr : b->probs) zmax = std::max<int64_t>(zmax, pr.nfaces * pr.K2 * pr.K2 + pr.m);
+  const unsigned zx = unsigned(std::min<int64_t>((zmax + 255) / 256, 1024));
+  hipLaunchKernelGGL(hyb::k_batch_zero, dim3(zx, unsigned(b->probs.size())), dim3(256), 0, st, b->d_probs);
+  HYB_HIP(hipGetLastError());
+  if (!b->items.empty()) {
+    hipLaunchKernelGGL(hyb::k_setup_batch, dim3(batch_grid(b)), dim3(hyb::kBatchThreads), b->lds_setup, st,
+                       b->d_probs, b->d_items, int64_t(b->items.size()));
+    HYB_HIP(hipGetLastError());
+  }
+  return HYB_OK;
+}
+
+int batch_launch_recover(hyb_batch* b, hipStream_t st) {
+  if (!b->items.empty()) {
+    hipLaunchKernelGGL(hyb::k_recover_batch, dim3(batch_grid(b)), dim3(hyb::kBatchThreads), b->lds_recover, st,
+                       b->d_probs, b->d_items, int64_t(b->items.size()));
+    HYB_HIP(hipGetLastError());
+  }
+  return HYB_OK;
+}
+
+// Run fn on the stream, or replay its captured graph.
+template <class Fn>
+int batch_run(hyb_batch* b, hipGraphExec_t& g, Fn&& fn) {
+  int rc = batch_upload(b);
+  if (rc) return rc;
+  if (!b->use_graph) return fn(b, b->stream);
+  // graphs are captured and replayed on the batch's own stream, ordered
+  // after and before the plans' stream by events
+  if (!g) {
+    hipGraph_t graph = nullptr;
+    HYB_HIP(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
+    rc = fn(b, b->gstream);
+    hipError_t e2 = hipStreamEndCapture(b->gstream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    HYB_HIP(e2);
+    hipError_t e3 = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HYB_HIP(e3);
+  }
+  HYB_HIP(hipEventRecord(b->ev_in, b->stream));
+  HYB_HIP(hipStreamWaitEvent(b->gstream, b->ev_in, 0));
+  HYB_HIP(hipGraphLaunch(g, b->gstream));
+  HYB_HIP(hipEventRecord(b->ev_out, b->gstream));
+  HYB_HIP(hipStreamWaitEvent(b->stream, b->ev_out, 0));
+  return HYB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out) {
+  if (!out || count <= 0 || !plans) return HYB_E_ARG;
+  *out = nullptr;
+  for (int32_t i = 0; i < count; ++i)
+    if (!plans[i]) return HYB_E_ARG;
+  for (int32_t i = 0; i < count; ++i)
+    if (!plans[i]->P.bound) return HYB_E_STATE;
+  hyb_batch* b = new (std::nothrow) hyb_batch;
+  if (!b) return HYB_E_NOMEM;
+  b->plans.assign(plans, plans + count);
+  b->stream = stream_of(plans[0]->P);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || b->cus <= 0)
+    b->cus = 256;
+  b->probs.resize(size_t(count));
+  for (int32_t i = 0; i < count; ++i) {
+    hyb::Plan& P = plans[i]->P;
+    // the batch kernels use the generic element routines and record layout
+    P.fast_k1 = false;
+    hyb::BatchProb& pr = b->probs[size_t(i)];
+    pr = hyb::BatchProb{};
+    pr.k = P.ord.k;
+    pr.K2 = P.ord.K2;
+    pr.nfaces = P.nfaces;
+    pr.m = P.m;
+    pr.s.mp = device_maps(P);
+    pr.s.ne = P.ne;
+    pr.s.factor = P.buf.factor;
+    pr.s.y = P.buf.y;
+    pr.s.Hval = P.buf.val;
+    pr.s.r = P.buf.r;
+    pr.s.status = P.buf.status;
+    pr.s.mode = hyb::MODE_MATRIX;
+    pr.r.mp = pr.s.mp;
+    pr.r.ne = P.ne;
+    pr.r.factor = P.buf.factor;
+    pr.r.y = P.buf.y;
+    b->lds_setup = std::max(b->lds_setup, hyb::batch_setup_lds(P.ord.k));
+    b->lds_recover = std::max(b->lds_recover, hyb::batch_recover_lds(P.ord.k));
+  }
+  hipError_t e1 = hipMalloc(&b->d_probs, sizeof(hyb::BatchProb) * b->probs.size());
+  if (e1 == hipSuccess) e1 = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+  if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e1 == hipSuccess)
+    e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(hyb::k_setup_batch),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_setup));
+  if (e1 == hipSuccess)
+    e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(hyb::k_recover_batch),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_recover));
+  if (e1 != hipSuccess) {
+    hyb_batch_destroy(b);
+    return hip_fail(e1);
+  }
+  batch_build_items(b);
+  *out = b;
+  return HYB_OK;
+}
+
+int hyb_batch_set(hyb_batch_t* b, int32_t p, const double* alpha, const double* beta, const double* f,
+                  const double* g, const double* lambda, double* u) {
+  if (!b || p < 0 || p >= int32_t(b->plans.size())) return HYB_E_ARG;
+  hyb::BatchProb& pr = b->probs[size_t(p)];
+  pr.s.alpha = alpha;
+  pr.s.beta = beta;
+  pr.s.f = f;
+  pr.s.g = f ? g : nullptr;
+  pr.s.mode = hyb::MODE_MATRIX | (f ? hyb::MODE_RHS : 0);
+  pr.r.lambda = lambda;
+  pr.r.u = u;
+  b->dirty = true;
+  return HYB_OK;
+}
+
+int hyb_batch_set_tiles(hyb_batch_t* b, const hyb_batch_tiles* tiles) {
+  if (!b || !tiles || tiles->blocks_per_cu < 0 || tiles->items_per_block < 0 || tiles->blocks_per_cu > 64 ||
+      tiles->items_per_block > 1024)
+    return HYB_E_ARG;
+  b->tiles = *tiles;
+  batch_build_items(b);
+  return HYB_OK;
+}
+
+int hyb_batch_get_tiles(const hyb_batch_t* b, hyb_batch_tiles* tiles) {
+  if (!b || !tiles) return HYB_E_ARG;
+  int bpc, ipb;
+  batch_tiles_effective(b, bpc, ipb);
+  tiles->blocks_per_cu = bpc;
+  tiles->items_per_block = ipb;
+  return HYB_OK;
+}
+
+int hyb_batch_graph(hyb_batch_t* b, int enable) {
+  if (!b) return HYB_E_ARG;
+  b->use_graph = enable != 0;
+  return HYB_OK;
+}
+
+int hyb_batch_setup(hyb_batch_t* b) {
+  if (!b) return HYB_E_ARG;
+  for (const auto& pr : b->probs)
+    if (!pr.s.alpha || !pr.s.beta) return HYB_E_STATE;
+  int rc = batch_run(b, b->g_setup, batch_launch_setup);
+  if (rc) return rc;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    hyb::Plan& P = b->plans[i]->P;
+    P.have_setup = true;
+    P.have_rhs = b->probs[i].s.f != nullptr;
+    P.alpha_d = b->probs[i].s.alpha;
+    P.beta_d = b->probs[i].s.beta;
+  }
+  return HYB_OK;
+}
+
+int hyb_batch_recover(hyb_batch_t* b) {
+  if (!b) return HYB_E_ARG;
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    if (!b->plans[i]->P.have_rhs || !b->probs[i].r.lambda || !b->probs[i].r.u) return HYB_E_STATE;
+  return batch_run(b, b->g_recover, batch_launch_recover);
+}
+
+int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best) {
+  if (!b || reps <= 0) return HYB_E_ARG;
+  for (const auto& pr : b->probs)
+    if (!pr.s.alpha || !pr.s.beta || !pr.r.lambda || !pr.r.u) return HYB_E_STATE;
+  const bool graph = b->use_graph;
+  b->use_graph = false;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  HYB_HIP(hipEventCreate(&t0));
+  HYB_HIP(hipEventCreate(&t1));
+  const int bpcs[] = {1, 2, 4, 8};
+  const int ipbs[] = {1, 2, 4, 8};
+  hyb_batch_tiles win{2, 1};
+  float wbest = -1.0f;
+  int rc = HYB_OK;
+  for (int bpc : bpcs) {
+    for (int ipb : ipbs) {
+      hyb_batch_tiles t{bpc, ipb};
+      if ((rc = hyb_batch_set_tiles(b, &t))) break;
+      // one untimed pass, then reps timed passes of setup + recovery
+      if ((rc = hyb_batch_setup(b)) || (rc = hyb_batch_recover(b))) break;
+      if (hipEventRecord(t0, b->stream) != hipSuccess) { rc = HYB_E_HIP; break; }
+      for (int r = 0; r < reps && !rc; ++r) {
+        rc = hyb_batch_setup(b);
+        if (!rc) rc = hyb_batch_recover(b);
+      }
+      if (rc) break;
+      if (hipEventRecord(t1, b->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess) {
+        rc = HYB_E_HIP;
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, t0, t1);
+      if (wbest < 0.0f || ms < wbest) {
+        wbest = ms;
+        win = t;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  b->use_graph = graph;
+  if (rc) return rc;
+  rc = hyb_batch_set_tiles(b, &win);
+  if (rc) return rc;
+  if (best) *best = win;
+  return HYB_OK;
+}
+
+void hyb_batch_destroy(hyb_batch_t* b) {
+  if (!b) return;
+  if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+  for (hipGraphExec_t g : {b->g_setup, b->g_recover})
+    if (g) (void)hipGraphExecDestroy(g);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_probs) (void)hipFree(b->d_probs);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  delete b;
 }
 
 }  // extern "C"

@@ -1,0 +1,109 @@
+"""Uneven batches of problems of mixed order and mesh in one persistent launch
+(through the C ABI): every problem's H, r and u equal those of its own plan
+calls bitwise (same element routines), they match the oracle, hipGraph
+replays equal the eager launches on every replay, and the autotuner's choice
+leaves the results unchanged."""
+import numpy as np
+import pytest
+
+import synth
+import scipy.sparse as sp
+
+from oracle import extended as oext
+from oracle import hybrid as ohyb
+from tests.gpu_common import accuracy_bound, ld_dense, norm_rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems():
+    # small C4-shaped batch: jittered n^3 meshes, n in 2..4, k in 0..3
+    return synth.config_c4(nprob=8, nmin=2, nmax=4, seed=40)
+
+
+def _batch(torch, probs):
+    from paper_1801_08914_amd import Batch, Plan
+    plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True).bind() for p in probs]
+    b = Batch(plans)
+    rng = np.random.default_rng(41)
+    lams = [rng.standard_normal(max(pl.m, 1)) for pl in plans]
+    for i, (p, pl) in enumerate(zip(probs, plans)):
+        b.set(i, p.alpha, p.beta, p.f, lam=lams[i])
+    return b, plans, lams
+
+
+def _outputs(torch, b, plans):
+    torch.cuda.synchronize()
+    out = []
+    for i, pl in enumerate(plans):
+        rc, det = pl.status()
+        assert rc == 0, (i, rc, det)
+        out.append((pl.csr()[2].clone(), pl.r().clone(), b.u(i).clone()))
+    return out
+
+
+def test_batch_matches_single_plans_and_oracle():
+    torch = require_gpu()
+    from paper_1801_08914_amd import Plan
+    probs = _problems()
+    print("orders", [p.k for p in probs], "elements", [p.mesh.ne for p in probs], flush=True)
+    assert sorted(set(p.k for p in probs)) == [0, 1, 2, 3]
+    b, plans, lams = _batch(torch, probs)
+    b.setup()
+    b.recover()
+    got = _outputs(torch, b, plans)
+    for i, p in enumerate(probs):
+        single = Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True).bind()
+        single.setup(p.alpha, p.beta, p.f)
+        u = single.recover(torch.as_tensor(lams[i], device="cuda")).cpu()
+        torch.cuda.synchronize()
+        val, r, ub = got[i]
+        assert torch.equal(val.cpu(), single.csr()[2].cpu()), i
+        assert torch.equal(r.cpu(), single.r().cpu()), i
+        assert torch.equal(ub.cpu(), u), i
+        # and against the long-double reference: at least as accurate as the
+        # FP64 oracle (normwise; the per-entry form is exercised by the
+        # single-plan parity tests)
+        args = (p.k, p.mesh.xyz, p.mesh.e2v, p.alpha, p.beta, p.f)
+        ref = ohyb.hybridize(*args)
+        Hld, rld, U = oext.hybridize_ld(*args, ref.topo, np.arange(p.mesh.ne), lams[i][:ref.r.size])
+        Hl, rl = ld_dense(Hld, rld, ref.r.size)
+        Hg = sp.csr_matrix((val.cpu().numpy(), ref.H.indices, ref.H.indptr), shape=ref.H.shape).toarray()
+        ul = np.array([U[e].astype(float) for e in range(p.mesh.ne)])
+        uref = ohyb.recover(ref, p.mesh.xyz, p.mesh.e2v, p.alpha, p.beta, p.f, lams[i][:ref.r.size])
+        eH, eHo = norm_rel(Hl, Hg), norm_rel(Hl, ref.H.toarray())
+        er, ero = norm_rel(rl, r.cpu().numpy()), norm_rel(rl, ref.r)
+        eu, euo = norm_rel(ul, ub.cpu().numpy()), norm_rel(ul, uref)
+        print(f"  problem {i} k={p.k} ne={p.mesh.ne}: vs long double, GPU / oracle: H {eH:.1e} / {eHo:.1e} "
+              f"r {er:.1e} / {ero:.1e} u {eu:.1e} / {euo:.1e}", flush=True)
+        assert eH <= accuracy_bound(eHo) and er <= accuracy_bound(ero) and eu <= accuracy_bound(euo)
+
+
+def test_batch_graph_replays_and_autotune():
+    torch = require_gpu()
+    probs = _problems()
+    b, plans, _ = _batch(torch, probs)
+    b.setup()
+    b.recover()
+    eager = _outputs(torch, b, plans)
+    b.graph(True)
+    for rep in range(3):
+        # eager work of the program between replays
+        torch.empty(1 << 20, dtype=torch.float64, device="cuda").fill_(float(rep))
+        for pl in plans:
+            pl.csr()[2].zero_()
+            pl.r().zero_()
+        b.setup()
+        b.recover()
+        out = _outputs(torch, b, plans)
+        for i in range(len(plans)):
+            assert all(torch.equal(x, y) for x, y in zip(eager[i], out[i])), (rep, i)
+    b.graph(False)
+    best = b.autotune(reps=1)
+    print("autotuned tiles", best, flush=True)
+    assert b.tiles() == best
+    b.setup()
+    b.recover()
+    tuned = _outputs(torch, b, plans)
+    for i in range(len(plans)):
+        assert all(torch.equal(x, y) for x, y in zip(eager[i], tuned[i])), i
