@@ -202,6 +202,11 @@ int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u);
  */
 int hyb_status(hyb_plan_t* plan, int64_t* detail);
 
+/* Launch the plan's later work on stream (a hipStream_t; NULL: the null
+ * stream).  The caller orders it after work already queued on the old
+ * stream.  Errors: HYB_E_ARG. */
+int hyb_set_stream(hyb_plan_t* plan, void* stream);
+
 /* Static text for a status code. */
 const char* hyb_strerror(int code);
 

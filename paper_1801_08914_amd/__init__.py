@@ -61,6 +61,11 @@ class Plan:
             return 0                     # the null stream (torch's default stream)
         return int(self._stream_obj.cuda_stream)
 
+    def set_stream(self, stream):
+        """Run the plan's later work on ``stream`` (a torch.cuda.Stream or None)."""
+        self._stream_obj = stream
+        _abi.check(self._lib, self._lib.hyb_set_stream(self._plan, ctypes.c_void_p(self._stream_handle())))
+
     def __del__(self):
         try:
             if getattr(self, "_plan", None) and self._plan.value:

@@ -20,7 +20,7 @@ HYB_E_HIP = -8
 EXPORTS = [
     "hyb_plan_create", "hyb_plan_topology", "hyb_last_detail", "hyb_bind", "hyb_setup", "hyb_rhs",
     "hyb_solve", "hyb_recover", "hyb_status", "hyb_strerror", "hyb_destroy",
-    "hyb_timing_enable", "hyb_timing_read",
+    "hyb_timing_enable", "hyb_timing_read", "hyb_set_stream",
     "hyb_batch_create", "hyb_batch_set", "hyb_batch_setup", "hyb_batch_recover", "hyb_batch_set_tiles",
     "hyb_batch_get_tiles", "hyb_batch_graph", "hyb_batch_autotune", "hyb_batch_destroy",
 ]
@@ -94,6 +94,7 @@ def load_library():
     lib.hyb_timing_read.argtypes = [vp, vp, vp, vp, vp]
     lib.hyb_destroy.argtypes = [vp]
     lib.hyb_destroy.restype = None
+    lib.hyb_set_stream.argtypes = [vp, vp]
     lib.hyb_batch_create.argtypes = [vp, ctypes.c_int32, vp]
     lib.hyb_batch_set.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
     lib.hyb_batch_setup.argtypes = [vp]

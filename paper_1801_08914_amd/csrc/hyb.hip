@@ -512,6 +512,12 @@ int hyb_timing_read(hyb_plan_t* plan, double* ms_setup, int* n_setup, double* ms
   return sum(P.ev_recover, ms_recover, n_recover);
 }
 
+int hyb_set_stream(hyb_plan_t* plan, void* stream) {
+  if (!plan) return HYB_E_ARG;
+  plan->P.opts.stream = stream;
+  return HYB_OK;
+}
+
 int hyb_status(hyb_plan_t* plan, int64_t* detail) {
   if (!plan) return HYB_E_ARG;
   hyb::Plan& P = plan->P;
