@@ -141,6 +141,87 @@ def parity_sample(prob, plan, lam_np, nface=48, nel=48, seed=0):
             "sample": f"{len(faces)} faces' rows of H and r, {len(els)} elements' u"}
 
 
+def run_c4(args):
+    """The uneven batch (64 jittered problems, n in 8..24, k in 0..3): setup +
+    recovery of every problem in one persistent launch each, tiles from the
+    library's autotuner, replayed as hipGraphs.  Recovery uses a seeded random
+    lambda (its cost does not depend on the values)."""
+    import torch
+
+    import synth
+    from paper_1801_08914_amd import Batch, Plan
+    probs = synth.config_c4()
+    t0 = time.perf_counter()
+    plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True).bind("cuda:0") for p in probs]
+    plan_s = time.perf_counter() - t0
+    b = Batch(plans)
+    rng = np.random.default_rng(0)
+    for i, (p, pl) in enumerate(zip(probs, plans)):
+        b.set(i, p.alpha, p.beta, p.f, lam=rng.standard_normal(max(pl.m, 1)))
+    ne = sum(p.mesh.ne for p in probs)
+    tiles = b.autotune(reps=1)
+    b.graph(True)
+    for _ in range(args.warmup):
+        b.setup()
+        b.recover()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        b.setup()
+        b.recover()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    for i, pl in enumerate(plans):
+        rc, det = pl.status()
+        assert rc == 0, (i, rc, det)
+    ts = np.array(ts)
+    by_k = {k: sum(p.mesh.ne for p in probs if p.k == k) for k in range(4)}
+    out = {"metric": METRIC, "value": ne * len(ts) / ts.sum(), "unit": "elements/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * ts.mean(), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "uneven batch: 64 jittered n^3 problems, n~U{8..24}, k~U{0..3}, seed 4",
+                      "elements": ne, "elements_by_order": by_k, "problems": len(probs),
+                      "precision": "fp64-plain", "launch": "one persistent launch per phase, hipGraph replay",
+                      "autotuned_tiles": {"blocks_per_cu": tiles[0], "items_per_block": tiles[1]}},
+           "step_ms_p50": 1e3 * float(np.median(ts)), "step_ms_p90": 1e3 * float(np.percentile(ts, 90)),
+           "host_planning_s": plan_s}
+    print(json.dumps(out), flush=True)
+
+
+def run_c5(args):
+    """The serving stream: Poisson arrivals of hybridization requests (jittered
+    meshes, k in 1..3, 1..8 right-hand sides reusing the factors).  First the
+    saturation throughput (every request queued at once), then the stream at
+    0.7 of it in real time; p50/p99 latency = completion - arrival."""
+    import synth
+    from paper_1801_08914_amd.serving import Request, Server, latency_stats, run_stream
+
+    def stream(qps):
+        return [(t, Request(p.mesh.xyz, p.mesh.e2v, p.k, p.alpha, p.beta, fs, tag=p.name))
+                for t, p, fs in synth.serving_requests(args.requests, qps, nmin=args.nmin, nmax=args.nmax)]
+
+    budget = int(args.budget_gb * 2**30)
+    srv = Server(budget, slots=args.slots, rtol=1e-12)
+    sat = latency_stats(run_stream(srv, stream(1.0), realtime=False))
+    srv.close()
+    qps = 0.7 * sat["req_per_s"]
+    srv = Server(budget, slots=args.slots, rtol=1e-12)
+    res = run_stream(srv, stream(qps), realtime=True)
+    srv.close()
+    st = latency_stats(res)
+    out = {"metric": METRIC, "value": st["element_solves_per_s"], "unit": "element-solves/s", "n_gpus": 1,
+           "steps": len(res), "warmup": 0, "ms_per_step": 1e3 * st["mean_s"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"serving stream: {args.requests} requests, jittered n^3 meshes "
+                                  f"n~U{{{args.nmin}..{args.nmax}}}, k~U{{1..3}}, 1..8 rhs per request, seed 5",
+                      "slots": args.slots, "budget_gb": args.budget_gb, "qps": qps,
+                      "saturation_req_per_s": sat["req_per_s"], "precision": "fp64-plain"},
+           "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"], "req_per_s": st["req_per_s"],
+           "saturation": sat}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,11 +233,26 @@ def main():
                     help="recover from a seeded random lambda instead of the PCG solution (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--config", default="c2", choices=["c2", "c4", "c5"],
+                    help="c2: the RT1 32^3 workload (default line); c4: the uneven 64-problem batch; "
+                         "c5: the serving stream")
+    ap.add_argument("--requests", type=int, default=40, help="c5: requests in the stream")
+    ap.add_argument("--nmin", type=int, default=8, help="c5: smallest mesh edge")
+    ap.add_argument("--nmax", type=int, default=16, help="c5: largest mesh edge")
+    ap.add_argument("--slots", type=int, default=4, help="c5: requests in flight")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="c5: device-memory budget")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design in DESIGN.md)"}))
         sys.exit(2)
+
+    if args.config == "c4":
+        run_c4(args)
+        return
+    if args.config == "c5":
+        run_c5(args)
+        return
 
     import torch
 

@@ -175,14 +175,15 @@ class Server:
 
 def run_stream(server: Server, requests, realtime: bool = True):
     """Submit (arrival_s, Request) pairs, waiting for each arrival time on the
-    server's clock when realtime, and return the results in submission order."""
+    server's clock when realtime (otherwise all at once), and return the
+    results in submission order.  A request's arrival is its submission time."""
     futs = []
     for arrival, req in requests:
         if realtime:
             dt = arrival - server.now()
             if dt > 0:
                 time.sleep(dt)
-        req.arrival = server.now() if realtime else arrival
+        req.arrival = server.now()
         futs.append(server.submit(req))
     return [f.result() for f in futs]
 
