@@ -189,6 +189,48 @@ def run_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def run_single(args, prob, label):
+    """Setup + recovery of one problem through the plan (C1: latency of the
+    tiny RT0 problem; C3: the RT2 48^3 jittered workload on the generic
+    kernels), timed over the steps; lambda from one PCG solve."""
+    import torch
+
+    from paper_1801_08914_amd import Plan
+    ne = prob.mesh.ne
+    plan = Plan(prob.mesh.xyz, prob.mesh.e2v, prob.k).bind("cuda:0")
+    dev = torch.device("cuda:0")
+    alpha, beta, f = (torch.as_tensor(x, device=dev) for x in (prob.alpha, prob.beta, prob.f))
+    u = torch.empty((ne, plan.n), dtype=torch.float64, device=dev)
+    plan.setup(alpha, beta, f)
+    lam, info = plan.solve(1e-12, 20000)
+    for _ in range(args.warmup):
+        plan.setup(alpha, beta, f)
+        plan.recover(lam, u)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    ts = []
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        plan.setup(alpha, beta, f)
+        plan.recover(lam, u)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    kt = plan.timing_read()
+    rc, det = plan.status()
+    assert rc == 0, (rc, det)
+    ts = np.array(ts)
+    out = {"metric": METRIC, "value": ne * len(ts) / ts.sum(), "unit": "elements/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * ts.mean(), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": label, "elements": ne, "k": prob.k, "m": plan.m, "nnz": plan.nnz,
+                      "precision": "fp64-plain"},
+           "step_us_p50": 1e6 * float(np.median(ts)), "step_us_p90": 1e6 * float(np.percentile(ts, 90)),
+           "setup_kernel_ms": kt["setup_ms"] / max(kt["setup_n"], 1),
+           "recover_kernel_ms": kt["recover_ms"] / max(kt["recover_n"], 1),
+           "pcg": {"iters": info["iters"], "rel_res": info["rel_res"]}}
+    print(json.dumps(out), flush=True)
+
+
 def run_c5(args):
     """The serving stream: Poisson arrivals of hybridization requests (jittered
     meshes, k in 1..3, 1..8 right-hand sides reusing the factors).  First the
@@ -233,9 +275,9 @@ def main():
                     help="recover from a seeded random lambda instead of the PCG solution (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--config", default="c2", choices=["c2", "c4", "c5"],
-                    help="c2: the RT1 32^3 workload (default line); c4: the uneven 64-problem batch; "
-                         "c5: the serving stream")
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2: the RT1 32^3 workload (default line); c1: RT0 4^3 latency; c3: RT2 48^3 jittered; "
+                         "c4: the uneven 64-problem batch; c5: the serving stream")
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the stream")
     ap.add_argument("--nmin", type=int, default=8, help="c5: smallest mesh edge")
     ap.add_argument("--nmax", type=int, default=16, help="c5: largest mesh edge")
@@ -252,6 +294,14 @@ def main():
         return
     if args.config == "c5":
         run_c5(args)
+        return
+    if args.config in ("c1", "c3"):
+        import synth
+        if args.config == "c1":
+            run_single(args, synth.config_c1(), "rt0_4x4x4 RT0 unit cube 4^3, alpha = beta = 1, seed 1")
+        else:
+            run_single(args, synth.config_c3(), "rt2_48x48x48 RT2 jittered 0.2h, alpha lognormal clipped "
+                                                "[1e-2,1e2], beta = 1e-2, seed 3")
         return
 
     import torch
