@@ -63,7 +63,8 @@ enum hyb_status_code {
   HYB_E_STATE = -5,     /* call out of order (e.g. rhs before setup) */
   HYB_E_NOMEM = -6,     /* a bound buffer is missing */
   HYB_E_NOCONV = -7,    /* PCG did not reach rtol within maxit */
-  HYB_E_HIP = -8        /* HIP runtime error; detail holds the hipError_t */
+  HYB_E_HIP = -8,       /* HIP runtime error; detail holds the hipError_t */
+  HYB_E_INTERNAL = -9   /* the plan broke one of its own invariants (a bug) */
 };
 
 enum hyb_precision {

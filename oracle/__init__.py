@@ -20,6 +20,7 @@ It is a plain, slow, obviously correct restatement of what the method computes:
 * ``conforming``   the plain definition: P, A = P^T A_hat P, direct solve
 * ``mixed``        the hybridized mixed form H~ (Sec. 3.2), an independent
                    route to H
+* ``pcg``          Jacobi-preconditioned CG on H lam = r (Sec. 6.1 stopping rule)
 
 Letters: this code calls the mass coefficient ``alpha`` and the div-div
 coefficient ``beta``; the paper's weak form uses the opposite letters

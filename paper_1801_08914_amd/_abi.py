@@ -15,6 +15,7 @@ HYB_E_STATE = -5
 HYB_E_NOMEM = -6
 HYB_E_NOCONV = -7
 HYB_E_HIP = -8
+HYB_E_INTERNAL = -9
 
 # Every extern "C" symbol declared in include/hyb.h.
 EXPORTS = [

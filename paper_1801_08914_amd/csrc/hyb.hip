@@ -175,8 +175,10 @@ int finalize_k1(const hyb::Plan& P, hipStream_t s, bool matrix, bool rhs) {
 
 // PCG vectors and partial sums; the RT_1 setup also uses the buffer for the
 // neighbour terms of the same-face blocks of H and of r (20 per face).
-int64_t work_bytes(int64_t m, int nblk, int64_t nfaces) {
-  const int64_t pcg = 8 * (5 * m + 2 * int64_t(nblk)) + 256;
+// PCG work: r, z, p (two buffers), q, dinv; SpMV partials (1 per block),
+// vector-kernel partials (2 per block), scalars.
+int64_t work_bytes(int64_t m, int nblk, int nblk_spmv, int64_t nfaces) {
+  const int64_t pcg = 8 * (6 * m + int64_t(nblk_spmv) + 2 * int64_t(nblk)) + 512;
   const int64_t side = 8 * 20 * nfaces;
   return pcg > side ? pcg : side;
 }
@@ -198,6 +200,7 @@ const char* hyb_strerror(int code) {
     case HYB_E_NOMEM: return "missing device buffer";
     case HYB_E_NOCONV: return "PCG did not converge";
     case HYB_E_HIP: return "HIP runtime error";
+    case HYB_E_INTERNAL: return "internal invariant broken";
     default: return "unknown status";
   }
 }
@@ -220,10 +223,33 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   hyb::Plan& P = p->P;
   P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0;
   if (P.fast_k1) P.factor_len = hyb::k1::REC;
-  int64_t nblk = (P.m + hyb::kPcgThreads * 4 - 1) / (hyb::kPcgThreads * 4);
-  if (nblk < 1) nblk = 1;
-  if (nblk > 2048) nblk = 2048;
-  P.work_blocks = int(nblk);
+  // PCG grids, multiples of the 8 XCDs: vector kernels about one row per
+  // thread, the SpMV two rows per lane group
+  auto grid_for = [](int64_t rows, int64_t per, int64_t cap) {
+    int64_t n = (rows + per - 1) / per;
+    n = (n + 7) / 8 * 8;
+    return int(n < 8 ? 8 : (n > cap ? cap : n));
+  };
+  const int64_t K2 = int64_t(k + 1) * (k + 1);
+  P.max_row = 0;
+  for (int64_t i = 0; i < P.m; ++i) P.max_row = std::max(P.max_row, P.row_ptr[i + 1] - P.row_ptr[i]);
+  // the face-panel SpMV relies on the pattern built by the plan: the K2 rows
+  // of a face have equal length, the same columns, and follow each other
+  bool panels = P.m % K2 == 0;
+  for (int64_t F = 0; panels && F < P.m / K2; ++F) {
+    const int64_t b = P.row_ptr[F * K2], w = P.row_ptr[F * K2 + 1] - b;
+    for (int64_t a = 1; panels && a < K2; ++a) {
+      panels = P.row_ptr[F * K2 + a] == b + a * w && P.row_ptr[F * K2 + a + 1] == b + (a + 1) * w;
+      for (int64_t c = 0; panels && c < w; ++c) panels = P.col[b + a * w + c] == P.col[b + c];
+    }
+  }
+  if (!panels) {
+    g_last_detail = 0;
+    delete p;
+    return HYB_E_INTERNAL;
+  }
+  P.work_blocks = grid_for(P.m, hyb::kPcgThreads, 16384);
+  P.spmv_blocks = grid_for(P.m / K2, hyb::spmv_shape(k).faces_per_block, 65536);
   if (sizes) {
     sizes->ne = P.ne;
     sizes->k = k;
@@ -238,7 +264,7 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
     sizes->bytes_maps = int64_t(P.lay.total);
     sizes->bytes_factor = 8 * P.ne * P.factor_len;
     sizes->bytes_y = 8 * P.ne * P.ord.n;
-    sizes->bytes_work = work_bytes(P.m, P.work_blocks, P.nfaces);
+    sizes->bytes_work = work_bytes(P.m, P.work_blocks, P.spmv_blocks, P.nfaces);
   }
   *out = p;
   return HYB_OK;
@@ -394,26 +420,35 @@ int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solv
   if (!P.have_rhs) return HYB_E_STATE;
   hipStream_t s = stream_of(P);
   const int64_t m = P.m;
-  const int nblk = P.work_blocks;
+  const int nblk = P.work_blocks, nspmv = P.spmv_blocks;
   double* w = P.buf.work;
   double* r = w;
   double* z = r + m;
-  double* p = z + m;
-  double* q = p + m;
+  double* pb[2] = {z + m, z + 2 * m};
+  double* q = z + 3 * m;
   double* dinv = q + m;
-  double* part = dinv + m;
+  double* part_s = dinv + m;           // SpMV partials
+  double* part_v = part_s + nspmv;     // vector-kernel partials
   auto* sc = reinterpret_cast<hyb::PcgScalars*>(
-      reinterpret_cast<uint8_t*>(part) + ((8 * 2 * size_t(nblk) + 63) & ~size_t(63)));
+      reinterpret_cast<uint8_t*>(w) + ((8 * (6 * size_t(m) + nspmv + 2 * size_t(nblk)) + 63) & ~size_t(63)));
   if (info) *info = hyb_solve_info{0, 0, 0.0};
   if (m == 0) {
     if (info) info->converged = 1;
     return HYB_OK;
   }
-  const dim3 grid{unsigned(nblk), 1, 1};
+  const int k = P.ord.k;
+  const int64_t nfb = m / ((k + 1) * (k + 1));   // faces with multipliers
+  const dim3 grid{unsigned(nblk), 1, 1}, grid_s{unsigned(nspmv), 1, 1};
   const dim3 blk{unsigned(hyb::kPcgThreads), 1, 1};
-  hipLaunchKernelGGL(hyb::k_pcg_init, grid, blk, 0, s, m, P.buf.row_ptr, P.buf.col, P.buf.val, P.buf.r, lambda, r,
-                     z, p, dinv, part, nblk);
-  hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part, nblk, sc, 0);
+  // lanes per row of the diagonal search; panel shapes (K2, lanes, columns
+  // per lane) cover the widest panels, 11 faces: 11, 44, 99, 176 columns
+  auto init = P.max_row <= 16 ? hyb::k_pcg_init<4> : P.max_row <= 48 ? hyb::k_pcg_init<8>
+            : P.max_row <= 112 ? hyb::k_pcg_init<16> : hyb::k_pcg_init<32>;
+  auto spmv = k == 0 ? hyb::k_pcg_spmv<1, 4, 3> : k == 1 ? hyb::k_pcg_spmv<4, 16, 3>
+            : k == 2 ? hyb::k_pcg_spmv<9, 32, 4> : hyb::k_pcg_spmv<16, 64, 3>;
+  hipLaunchKernelGGL(init, grid, blk, 0, s, m, P.buf.row_ptr, P.buf.col, P.buf.val, P.buf.r, lambda, r, z, pb[0],
+                     dinv, part_v, nblk);
+  hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part_v, nblk, sc, 0);
   HYB_HIP(hipGetLastError());
   hyb::PcgScalars hs{};
   HYB_HIP(hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -427,11 +462,14 @@ int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solv
   while (!conv && it < maxit) {
     const int batch = (maxit - it) < check ? (maxit - it) : check;
     for (int b = 0; b < batch; ++b) {
-      hipLaunchKernelGGL(hyb::k_pcg_spmv, grid, blk, 0, s, m, P.buf.row_ptr, P.buf.col, P.buf.val, p, q, part, nblk);
-      hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part, nblk, sc, 1);
-      hipLaunchKernelGGL(hyb::k_pcg_update, grid, blk, 0, s, m, sc, p, q, dinv, lambda, r, z, part, nblk);
-      hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part, nblk, sc, 2);
-      hipLaunchKernelGGL(hyb::k_pcg_direction, grid, blk, 0, s, m, sc, z, p);
+      // iteration it + b: p_prev = pb[(it + b) & 1], new p into the other buffer
+      const double* pp = pb[(it + b) & 1];
+      double* pn = pb[(it + b + 1) & 1];
+      hipLaunchKernelGGL(spmv, grid_s, blk, 0, s, nfb, P.buf.row_ptr, P.buf.col, P.buf.val, z, pp, pn, q, sc, part_s,
+                         nspmv);
+      hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part_s, nspmv, sc, 1);
+      hipLaunchKernelGGL(hyb::k_pcg_update, grid, blk, 0, s, m, sc, pn, q, dinv, lambda, r, z, part_v, nblk);
+      hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part_v, nblk, sc, 2);
     }
     HYB_HIP(hipGetLastError());
     it += batch;

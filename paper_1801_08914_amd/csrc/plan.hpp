@@ -87,7 +87,9 @@ struct Plan {
   bool bound = false, have_setup = false, have_rhs = false;
   const double* alpha_d = nullptr;  // coefficients of the last setup (caller-owned)
   const double* beta_d = nullptr;
-  int work_blocks = 0;
+  int work_blocks = 0;                // PCG vector kernels (init, update)
+  int spmv_blocks = 0;                // PCG SpMV
+  int64_t max_row = 0;                // longest row of H
   // optional HIP-event timing of the main kernels (hipEvent_t kept as void*)
   bool timing = false;
   std::vector<void*> ev_setup, ev_recover;  // start/stop pairs, in launch order
