@@ -83,6 +83,10 @@ typedef struct hyb_opts {
   void* stream;           /* hipStream_t for every device call; NULL = null stream */
   int kernel_variant;     /* 0: automatic (order- and geometry-specific kernels
                              where they apply), 1: the generic kernels only */
+  int pcg_reduce;         /* where hyb_solve sums its per-block partials:
+                             0 automatic (by size), 1 inside the consuming
+                             kernels, 2 in separate one-block kernels; the
+                             results are the same bits either way */
 } hyb_opts;
 
 /* Sizes of the caller-owned device buffers, filled by hyb_plan_create. */

@@ -36,7 +36,8 @@ def _dptr(t):
 class Plan:
     """One hybridization problem: mesh + order, its topology and device buffers."""
 
-    def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None, generic: bool = False):
+    def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None, generic: bool = False,
+                 pcg_reduce: int = 0):
         lib = load_library()
         self._lib = lib
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -46,7 +47,7 @@ class Plan:
                             self.xyz.ctypes.data_as(ctypes.c_void_p),
                             self.e2v.ctypes.data_as(ctypes.c_void_p))
         self._stream_obj = stream
-        opts = _abi.HybOpts(0, ctypes.c_void_p(self._stream_handle()), 1 if generic else 0)
+        opts = _abi.HybOpts(0, ctypes.c_void_p(self._stream_handle()), 1 if generic else 0, int(pcg_reduce))
         self._plan = ctypes.c_void_p()
         sz = _abi.HybSizes()
         rc = lib.hyb_plan_create(ctypes.byref(mesh), self.k, ctypes.byref(opts), ctypes.byref(self._plan),

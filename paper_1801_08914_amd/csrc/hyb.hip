@@ -176,9 +176,9 @@ int finalize_k1(const hyb::Plan& P, hipStream_t s, bool matrix, bool rhs) {
 // PCG vectors and partial sums; the RT_1 setup also uses the buffer for the
 // neighbour terms of the same-face blocks of H and of r (20 per face).
 // PCG work: r, z, p (two buffers), q, dinv; SpMV partials (1 per block),
-// vector-kernel partials (2 per block), scalars.
+// update partials (2 per block, two slots), scalars.
 int64_t work_bytes(int64_t m, int nblk, int nblk_spmv, int64_t nfaces) {
-  const int64_t pcg = 8 * (6 * m + int64_t(nblk_spmv) + 2 * int64_t(nblk)) + 512;
+  const int64_t pcg = 8 * (6 * m + int64_t(nblk_spmv) + 4 * int64_t(nblk)) + 512;
   const int64_t side = 8 * 20 * nfaces;
   return pcg > side ? pcg : side;
 }
@@ -209,7 +209,7 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   g_last_detail = -1;
   if (!out) return HYB_E_ARG;
   *out = nullptr;
-  if (opt && opt->precision != HYB_FP64) return HYB_E_ARG;
+  if (opt && (opt->precision != HYB_FP64 || opt->pcg_reduce < 0 || opt->pcg_reduce > 2)) return HYB_E_ARG;
   hyb_plan* p = new (std::nothrow) hyb_plan;
   if (!p) return HYB_E_NOMEM;
   int64_t detail = -1;
@@ -428,9 +428,9 @@ int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solv
   double* q = z + 3 * m;
   double* dinv = q + m;
   double* part_s = dinv + m;           // SpMV partials
-  double* part_v = part_s + nspmv;     // vector-kernel partials
+  double* part_u = part_s + nspmv;     // update partials, two slots
   auto* sc = reinterpret_cast<hyb::PcgScalars*>(
-      reinterpret_cast<uint8_t*>(w) + ((8 * (6 * size_t(m) + nspmv + 2 * size_t(nblk)) + 63) & ~size_t(63)));
+      reinterpret_cast<uint8_t*>(w) + ((8 * (6 * size_t(m) + nspmv + 4 * size_t(nblk)) + 63) & ~size_t(63)));
   if (info) *info = hyb_solve_info{0, 0, 0.0};
   if (m == 0) {
     if (info) info->converged = 1;
@@ -444,11 +444,18 @@ int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solv
   // per lane) cover the widest panels, 11 faces: 11, 44, 99, 176 columns
   auto init = P.max_row <= 16 ? hyb::k_pcg_init<4> : P.max_row <= 48 ? hyb::k_pcg_init<8>
             : P.max_row <= 112 ? hyb::k_pcg_init<16> : hyb::k_pcg_init<32>;
-  auto spmv = k == 0 ? hyb::k_pcg_spmv<1, 4, 3> : k == 1 ? hyb::k_pcg_spmv<4, 16, 3>
-            : k == 2 ? hyb::k_pcg_spmv<9, 32, 4> : hyb::k_pcg_spmv<16, 64, 3>;
+  // partial sums in the consuming kernels unless every block reading every
+  // partial would move more than about 8 MB through L2 per iteration
+  const double sum_bytes = 8.0 * (double(nspmv) * nblk + 2.0 * double(nblk) * nspmv);
+  const bool fused = P.opts.pcg_reduce == 1 || (P.opts.pcg_reduce == 0 && sum_bytes <= 8.0 * (1 << 20));
+  auto spmv = fused ? (k == 0 ? hyb::k_pcg_spmv<1, 4, 3, true> : k == 1 ? hyb::k_pcg_spmv<4, 16, 3, true>
+                       : k == 2 ? hyb::k_pcg_spmv<9, 32, 4, true> : hyb::k_pcg_spmv<16, 64, 3, true>)
+                    : (k == 0 ? hyb::k_pcg_spmv<1, 4, 3, false> : k == 1 ? hyb::k_pcg_spmv<4, 16, 3, false>
+                       : k == 2 ? hyb::k_pcg_spmv<9, 32, 4, false> : hyb::k_pcg_spmv<16, 64, 3, false>);
+  auto update = fused ? hyb::k_pcg_update<true> : hyb::k_pcg_update<false>;
   hipLaunchKernelGGL(init, grid, blk, 0, s, m, P.buf.row_ptr, P.buf.col, P.buf.val, P.buf.r, lambda, r, z, pb[0],
-                     dinv, part_v, nblk);
-  hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part_v, nblk, sc, 0);
+                     dinv, part_u, nblk);
+  hipLaunchKernelGGL(hyb::k_pcg_rr, dim3(1), blk, 0, s, part_u, nblk, 1, sc, 1);
   HYB_HIP(hipGetLastError());
   hyb::PcgScalars hs{};
   HYB_HIP(hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -462,17 +469,20 @@ int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solv
   while (!conv && it < maxit) {
     const int batch = (maxit - it) < check ? (maxit - it) : check;
     for (int b = 0; b < batch; ++b) {
-      // iteration it + b: p_prev = pb[(it + b) & 1], new p into the other buffer
-      const double* pp = pb[(it + b) & 1];
-      double* pn = pb[(it + b + 1) & 1];
-      hipLaunchKernelGGL(spmv, grid_s, blk, 0, s, nfb, P.buf.row_ptr, P.buf.col, P.buf.val, z, pp, pn, q, sc, part_s,
-                         nspmv);
-      hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part_s, nspmv, sc, 1);
-      hipLaunchKernelGGL(hyb::k_pcg_update, grid, blk, 0, s, m, sc, pn, q, dinv, lambda, r, z, part_v, nblk);
-      hipLaunchKernelGGL(hyb::k_pcg_reduce, dim3(1), blk, 0, s, part_v, nblk, sc, 2);
+      // iteration j: p_{j-1} = pb[j & 1], p_j into the other buffer
+      const int j = it + b;
+      const double* pp = pb[j & 1];
+      double* pn = pb[(j + 1) & 1];
+      if (!fused && j > 0)
+        hipLaunchKernelGGL(hyb::k_pcg_scalar, dim3(1), blk, 0, s, part_s, nspmv, part_u, nblk, sc, j - 1, 1);
+      hipLaunchKernelGGL(spmv, grid_s, blk, 0, s, nfb, P.buf.row_ptr, P.buf.col, P.buf.val, z, pp, pn, q, part_u,
+                         nblk, sc, j, part_s, nspmv);
+      if (!fused) hipLaunchKernelGGL(hyb::k_pcg_scalar, dim3(1), blk, 0, s, part_s, nspmv, part_u, nblk, sc, j, 0);
+      hipLaunchKernelGGL(update, grid, blk, 0, s, m, pn, q, dinv, lambda, r, z, part_s, nspmv, part_u, sc, j, nblk);
     }
-    HYB_HIP(hipGetLastError());
     it += batch;
+    hipLaunchKernelGGL(hyb::k_pcg_rr, dim3(1), blk, 0, s, part_u, nblk, (it - 1) & 1, sc, 0);
+    HYB_HIP(hipGetLastError());
     HYB_HIP(hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
     HYB_HIP(hipStreamSynchronize(s));
     rr = hs.rr;

@@ -1,10 +1,21 @@
-// Jacobi-preconditioned CG on the CSR matrix H with deterministic reductions:
-// every block reduces a fixed contiguous range of rows in a fixed tree order,
-// and a one-block kernel sums the per-block partials in index order.  (A
-// "last block sums" handshake inside the producing kernel would need an
-// agent-scope release per block, which writes back the XCD's L2 each time.)
-// Per iteration: SpMV with the direction update folded in (p double-buffered),
-// sum -> alpha, vector update, sum -> beta.
+// Jacobi-preconditioned CG on the CSR matrix H:
+//   SpMV j:    beta_{j-1} = rz_j / rz_{j-1};  p_j = z_j + beta_{j-1} p_{j-1};
+//              q_j = H p_j;  partials of p_j . q_j
+//   update j:  alpha_j = rz_j / (p_j . q_j);  x += alpha_j p_j;
+//              r -= alpha_j q_j;  z = D^{-1} r;  partials of r.z and r.r
+// Reductions are deterministic: every block reduces a fixed contiguous range
+// of rows in a fixed tree order, and the per-block partials are summed in
+// index order by one routine (sum_partials).  Who sums them depends on size:
+// * in-kernel (small systems, launch-bound): every block of the consuming
+//   kernel sums the producing kernel's partials itself, so all blocks hold
+//   the same scalar bit for bit; two launches per iteration;
+// * separate (large systems, where every block reading every partial would
+//   cost more L2 traffic than two more launches): a one-block kernel after
+//   each of the two forms the scalar.
+// Both give the same bits.  (A "last block sums" handshake would need an
+// agent-scope release per block, which writes back the XCD's L2 every time.)
+// The update partials alternate between two slots by iteration parity (U_j
+// in slot j & 1, the initial ones in slot 1), and p between two buffers.
 #pragma once
 
 #include "kernels_common.hpp"
@@ -13,14 +24,14 @@ namespace hyb {
 
 constexpr int kPcgThreads = 256;
 
-// Scalars kept on the device between kernels.
+// Scalars for the host: rr of the current iterate (after a k_pcg_rr launch)
+// and rr0; rz_j of each update kernel, by parity (written by its block 0).
 struct PcgScalars {
-  double rz;       // r . z of the current iterate
-  double pq;       // p . H p
-  double rr;       // r . r
+  double rr;
   double rr0;
-  double alpha;
-  double beta;     // direction update of the next SpMV (0 before the first)
+  double rz[2];
+  double alpha;    // separate reductions: alpha_j for update j
+  double beta;     // separate reductions: beta_{j-1} for SpMV j
   double pad[2];
 };
 
@@ -54,6 +65,16 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return out;
 }
 
+// Sum of part[stride i + c] over i < n in index order: contiguous runs per
+// thread, then the fixed tree; the same value in every block.
+__device__ __forceinline__ double sum_partials(const double* part, int n, int stride, int c, double* red) {
+  const int per = (n + kPcgThreads - 1) / kPcgThreads;
+  const int i0 = threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) s += part[stride * i + c];
+  return block_sum(s, red);
+}
+
 // Logical block of this workgroup: consecutive logical blocks (consecutive
 // rows) go to the same XCD, whose L2 then holds the vector entries that the
 // rows of that XCD gather.
@@ -70,13 +91,13 @@ __device__ __forceinline__ void chunk(int64_t m, int nblk, int lb, int64_t& lo, 
   hi = lo + per < m ? lo + per : m;
 }
 
-// dinv = 1 / diag(H); x = 0; r = b; z = dinv r; p_prev = 0; partial r.z, r.r.
-// LPR lanes per row look for the diagonal entry.
+// dinv = 1 / diag(H); x = 0; r = b; z = dinv r; p_prev = 0; partials of
+// r.z, r.r into update slot 1.  LPR lanes per row look for the diagonal entry.
 template <int LPR>
 __global__ __launch_bounds__(kPcgThreads) void k_pcg_init(int64_t m, const int64_t* rp, const int32_t* ci,
                                                        const double* val, const double* b, double* x,
                                                        double* r, double* z, double* p0, double* dinv,
-                                                       double* part, int nblk) {
+                                                       double* part_u, int nblk) {
   __shared__ double red[kPcgThreads];
   constexpr int G = kPcgThreads / LPR;
   const int lb = pcg_block();
@@ -106,9 +127,28 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_init(int64_t m, const int64
   srz = block_sum(srz, red);
   srr = block_sum(srr, red);
   if (threadIdx.x == 0) {
-    part[2 * lb] = srz;
-    part[2 * lb + 1] = srr;
+    double* u = part_u + 2 * size_t(nblk);   // slot 1
+    u[2 * lb] = srz;
+    u[2 * lb + 1] = srr;
   }
+}
+
+// beta_{it-1} = rz_it / rz_{it-1}: rz_it from the partials of update it - 1
+// (slot (it - 1) & 1), rz_{it-1} as update it - 1 recorded it.
+__device__ __forceinline__ double pcg_beta(const double* part_u, int nblk_u, const PcgScalars* sc, int it,
+                                           double* red) {
+  const double rz = sum_partials(part_u + 2 * size_t(nblk_u) * ((it - 1) & 1), nblk_u, 2, 0, red);
+  const double rz_prev = sc->rz[(it - 1) & 1];
+  return rz_prev != 0.0 ? rz / rz_prev : 0.0;
+}
+
+// alpha_it = rz_it / (p.q) from the SpMV partials and those of update it - 1
+// (or of the initialisation), slot (it + 1) & 1; rz_it is returned too.
+__device__ __forceinline__ double pcg_alpha(const double* part_s, int nblk_s, const double* part_u, int nblk_u,
+                                            int it, double* red, double& rz) {
+  const double pq = sum_partials(part_s, nblk_s, 1, 0, red);
+  rz = sum_partials(part_u + 2 * size_t(nblk_u) * ((it + 1) & 1), nblk_u, 2, 0, red);
+  return pq != 0.0 ? rz / pq : 0.0;
 }
 
 // New search direction of entry j: z + beta p_prev (one expression, so every
@@ -117,23 +157,28 @@ __device__ __forceinline__ double direction(const double* z, const double* pp, d
   return __builtin_fma(be, pp[j], z[j]);
 }
 
-// p = z + beta p_prev (own rows, into the other p buffer) and q = H p over
-// face panels, gathering z + beta p_prev for the panel columns; partial p.q.
-// Matrix entries are streamed once (non-temporal loads), the vectors stay in
-// cache.  Each row's sum runs over the panel columns in a fixed order: per
-// lane in column order, then a fixed butterfly over the L lanes.
-template <int K2, int L, int CPL>
+// SpMV of iteration it over face panels, gathering z + beta p_prev for the
+// panel columns; p_it for the own rows into the other p buffer; partials of
+// p.q.  Matrix entries are streamed once (non-temporal loads), the vectors
+// stay in cache.  Each row's sum runs over the panel columns in a fixed
+// order: per lane in column order, then a fixed butterfly over the L lanes.
+template <int K2, int L, int CPL, bool FUSED>
 __global__ __launch_bounds__(kPcgThreads) void k_pcg_spmv(int64_t nfb, const int64_t* rp, const int32_t* ci,
                                                        const double* val, const double* z, const double* pp,
-                                                       double* p, double* q, const PcgScalars* sc, double* part,
-                                                       int nblk) {
+                                                       double* p, double* q, const double* part_u, int nblk_u,
+                                                       const PcgScalars* sc, int it, double* part_s, int nblk) {
   static_assert(L >= K2 && (L & (L - 1)) == 0, "one lane per panel row for the output");
   __shared__ double red[kPcgThreads];
   constexpr int G = kPcgThreads / L;
+  double be = 0.0;
+  if (!FUSED) {
+    be = it > 0 ? sc->beta : 0.0;
+  } else if (it > 0) {
+    be = pcg_beta(part_u, nblk_u, sc, it, red);
+  }
   const int lb = pcg_block();
   int64_t lo, hi;
   chunk(nfb, nblk, lb, lo, hi);
-  const double be = sc->beta;
   const int sub = threadIdx.x % L, grp = threadIdx.x / L;
   double s = 0.0;
   for (int64_t F = lo + grp; F < hi; F += G) {
@@ -183,51 +228,32 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_spmv(int64_t nfb, const int
     }
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) part[lb] = s;
+  if (threadIdx.x == 0) part_s[lb] = s;
 }
 
-// One block: sums of the partials in index order (contiguous runs per thread,
-// then the fixed tree).  stride 1: part[i] (p.q); stride 2: part[2i], part[2i+1]
-// (r.z, r.r).  which = 0: init (rz, rr, rr0, beta = 0); 1: alpha = rz / pq;
-// 2: beta = rz_new / rz, rz = rz_new, rr.
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_reduce(const double* part, int nblk, PcgScalars* sc,
-                                                         int which) {
+// Update of iteration it: alpha = rz_it / (p.q) from the SpMV partials and
+// the partials of update it - 1 (or of the initialisation); x += alpha p;
+// r -= alpha q; z = dinv r; partials of r.z, r.r into slot it & 1.  Block 0
+// records rz_it for the next SpMV.
+template <bool FUSED>
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_update(int64_t m, const double* __restrict__ p,
+                                                         const double* __restrict__ q,
+                                                         const double* __restrict__ dinv, double* __restrict__ x,
+                                                         double* __restrict__ r, double* __restrict__ z,
+                                                         const double* part_s, int nblk_s, double* part_u,
+                                                         PcgScalars* sc, int it, int nblk) {
   __shared__ double red[kPcgThreads];
-  const int stride = which == 1 ? 1 : 2;
-  double s0 = 0.0, s1 = 0.0;
-  const int per = (nblk + kPcgThreads - 1) / kPcgThreads;
-  for (int i = threadIdx.x * per; i < (threadIdx.x + 1) * per && i < nblk; ++i) {
-    s0 += part[stride * i];
-    if (stride == 2) s1 += part[2 * i + 1];
+  double al;
+  if (FUSED) {
+    double rz;
+    al = pcg_alpha(part_s, nblk_s, part_u, nblk, it, red, rz);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->rz[it & 1] = rz;
+  } else {
+    al = sc->alpha;
   }
-  s0 = block_sum(s0, red);
-  s1 = block_sum(s1, red);
-  if (threadIdx.x == 0) {
-    if (which == 0) {
-      sc->rz = s0;
-      sc->rr = s1;
-      sc->rr0 = s1;
-      sc->beta = 0.0;
-    } else if (which == 1) {
-      sc->pq = s0;
-      sc->alpha = s0 != 0.0 ? sc->rz / s0 : 0.0;
-    } else {
-      sc->beta = sc->rz != 0.0 ? s0 / sc->rz : 0.0;
-      sc->rz = s0;
-      sc->rr = s1;
-    }
-  }
-}
-
-// x += alpha p; r -= alpha q; z = dinv r; partial r.z, r.r
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_update(int64_t m, const PcgScalars* sc, const double* p,
-                                                         const double* q, const double* dinv, double* x,
-                                                         double* r, double* z, double* part, int nblk) {
-  __shared__ double red[kPcgThreads];
   const int lb = pcg_block();
   int64_t lo, hi;
   chunk(m, nblk, lb, lo, hi);
-  const double al = sc->alpha;
   double srz = 0.0, srr = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kPcgThreads) {
     x[i] += al * p[i];
@@ -241,8 +267,41 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_update(int64_t m, const Pcg
   srz = block_sum(srz, red);
   srr = block_sum(srr, red);
   if (threadIdx.x == 0) {
-    part[2 * lb] = srz;
-    part[2 * lb + 1] = srr;
+    double* u = part_u + 2 * size_t(nblk) * (it & 1);
+    u[2 * lb] = srz;
+    u[2 * lb + 1] = srr;
+  }
+}
+
+// Separate reductions, one block: which = 0: alpha_it (and rz_it recorded
+// as the in-kernel form records it) after SpMV it; 1: beta_it for SpMV it + 1
+// after update it.
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_scalar(const double* part_s, int nblk_s,
+                                                         const double* part_u, int nblk_u, PcgScalars* sc, int it,
+                                                         int which) {
+  __shared__ double red[kPcgThreads];
+  if (which == 0) {
+    double rz;
+    const double al = pcg_alpha(part_s, nblk_s, part_u, nblk_u, it, red, rz);
+    if (threadIdx.x == 0) {
+      sc->alpha = al;
+      sc->rz[it & 1] = rz;
+    }
+  } else {
+    const double be = pcg_beta(part_u, nblk_u, sc, it + 1, red);
+    if (threadIdx.x == 0) sc->beta = be;
+  }
+}
+
+// One block: rr of the update partials in slot `slot` for the host's
+// convergence test (and rr0 when first).
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_rr(const double* part_u, int nblk, int slot, PcgScalars* sc,
+                                                     int first) {
+  __shared__ double red[kPcgThreads];
+  const double rr = sum_partials(part_u + 2 * size_t(nblk) * slot, nblk, 2, 1, red);
+  if (threadIdx.x == 0) {
+    sc->rr = rr;
+    if (first) sc->rr0 = rr;
   }
 }
 

@@ -87,6 +87,23 @@ def test_full_solve_matches_direct_solution(k, N, jit, rot):
     assert info2["iters"] == info["iters"] and np.array_equal(lam2.cpu().numpy(), lam)
 
 
+@pytest.mark.parametrize("k,N", [(1, 6), (2, 4)])
+def test_reduction_modes_agree_bitwise(k, N):
+    """Partial sums inside the consuming kernels or in separate one-block
+    kernels: the same partials in the same order, so the same bits."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Plan
+    mesh, a, b, f = _problem(k, N, 0.2, True, 950 + k)
+    out = []
+    for mode in (1, 2):
+        plan = Plan(mesh.xyz, mesh.e2v, k, pcg_reduce=mode).bind()
+        plan.setup(a, b, f)
+        lam, info = plan.solve(1e-12, 5000)
+        assert info["converged"]
+        out.append((lam.cpu().numpy(), info["iters"], info["rel_res"]))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
+
+
 def test_not_converged_zero_rhs_and_empty_system():
     torch = require_gpu()
     from paper_1801_08914_amd import Plan
