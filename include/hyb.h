@@ -68,7 +68,16 @@ enum hyb_status_code {
 };
 
 enum hyb_precision {
-  HYB_FP64 = 0          /* every step in double precision */
+  HYB_FP64 = 0,         /* every step in double precision */
+  HYB_MIXED = 1         /* element Cholesky and triangular solves in FP32
+                           (after an exact power-of-two diagonal scaling),
+                           refined against the FP64 element matrix for
+                           refine_sweeps sweeps; the element matrix, the
+                           refinement residuals, H, r, the solve and u are
+                           FP64.  The factor record then holds X = M_T^{-1}
+                           C_T^T, M_T, the FP32 factor and the scaling, and
+                           recovery is u_T = y_T - X lambda_T (y_T = M_T^{-1}
+                           f_hat_T in the y buffer) */
 };
 
 typedef struct hyb_mesh {
@@ -79,10 +88,12 @@ typedef struct hyb_mesh {
 } hyb_mesh;
 
 typedef struct hyb_opts {
-  int precision;          /* HYB_FP64 */
+  int precision;          /* HYB_FP64 or HYB_MIXED */
   void* stream;           /* hipStream_t for every device call; NULL = null stream */
   int kernel_variant;     /* 0: automatic (order- and geometry-specific kernels
                              where they apply), 1: the generic kernels only */
+  int refine_sweeps;      /* HYB_MIXED: refinement sweeps after the FP32
+                             solve (0: none, the unrefined form); < 0: 3 */
   int pcg_reduce;         /* where hyb_solve sums its per-block partials:
                              0 automatic (by size), 1 inside the consuming
                              kernels, 2 in separate one-block kernels; the
@@ -255,7 +266,8 @@ typedef struct {
 } hyb_batch_tiles;
 
 /* plans: count bound plans (the batch keeps pointers, it does not own them),
- * launched on plans[0]'s stream.  Errors: HYB_E_ARG, HYB_E_STATE (unbound),
+ * launched on plans[0]'s stream.  Errors: HYB_E_ARG (also for a HYB_MIXED
+ * plan: batches run the FP64 element kernels), HYB_E_STATE (unbound),
  * HYB_E_NOMEM, HYB_E_HIP. */
 int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out);
 

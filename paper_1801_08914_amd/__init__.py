@@ -37,7 +37,7 @@ class Plan:
     """One hybridization problem: mesh + order, its topology and device buffers."""
 
     def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None, generic: bool = False,
-                 pcg_reduce: int = 0):
+                 pcg_reduce: int = 0, precision: str = "fp64", sweeps: int | None = None):
         lib = load_library()
         self._lib = lib
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -47,7 +47,12 @@ class Plan:
                             self.xyz.ctypes.data_as(ctypes.c_void_p),
                             self.e2v.ctypes.data_as(ctypes.c_void_p))
         self._stream_obj = stream
-        opts = _abi.HybOpts(0, ctypes.c_void_p(self._stream_handle()), 1 if generic else 0, int(pcg_reduce))
+        if precision not in ("fp64", "mixed"):
+            raise ValueError(f"precision must be 'fp64' or 'mixed', not {precision!r}")
+        self.precision = precision
+        opts = _abi.HybOpts(_abi.HYB_MIXED if precision == "mixed" else _abi.HYB_FP64,
+                            ctypes.c_void_p(self._stream_handle()), 1 if generic else 0,
+                            -1 if sweeps is None else int(sweeps), int(pcg_reduce))
         self._plan = ctypes.c_void_p()
         sz = _abi.HybSizes()
         rc = lib.hyb_plan_create(ctypes.byref(mesh), self.k, ctypes.byref(opts), ctypes.byref(self._plan),

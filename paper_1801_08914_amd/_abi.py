@@ -16,6 +16,8 @@ HYB_E_NOMEM = -6
 HYB_E_NOCONV = -7
 HYB_E_HIP = -8
 HYB_E_INTERNAL = -9
+HYB_FP64 = 0
+HYB_MIXED = 1
 
 # Every extern "C" symbol declared in include/hyb.h.
 EXPORTS = [
@@ -45,7 +47,7 @@ class HybMesh(ctypes.Structure):
 
 class HybOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("kernel_variant", ctypes.c_int),
-                ("pcg_reduce", ctypes.c_int)]
+                ("refine_sweeps", ctypes.c_int), ("pcg_reduce", ctypes.c_int)]
 
 
 class HybSizes(ctypes.Structure):

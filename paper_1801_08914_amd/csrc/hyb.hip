@@ -12,6 +12,7 @@
 #include "plan.hpp"
 #include "k1_fast.hpp"
 #include "setup_generic.hpp"
+#include "mixed.hpp"
 #include "batch.hpp"
 
 #include <algorithm>
@@ -103,6 +104,53 @@ int dispatch_recover(int k, const hyb::RecoverArgs& a, hipStream_t s) {
     case 1: return launch_recover<1, 64, 4>(a, s);
     case 2: return launch_recover<2, 256, 1>(a, s);
     case 3: return launch_recover<3, 256, 1>(a, s);
+    default: return HYB_E_ARG;
+  }
+}
+
+int64_t mixed_record_len(int k) {
+  switch (k) {
+    case 0: return hyb::MixedRec<0>::len;
+    case 1: return hyb::MixedRec<1>::len;
+    case 2: return hyb::MixedRec<2>::len;
+    default: return hyb::MixedRec<3>::len;
+  }
+}
+
+template <int K, int TEAM, int EPB>
+int launch_setup_mixed(const hyb::SetupArgs& a, int sweeps, hipStream_t s) {
+  if (a.ne == 0) return HYB_OK;
+  const int64_t blocks = (a.ne + EPB - 1) / EPB;
+  hipLaunchKernelGGL((hyb::k_setup_mixed<K, TEAM, EPB>), dim3(unsigned(blocks)), dim3(TEAM * EPB), 0, s, a, sweeps);
+  HYB_HIP(hipGetLastError());
+  return HYB_OK;
+}
+
+template <int K, int TEAM, int EPB>
+int launch_recover_mixed(const hyb::RecoverArgs& a, hipStream_t s) {
+  if (a.ne == 0) return HYB_OK;
+  const int64_t blocks = (a.ne + EPB - 1) / EPB;
+  hipLaunchKernelGGL((hyb::k_recover_mixed<K, TEAM, EPB>), dim3(unsigned(blocks)), dim3(TEAM * EPB), 0, s, a);
+  HYB_HIP(hipGetLastError());
+  return HYB_OK;
+}
+
+int dispatch_setup_mixed(int k, const hyb::SetupArgs& a, int sweeps, hipStream_t s) {
+  switch (k) {
+    case 0: return launch_setup_mixed<0, 16, 16>(a, sweeps, s);
+    case 1: return launch_setup_mixed<1, 64, 4>(a, sweeps, s);
+    case 2: return launch_setup_mixed<2, 256, 1>(a, sweeps, s);
+    case 3: return launch_setup_mixed<3, 256, 1>(a, sweeps, s);
+    default: return HYB_E_ARG;
+  }
+}
+
+int dispatch_recover_mixed(int k, const hyb::RecoverArgs& a, hipStream_t s) {
+  switch (k) {
+    case 0: return launch_recover_mixed<0, 16, 16>(a, s);
+    case 1: return launch_recover_mixed<1, 64, 4>(a, s);
+    case 2: return launch_recover_mixed<2, 128, 1>(a, s);
+    case 3: return launch_recover_mixed<3, 256, 1>(a, s);
     default: return HYB_E_ARG;
   }
 }
@@ -209,7 +257,9 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   g_last_detail = -1;
   if (!out) return HYB_E_ARG;
   *out = nullptr;
-  if (opt && (opt->precision != HYB_FP64 || opt->pcg_reduce < 0 || opt->pcg_reduce > 2)) return HYB_E_ARG;
+  if (opt && ((opt->precision != HYB_FP64 && opt->precision != HYB_MIXED) || opt->pcg_reduce < 0 ||
+              opt->pcg_reduce > 2 || opt->refine_sweeps > 16))
+    return HYB_E_ARG;
   hyb_plan* p = new (std::nothrow) hyb_plan;
   if (!p) return HYB_E_NOMEM;
   int64_t detail = -1;
@@ -221,8 +271,11 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   }
   if (opt) p->P.opts = *opt;
   hyb::Plan& P = p->P;
-  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0;
+  P.mixed = P.opts.precision == HYB_MIXED;
+  P.sweeps = P.opts.refine_sweeps < 0 ? 3 : P.opts.refine_sweeps;
+  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0 && !P.mixed;
   if (P.fast_k1) P.factor_len = hyb::k1::REC;
+  if (P.mixed) P.factor_len = mixed_record_len(k);
   // PCG grids, multiples of the 8 XCDs: vector kernels about one row per
   // thread, the SpMV two rows per lane group
   auto grid_for = [](int64_t rows, int64_t per, int64_t cap) {
@@ -363,7 +416,7 @@ int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta, const d
   } else {
     rc = zero_diag(P, s);
     if (!rc && f) rc = fill(s, P.buf.r, P.m, 0.0);
-    if (!rc) rc = dispatch_setup(P.ord.k, a, s);
+    if (!rc) rc = P.mixed ? dispatch_setup_mixed(P.ord.k, a, P.sweeps, s) : dispatch_setup(P.ord.k, a, s);
   }
   mark(P, P.ev_setup);
   if (rc) return rc;
@@ -407,7 +460,7 @@ int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g) {
     a.r = P.buf.r;
     a.status = P.buf.status;
     a.mode = hyb::MODE_RHS;
-    rc = dispatch_setup(P.ord.k, a, s);
+    rc = P.mixed ? dispatch_setup_mixed(P.ord.k, a, P.sweeps, s) : dispatch_setup(P.ord.k, a, s);
   }
   if (rc) return rc;
   P.have_rhs = true;
@@ -518,7 +571,7 @@ int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u) {
       HYB_HIP(hipGetLastError());
     }
   } else {
-    rc = dispatch_recover(P.ord.k, a, stream_of(P));
+    rc = P.mixed ? dispatch_recover_mixed(P.ord.k, a, stream_of(P)) : dispatch_recover(P.ord.k, a, stream_of(P));
   }
   mark(P, P.ev_recover);
   return rc;
@@ -740,8 +793,10 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
   *out = nullptr;
   for (int32_t i = 0; i < count; ++i)
     if (!plans[i]) return HYB_E_ARG;
-  for (int32_t i = 0; i < count; ++i)
+  for (int32_t i = 0; i < count; ++i) {
     if (!plans[i]->P.bound) return HYB_E_STATE;
+    if (plans[i]->P.mixed) return HYB_E_ARG;   // batches run the FP64 element kernels
+  }
   hyb_batch* b = new (std::nothrow) hyb_batch;
   if (!b) return HYB_E_NOMEM;
   b->plans.assign(plans, plans + count);

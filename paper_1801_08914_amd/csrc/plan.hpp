@@ -68,6 +68,8 @@ struct Plan {
   std::vector<int32_t> face_selfslot; // nfaces: slot of the face in its own rows
   bool all_affine = false;            // every element is a parallelepiped
   bool fast_k1 = false;               // RT_1 affine kernels (own factor record layout)
+  bool mixed = false;                 // HYB_MIXED element kernels (own factor record layout)
+  int sweeps = 0;                     // HYB_MIXED refinement sweeps
   // reference tables at the Gauss points (axis 0 fastest)
   std::vector<double> tab_s;        // Q x n: basis value (its only nonzero component)
   std::vector<double> tab_d;        // Q x n: reference divergence

@@ -52,6 +52,75 @@ struct GenericLayout {
   static constexpr int per = (kGlobal ? 0 : R::npk + R::nbpk) + R::Q * QD + R::n + 24 + R::nb;
 };
 
+// Geometry at the Gauss points of one element (team of TEAM lanes): the
+// trilinear map's Jacobian J from the 8 vertices and, per point q, the
+// weighted terms w alpha (J^T J)_de / det J (6, when need_matrix), the
+// div-div weight w beta / det J, and (need_rhs) w (J^T f)_d for the element
+// load f.  det J <= 0 is reported.  Ends with a barrier.
+template <int K, int TEAM>
+__device__ __forceinline__ void element_qd(const DeviceMaps& mp, int64_t es, double al, double be, const double* fv,
+                                           bool need_matrix, bool need_rhs, double* xe, double* qd, int lane,
+                                           bool live, int32_t* status, int64_t e) {
+  using R = RT<K>;
+  constexpr int Q = R::Q, q1 = R::q1, QD = 10;
+  for (int t = lane; t < 24; t += TEAM) xe[t] = mp.xyz[3 * int64_t(mp.e2v[es * 8 + t / 3]) + t % 3];
+  __syncthreads();
+  for (int q = lane; q < Q; q += TEAM) {
+    double xi[3] = {mp.gauss_x[q % q1], mp.gauss_x[(q / q1) % q1], mp.gauss_x[q / (q1 * q1)]};
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      double fa[3], ga[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int bit = (v >> c) & 1;
+        fa[c] = bit ? xi[c] : 1.0 - xi[c];
+        ga[c] = bit ? 1.0 : -1.0;
+      }
+      const double dN[3] = {ga[0] * fa[1] * fa[2], fa[0] * ga[1] * fa[2], fa[0] * fa[1] * ga[2]};
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) J[r][c] += xe[3 * v + r] * dN[c];
+    }
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (live && !(det > 0.0)) report_error(status, HYB_E_JACOBIAN, e);
+    const double w = mp.tab_w[q];
+    if (need_matrix) {
+      const double s = w * al / det;
+      double G[6];
+      int t = 0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = d; c < 3; ++c) G[t++] = J[0][d] * J[0][c] + J[1][d] * J[1][c] + J[2][d] * J[2][c];
+#pragma unroll
+      for (int t2 = 0; t2 < 6; ++t2) qd[q * QD + t2] = s * G[t2];
+      qd[q * QD + 6] = w * be / det;
+    }
+    if (need_rhs) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) qd[q * QD + 7 + d] = w * (fv[0] * J[0][d] + fv[1] * J[1][d] + fv[2] * J[2][d]);
+    }
+  }
+  __syncthreads();
+}
+
+// Entry (i, j) of M_T by Gauss quadrature from element_qd's per-point terms.
+template <int K>
+__device__ __forceinline__ double m_entry(const DeviceMaps& mp, const double* qd, int i, int j) {
+  using R = RT<K>;
+  constexpr int n = R::n, Q = R::Q, QD = 10;
+  const int gi = gidx(R::comp(i), R::comp(j));
+  double s = 0.0;
+  for (int q = 0; q < Q; ++q)
+    s += qd[q * QD + gi] * mp.tab_s[q * n + i] * mp.tab_s[q * n + j] +
+         qd[q * QD + 6] * mp.tab_d[q * n + i] * mp.tab_d[q * n + j];
+  return s;
+}
+
 // Local assembly (Gauss quadrature), essential-face masking, packed
 // Cholesky in i-first order, inversion of the face block, H_T scatter, and
 // the right-hand side y = L^{-1} f_hat, r_T = D L_bb^{-T} y_b.
@@ -85,56 +154,13 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   }
   auto is_ess = [&](int i) { return i >= ni && fid[(i - ni) / K2] < 0; };
 
-  for (int t = lane; t < 24; t += TEAM) xe[t] = mp.xyz[3 * int64_t(mp.e2v[es * 8 + t / 3]) + t % 3];
-  __syncthreads();
-
   const double al = a.alpha ? a.alpha[es] : 0.0, be = a.beta ? a.beta[es] : 0.0;
   double fv[3] = {0.0, 0.0, 0.0};
   if (a.mode & MODE_RHS) {
     fv[0] = a.f[es * 3 + 0]; fv[1] = a.f[es * 3 + 1]; fv[2] = a.f[es * 3 + 2];
   }
   const bool need_matrix = (a.mode & MODE_MATRIX) || ((a.mode & MODE_RHS) && a.g);
-  for (int q = lane; q < Q; q += TEAM) {
-    double xi[3] = {mp.gauss_x[q % q1], mp.gauss_x[(q / q1) % q1], mp.gauss_x[q / (q1 * q1)]};
-    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      double fa[3], ga[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int bit = (v >> c) & 1;
-        fa[c] = bit ? xi[c] : 1.0 - xi[c];
-        ga[c] = bit ? 1.0 : -1.0;
-      }
-      const double dN[3] = {ga[0] * fa[1] * fa[2], fa[0] * ga[1] * fa[2], fa[0] * fa[1] * ga[2]};
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) J[r][c] += xe[3 * v + r] * dN[c];
-    }
-    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-    if (live && !(det > 0.0)) report_error(a.status, HYB_E_JACOBIAN, e);
-    const double w = mp.tab_w[q];
-    if (need_matrix) {
-      const double s = w * al / det;
-      double G[6];
-      int t = 0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int c = d; c < 3; ++c) G[t++] = J[0][d] * J[0][c] + J[1][d] * J[1][c] + J[2][d] * J[2][c];
-#pragma unroll
-      for (int t2 = 0; t2 < 6; ++t2) qd[q * QD + t2] = s * G[t2];
-      qd[q * QD + 6] = w * be / det;
-    }
-    if (a.mode & MODE_RHS) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) qd[q * QD + 7 + d] = w * (fv[0] * J[0][d] + fv[1] * J[1][d] + fv[2] * J[2][d]);
-    }
-  }
-  __syncthreads();
+  element_qd<K, TEAM>(mp, es, al, be, fv, need_matrix, (a.mode & MODE_RHS) != 0, xe, qd, lane, live, a.status, e);
 
   // entry (i, j) of M_T by Gauss quadrature
   auto mij = [&](int i, int j) {

@@ -1,0 +1,121 @@
+"""Mixed-precision form (HYB_MIXED) through the C ABI against the oracle.
+
+The element Cholesky and triangular solves run in FP32 and are refined
+against the FP64 element matrix; H, r and u are FP64.  Against the oracle's
+long-double reference (the exact values to far below FP64 rounding):
+* refined (the default 3 sweeps): H, r and u within 1e-10, normwise and
+  entrywise per row, the stated target of the mixed form;
+* unrefined (0 sweeps): the FP32 solve alone, error printed; it must be
+  above the refined error (the sweeps do work) and below 1e-2: an FP32
+  factor leaves an error of about kappa(S M_T S) 2^-24, and the scaled
+  element matrices of these jittered lognormal meshes reach kappa ~ 1e5.
+The right-hand side alone on the stored factors equals a fresh setup bit for
+bit, and a full solve reaches the oracle's solution.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import extended as oext
+from oracle import hybrid as ohyb
+from tests.gpu_common import ld_dense, ld_row_errors, norm_rel, rel_inf, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+REFINED = 1e-10
+UNREFINED_MAX = 1e-2
+
+CASES = [
+    (0, 4, 0.2, True), (1, 3, 0.0, False), (1, 4, 0.2, True), (2, 2, 0.2, True), (2, 3, 0.2, False),
+    (3, 2, 0.2, True),
+]
+
+
+def _problem(k, N, jit, rot, seed):
+    rng = np.random.default_rng(seed)
+    mesh = synth.structured_hex(N, jitter=jit, rng=rng)
+    if rot:
+        mesh, _ = synth.rotate_connectivity(mesh, rng)
+    ne = mesh.ne
+    return mesh, synth.lognormal(rng, ne), synth.lognormal(rng, ne, 0.5), synth.element_loads(rng, ne)
+
+
+def _mixed(torch, mesh, k, a, b, f, sweeps=None):
+    from paper_1801_08914_amd import Plan
+    plan = Plan(mesh.xyz, mesh.e2v, k, precision="mixed", sweeps=sweeps).bind()
+    plan.setup(a, b, f)
+    torch.cuda.synchronize()
+    rc, det = plan.status()
+    assert rc == 0, (rc, det)
+    return plan
+
+
+@pytest.mark.parametrize("k,N,jit,rot", CASES)
+def test_mixed_H_r_u_refined_and_unrefined(k, N, jit, rot):
+    torch = require_gpu()
+    print(f"case k={k} N={N} jitter={jit} rotate={rot}", flush=True)
+    mesh, a, b, f = _problem(k, N, jit, rot, 3000 + 10 * k + N)
+    ref = ohyb.hybridize(k, mesh.xyz, mesh.e2v, a, b, f)
+    lam = np.random.default_rng(8).standard_normal(ref.r.size)
+    Hld, rld, U = oext.hybridize_ld(k, mesh.xyz, mesh.e2v, a, b, f, ref.topo, np.arange(mesh.ne), lam)
+    Hl, rl = ld_dense(Hld, rld, ref.r.size)
+    ul = np.array([U[e].astype(float) for e in range(mesh.ne)])
+    rows = np.arange(ref.r.size)
+    errs = {}
+    for sweeps in (0, None):
+        plan = _mixed(torch, mesh, k, a, b, f, sweeps)
+        rp, ci, val = [t.cpu().numpy() for t in plan.csr()]
+        assert np.array_equal(ref.H.indptr, rp) and np.array_equal(ref.H.indices, ci)
+        Hg = sp.csr_matrix((val, ci, rp), shape=ref.H.shape)
+        rg = plan.r().cpu().numpy()
+        u = plan.recover(torch.as_tensor(lam, device="cuda")).cpu().numpy()
+        eH, er = ld_row_errors(Hld, rld, rows, Hg, rg)
+        nH, nr = norm_rel(Hl, Hg.toarray()), norm_rel(rl, rg)
+        eu, nu = rel_inf(ul, u), norm_rel(ul, u)
+        errs[sweeps] = max(eH, er, nH, nr, eu, nu)
+        label = "unrefined" if sweeps == 0 else "refined"
+        print(f"  {label}: vs long double: row-rel H {eH:.1e} r {er:.1e}; normwise H {nH:.1e} r {nr:.1e}; "
+              f"u entrywise {eu:.1e} normwise {nu:.1e}", flush=True)
+    assert errs[None] <= REFINED
+    assert errs[None] < errs[0] <= UNREFINED_MAX
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_mixed_rhs_reuses_factors_bitwise(k):
+    torch = require_gpu()
+    mesh, a, b, f = _problem(k, 2 if k == 3 else 3, 0.2, True, 3100 + k)
+    f2 = np.random.default_rng(10).standard_normal(f.shape)
+    p1 = _mixed(torch, mesh, k, a, b, f)
+    p1.rhs(f2)
+    p2 = _mixed(torch, mesh, k, a, b, f2)
+    torch.cuda.synchronize()
+    assert torch.equal(p1.r().cpu(), p2.r().cpu())
+    assert torch.equal(p1.y_raw().cpu(), p2.y_raw().cpu())
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_mixed_end_to_end_solve(k):
+    torch = require_gpu()
+    mesh, a, b, f = _problem(k, 2 if k == 3 else 3, 0.2, True, 3200 + k)
+    plan = _mixed(torch, mesh, k, a, b, f)
+    lam, info = plan.solve(1e-13, 5000)
+    assert info["converged"]
+    u = plan.recover(lam).cpu().numpy()
+    ref = ohyb.hybridize(k, mesh.xyz, mesh.e2v, a, b, f)
+    lref = ohyb.solve_reduced(ref.H, ref.r)
+    uref = ohyb.recover(ref, mesh.xyz, mesh.e2v, a, b, f, lref)
+    err = rel_inf(uref, u)
+    print(f"k={k}: mixed end to end, u vs oracle {err:.1e} ({info['iters']} PCG iterations)", flush=True)
+    assert err <= 1e-9
+
+
+def test_mixed_argument_errors():
+    require_gpu()
+    from paper_1801_08914_amd import Batch, HybError, Plan
+    mesh = synth.structured_hex(2)
+    with pytest.raises(HybError):
+        Plan(mesh.xyz, mesh.e2v, 1, precision="mixed", sweeps=99)
+    plan = Plan(mesh.xyz, mesh.e2v, 1, precision="mixed").bind()
+    with pytest.raises(HybError):
+        Batch([plan])
