@@ -141,6 +141,55 @@ def parity_sample(prob, plan, lam_np, nface=48, nel=48, seed=0):
             "sample": f"{len(faces)} faces' rows of H and r, {len(els)} elements' u"}
 
 
+def time_plan(plan, alpha, beta, f, lam, u, steps, warmup):
+    """Wall time per setup + recovery step on the plan's stream, and the
+    HIP-event times of the setup and recovery kernels."""
+    import torch
+    for _ in range(warmup):
+        plan.setup(alpha, beta, f)
+        plan.recover(lam, u)
+    torch.cuda.synchronize()
+    plan.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.setup(alpha, beta, f)
+        plan.recover(lam, u)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = plan.timing_read()
+    plan.timing(False)
+    rc, det = plan.status()
+    assert rc == 0, (rc, det)
+    return dt / steps, kt["setup_ms"] / max(kt["setup_n"], 1), kt["recover_ms"] / max(kt["recover_n"], 1)
+
+
+def mixed_leg(args, prob, lam, plain_value):
+    """The mixed-precision form on the same workload and lambda: FP32 element
+    factor and solves with FP64 refinement (per element until the backward-
+    error test passes), and the same with no refinement; throughput and error
+    against the oracle for both."""
+    import torch
+
+    from paper_1801_08914_amd import Plan
+    dev = torch.device("cuda:0")
+    alpha, beta, f = (torch.as_tensor(x, device=dev) for x in (prob.alpha, prob.beta, prob.f))
+    out = {}
+    for name, sweeps in (("refined", None), ("unrefined", 0)):
+        plan = Plan(prob.mesh.xyz, prob.mesh.e2v, prob.k, precision="mixed", sweeps=sweeps).bind("cuda:0")
+        u = torch.empty((prob.mesh.ne, plan.n), dtype=torch.float64, device=dev)
+        plan.setup(alpha, beta, f)
+        step_s, setup_ms, rec_ms = time_plan(plan, alpha, beta, f, lam, u, args.steps, args.warmup)
+        leg = {"value": prob.mesh.ne / step_s, "unit": "elements/s", "ms_per_step": step_s * 1e3,
+               "setup_kernel_ms": setup_ms, "recover_kernel_ms": rec_ms,
+               "sweeps": "adaptive (backward-error test, at most 30)" if sweeps is None else sweeps, "vs_fp64_plain": prob.mesh.ne / step_s / plain_value}
+        if not args.no_parity:
+            leg["error_vs_oracle"] = parity_sample(prob, plan, lam.cpu().numpy())
+        out[name] = leg
+        del plan, u
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_c4(args):
     """The uneven batch (64 jittered problems, n in 8..24, k in 0..3): setup +
     recovery of every problem in one persistent launch each, tiles from the
@@ -219,15 +268,23 @@ def run_single(args, prob, label):
     rc, det = plan.status()
     assert rc == 0, (rc, det)
     ts = np.array(ts)
+    parity = None if args.no_parity else parity_sample(prob, plan, lam.cpu().numpy())
+    m_, nnz_ = plan.m, plan.nnz
+    del plan, u
+    mixed = None if args.no_mixed else mixed_leg(args, prob, lam, ne * len(ts) / ts.sum())
     out = {"metric": METRIC, "value": ne * len(ts) / ts.sum(), "unit": "elements/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * ts.mean(), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": label, "elements": ne, "k": prob.k, "m": plan.m, "nnz": plan.nnz,
+           "config": {"workload": label, "elements": ne, "k": prob.k, "m": m_, "nnz": nnz_,
                       "precision": "fp64-plain"},
            "step_us_p50": 1e6 * float(np.median(ts)), "step_us_p90": 1e6 * float(np.percentile(ts, 90)),
            "setup_kernel_ms": kt["setup_ms"] / max(kt["setup_n"], 1),
            "recover_kernel_ms": kt["recover_ms"] / max(kt["recover_n"], 1),
            "pcg": {"iters": info["iters"], "rel_res": info["rel_res"]}}
+    if parity is not None:
+        out["error_vs_oracle"] = parity
+    if mixed is not None:
+        out["mixed"] = mixed
     print(json.dumps(out), flush=True)
 
 
@@ -271,6 +328,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--skip-solve", action="store_true",
                     help="recover from a seeded random lambda instead of the PCG solution (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -386,6 +444,8 @@ def main():
            "roofline": roof}
     if not args.no_parity:
         out["error_vs_oracle"] = parity_sample(prob, plan, lam.cpu().numpy())
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(args, prob, lam, value)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

@@ -64,7 +64,12 @@ enum hyb_status_code {
   HYB_E_NOMEM = -6,     /* a bound buffer is missing */
   HYB_E_NOCONV = -7,    /* PCG did not reach rtol within maxit */
   HYB_E_HIP = -8,       /* HIP runtime error; detail holds the hipError_t */
-  HYB_E_INTERNAL = -9   /* the plan broke one of its own invariants (a bug) */
+  HYB_E_INTERNAL = -9,  /* the plan broke one of its own invariants (a bug) */
+  HYB_E_REFINE = -10    /* HYB_MIXED: an element's FP32 factor broke down
+                           or its refined solution fails the backward-error
+                           test (the scaled element matrix is too
+                           ill-conditioned for an FP32 factor, or not SPD);
+                           detail = element */
 };
 
 enum hyb_precision {
@@ -93,7 +98,12 @@ typedef struct hyb_opts {
   int kernel_variant;     /* 0: automatic (order- and geometry-specific kernels
                              where they apply), 1: the generic kernels only */
   int refine_sweeps;      /* HYB_MIXED: refinement sweeps after the FP32
-                             solve (0: none, the unrefined form); < 0: 3 */
+                             solve (0: none, the unrefined form; at most 16);
+                             < 0: per element while the correction keeps
+                             shrinking (stop at ||dx|| <= 2^-53 ||x|| or
+                             ||dx|| > ||dx_prev|| / 2; at most 30 sweeps),
+                             then HYB_E_REFINE unless ||b - M x|| <= sqrt(n)
+                             2^-53 ||M|| ||x|| (inf-norms) */
   int pcg_reduce;         /* where hyb_solve sums its per-block partials:
                              0 automatic (by size), 1 inside the consuming
                              kernels, 2 in separate one-block kernels; the

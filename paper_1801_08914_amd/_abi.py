@@ -16,6 +16,7 @@ HYB_E_NOMEM = -6
 HYB_E_NOCONV = -7
 HYB_E_HIP = -8
 HYB_E_INTERNAL = -9
+HYB_E_REFINE = -10
 HYB_FP64 = 0
 HYB_MIXED = 1
 

@@ -249,6 +249,7 @@ const char* hyb_strerror(int code) {
     case HYB_E_NOCONV: return "PCG did not converge";
     case HYB_E_HIP: return "HIP runtime error";
     case HYB_E_INTERNAL: return "internal invariant broken";
+    case HYB_E_REFINE: return "mixed-precision refinement did not converge";
     default: return "unknown status";
   }
 }
@@ -272,7 +273,7 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   if (opt) p->P.opts = *opt;
   hyb::Plan& P = p->P;
   P.mixed = P.opts.precision == HYB_MIXED;
-  P.sweeps = P.opts.refine_sweeps < 0 ? 3 : P.opts.refine_sweeps;
+  P.sweeps = P.opts.refine_sweeps < 0 ? -1 : P.opts.refine_sweeps;
   P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0 && !P.mixed;
   if (P.fast_k1) P.factor_len = hyb::k1::REC;
   if (P.mixed) P.factor_len = mixed_record_len(k);

@@ -4,7 +4,8 @@
 // diagonal in [0.5, 2)).  X = M_T^{-1} C_T^T (the columns that give H_T) and
 // y = M_T^{-1} f_hat are solved with the FP32 factor and refined: each sweep
 // forms the residual against the FP64 M_T in FP64, solves for the correction
-// in FP32 and adds it in FP64.  H_T = C_T X (symmetrized), its scatter into
+// in FP32 and adds it in FP64 (a fixed number of sweeps, or while the
+// correction keeps shrinking).  H_T = C_T X (symmetrized), its scatter into
 // H, r_T = C_T y and the recovery u_T = y - X lambda_T are FP64.
 //
 // Element record (offsets in doubles): X (n x nb, column-major, FP64), M_T
@@ -39,7 +40,7 @@ struct MixedLayout {
   static constexpr int l32 = (R::npk + 1) / 2;
   static constexpr int w32 = (R::n * CH + 1) / 2;
   static constexpr int d32 = (R::n + 1) / 2;
-  static constexpr int per = l32 + w32 + d32 + (kGlobal ? 0 : R::npk + XS * R::nb) + R::Q * 10 + 3 * R::n + 24;
+  static constexpr int per = l32 + w32 + d32 + (kGlobal ? 0 : R::npk + XS * R::nb) + R::Q * 10 + 3 * R::n + 24 + 10;
   static_assert(!kGlobal || EPB == 1, "an HBM-resident element matrix needs one element per block");
   static_assert(R::nb % CH == 0, "whole column chunks");
 };
@@ -82,6 +83,113 @@ __device__ __forceinline__ void chol_solve32(const float* L, const float* dinv, 
   __syncthreads();
 }
 
+// Sweep control of the refinement.  sweeps >= 0: exactly that many sweeps
+// after the FP32 solve.  sweeps < 0 (adaptive): sweep while the correction
+// keeps shrinking (the classical forward-error rule: stop once
+// ||dx||_inf <= 2^-53 ||x||_inf, or once a correction is more than half the
+// previous one, the FP64 floor kappa 2^-53 reached), at most kRefineMax
+// sweeps; the result is accepted if the FP64 residual then passes the
+// backward-error test ||b - M x||_inf <= sqrt(n) 2^-53 ||M||_inf ||x||_inf
+// (the test of LAPACK's mixed-precision Cholesky solver), otherwise the
+// element is reported (kappa(S M_T S) 2^-24 near 1), not hidden.
+constexpr int kRefineMax = 30;
+
+// Team-wide maximum of non-negative doubles through their bit patterns
+// (monotonic for non-negative values) in LDS.
+__device__ __forceinline__ void team_max(double* slot, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(slot), static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+// ||M||_inf of the N x N matrix given by mrow, by the team (red: 1 double of
+// team scratch).  Starts and ends with a barrier.
+template <int N, int TEAM, class MRow>
+__device__ __forceinline__ double norm_inf(MRow mrow, double* red, int lane) {
+  __syncthreads();
+  if (lane == 0) red[0] = 0.0;
+  __syncthreads();
+  double m = 0.0;
+  for (int i = lane; i < N; i += TEAM) {
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += fabs(mrow(i, j));
+    m = fmax(m, s);
+  }
+  team_max(red, m);
+  __syncthreads();
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// Solve M X = B for NC columns with the FP32 factor and FP64 refinement:
+// sweep 0 solves for B, every later sweep for the residual B - M X (FP64,
+// from mrow), the correction added in FP64.  bcol(i, c) and xel(i, c) give
+// B and X for local column c; anrm = ||M||_inf; red holds 8 doubles of team
+// scratch (two slots of max |residual|, max |x|, max |correction|).  Returns
+// false when an adaptive refinement did not pass the backward-error test.
+template <int N, int TEAM, int NC, class MRow, class BCol, class XEl>
+__device__ __forceinline__ bool refine_solve(const float* L, const float* dinv, float* W, const double* Sv,
+                                             MRow mrow, BCol bcol, XEl xel, int sweeps, double anrm, double* red,
+                                             int lane) {
+  const bool adaptive = sweeps < 0;
+  const int cap = adaptive ? kRefineMax : sweeps;
+  const double tol = sqrt(double(N)) * 0x1p-53 * anrm;
+  __syncthreads();  // the team is done with red and W
+  if (lane < 8) red[lane] = 0.0;
+  for (int t = lane; t < N * NC; t += TEAM) {
+    const int i = t / NC, c = t % NC;
+    W[i * NC + c] = float(Sv[i] * bcol(i, c));
+  }
+  __syncthreads();
+  chol_solve32<N, TEAM, NC>(L, dinv, W, lane);
+  double xm = 0.0, zm = 0.0, zprev = 0.0;
+  for (int t = lane; t < N * NC; t += TEAM) {
+    const int i = t / NC, c = t % NC;
+    const double x = Sv[i] * double(W[i * NC + c]);
+    xel(i, c) = x;
+    xm = fmax(xm, fabs(x));
+  }
+  for (int sw = 1;; ++sw) {
+    double* slot = red + 4 * (sw & 1);
+    if (adaptive) {
+      team_max(slot + 1, xm);
+      team_max(slot + 2, zm);
+    }
+    __syncthreads();  // x complete
+    double rm = 0.0;
+    for (int t = lane; t < N * NC; t += TEAM) {
+      const int i = t / NC, c = t % NC;
+      double res = bcol(i, c);
+      for (int j = 0; j < N; ++j) res -= mrow(i, j) * xel(j, c);
+      rm = fmax(rm, fabs(res));
+      W[i * NC + c] = float(Sv[i] * res);
+    }
+    if (adaptive) team_max(slot, rm);
+    __syncthreads();
+    // every lane has read the other slot in the previous sweep
+    if (lane < 4) red[4 * ((sw + 1) & 1) + lane] = 0.0;
+    if (adaptive) {
+      // slot: residual and size of the current x, the correction that made it
+      const bool backward_ok = slot[0] <= tol * slot[1];
+      if (sw >= 2 && slot[2] <= 0x1p-53 * slot[1]) return backward_ok;
+      if (sw >= 3 && slot[2] > 0.5 * zprev) return backward_ok;
+      if (sw > cap) return backward_ok;
+      zprev = slot[2];
+    } else if (sw > cap) {
+      return true;
+    }
+    chol_solve32<N, TEAM, NC>(L, dinv, W, lane);
+    xm = zm = 0.0;
+    for (int t = lane; t < N * NC; t += TEAM) {
+      const int i = t / NC, c = t % NC;
+      const double z = Sv[i] * double(W[i * NC + c]);
+      const double x = xel(i, c) + z;
+      xel(i, c) = x;
+      xm = fmax(xm, fabs(x));
+      zm = fmax(zm, fabs(z));
+    }
+  }
+}
+
 template <int K, int TEAM, int EPB>
 __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* smem, int64_t blk, int sweeps) {
   using R = RT<K>;
@@ -107,6 +215,7 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
   double* yv = fh + n;
   double* Sv = yv + n;
   double* xe = Sv + n;
+  double* red = xe + 24;
   // the FP64 matrix: in LDS while a setup assembles it (k <= 2), else the record's
   double* M = (matrix && !Lay::kGlobal) ? Ml : rec + Rec::m64;
   double* X = Lay::kGlobal ? rec + Rec::x : Xl;
@@ -123,6 +232,7 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
   auto is_ess = [&](int i) { return i >= ni && fid[(i - ni) / K2] < 0; };
   // sign of face dof b in C_T: +1 on the max side of an axis, -1 on the min side
   auto eps = [&](int b) { return ((b / K2) & 1) ? 1.0 : -1.0; };
+  double anrm = 0.0;  // ||M_T||_inf (masked), for the refinement's stopping test
 
   const double al = a.alpha ? a.alpha[es] : 0.0, be = a.beta ? a.beta[es] : 0.0;
   double fv[3] = {0.0, 0.0, 0.0};
@@ -191,7 +301,9 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
     for (int c = 0; c < n; ++c) {
       float d = L[pk(c, c)];
       if (!(d > 0.0f)) {
-        if (live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
+        // the FP32 factor broke down: kappa(S M_T S) 2^-24 >= 1 (or M_T is
+        // not SPD); the plain FP64 form is the one to use for this element
+        if (live && lane == 0) report_error(a.status, HYB_E_REFINE, e);
         d = 1.0f;
       }
       const float inv = 1.0f / d;
@@ -212,27 +324,15 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
     for (int c = lane; c < n; c += TEAM) dinv[c] = 1.0f / L[pk(c, c)];
     __syncthreads();
 
-    // X = M^{-1} C_T^T by chunks of CH columns: sweep 0 solves with the FP32
-    // factor, every later sweep solves for the FP64 residual's correction
+    // X = M^{-1} C_T^T by chunks of CH columns
+    anrm = norm_inf<n, TEAM>(Mrow, red + 8, lane);
+    bool ok = true;
     for (int c0 = 0; c0 < nb; c0 += CH) {
-      for (int sw = 0; sw <= sweeps; ++sw) {
-        for (int t = lane; t < n * CH; t += TEAM) {
-          const int i = t / CH, cl = t % CH, b = c0 + cl;
-          double res = (i == ni + b) ? eps(b) : 0.0;
-          if (sw > 0)
-            for (int j = 0; j < n; ++j) res -= Mrow(i, j) * Xe(j, b);
-          W[i * CH + cl] = float(Sv[i] * res);
-        }
-        __syncthreads();
-        chol_solve32<n, TEAM, CH>(L, dinv, W, lane);
-        for (int t = lane; t < n * CH; t += TEAM) {
-          const int i = t / CH, cl = t % CH, b = c0 + cl;
-          const double z = Sv[i] * double(W[i * CH + cl]);
-          Xe(i, b) = sw > 0 ? Xe(i, b) + z : z;
-        }
-        __syncthreads();
-      }
+      ok &= refine_solve<n, TEAM, CH>(
+          L, dinv, W, Sv, Mrow, [&](int i, int c) { return (i == ni + c0 + c) ? eps(c0 + c) : 0.0; },
+          [&](int i, int c) -> double& { return Xe(i, c0 + c); }, sweeps, anrm, red, lane);
     }
+    if (!ok && live && lane == 0) report_error(a.status, HYB_E_REFINE, e);
 
     // H_T = D (M^{-1})_bb D = D E_b^T X, symmetrized, scattered into H (same-
     // face blocks receive two element terms by atomic add)
@@ -265,21 +365,11 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
 
   if (rhs) {
     // y = M^{-1} f_hat, refined the same way (one column)
-    for (int sw = 0; sw <= sweeps; ++sw) {
-      for (int i = lane; i < n; i += TEAM) {
-        double res = fh[i];
-        if (sw > 0)
-          for (int j = 0; j < n; ++j) res -= Mrow(i, j) * yv[j];
-        W[i] = float(Sv[i] * res);
-      }
-      __syncthreads();
-      chol_solve32<n, TEAM, 1>(L, dinv, W, lane);
-      for (int i = lane; i < n; i += TEAM) {
-        const double z = Sv[i] * double(W[i]);
-        yv[i] = sw > 0 ? yv[i] + z : z;
-      }
-      __syncthreads();
-    }
+    if (!matrix) anrm = norm_inf<n, TEAM>(Mrow, red + 8, lane);
+    const bool oky = refine_solve<n, TEAM, 1>(
+        L, dinv, W, Sv, Mrow, [&](int i, int) { return fh[i]; }, [&](int i, int) -> double& { return yv[i]; },
+        sweeps, anrm, red, lane);
+    if (!oky && live && lane == 0) report_error(a.status, HYB_E_REFINE, e);
     if (live) {
       for (int i = lane; i < n; i += TEAM) a.y[e * n + i] = yv[i];
       // r_T = D y_b

@@ -3,12 +3,17 @@
 The element Cholesky and triangular solves run in FP32 and are refined
 against the FP64 element matrix; H, r and u are FP64.  Against the oracle's
 long-double reference (the exact values to far below FP64 rounding):
-* refined (the default 3 sweeps): H, r and u within 1e-10, normwise and
-  entrywise per row, the stated target of the mixed form;
+* refined (default: per element while the correction keeps shrinking):
+  H, r and u within 1e-10 (or twice the FP64 oracle's own error where that is
+  larger: no FP64 method gets below about kappa 2^-53), normwise and
+  entrywise per row, the stated target of the mixed form, also where a
+  strong div-div term (beta / alpha ~ 1e3, as on the 32^3 RT_1 workload with
+  h = 1/32) makes the FP32 factor converge slowly;
 * unrefined (0 sweeps): the FP32 solve alone, error printed; it must be
-  above the refined error (the sweeps do work) and below 1e-2: an FP32
-  factor leaves an error of about kappa(S M_T S) 2^-24, and the scaled
-  element matrices of these jittered lognormal meshes reach kappa ~ 1e5.
+  above the refined error (the sweeps do work) and below 1e-2, or below
+  4 x 2^29 times the FP64 oracle's error where that is larger: an FP32 factor
+  leaves an error of about kappa(S M_T S) 2^-24, the FP64 oracle one of about
+  kappa 2^-53.
 The right-hand side alone on the stored factors equals a fresh setup bit for
 bit, and a full solve reaches the oracle's solution.
 """
@@ -26,19 +31,21 @@ pytestmark = pytest.mark.gpu
 REFINED = 1e-10
 UNREFINED_MAX = 1e-2
 
+# (k, N, jitter, rotated frames, beta scale)
 CASES = [
-    (0, 4, 0.2, True), (1, 3, 0.0, False), (1, 4, 0.2, True), (2, 2, 0.2, True), (2, 3, 0.2, False),
-    (3, 2, 0.2, True),
+    (0, 4, 0.2, True, 1.0), (1, 3, 0.0, False, 1.0), (1, 4, 0.2, True, 1.0), (1, 3, 0.0, True, 1e3),
+    (2, 2, 0.2, True, 1.0), (2, 3, 0.2, False, 1.0), (2, 2, 0.2, False, 1e2), (3, 2, 0.2, True, 1.0),
 ]
 
 
-def _problem(k, N, jit, rot, seed):
+def _problem(k, N, jit, rot, seed, beta_scale=1.0):
     rng = np.random.default_rng(seed)
     mesh = synth.structured_hex(N, jitter=jit, rng=rng)
     if rot:
         mesh, _ = synth.rotate_connectivity(mesh, rng)
     ne = mesh.ne
-    return mesh, synth.lognormal(rng, ne), synth.lognormal(rng, ne, 0.5), synth.element_loads(rng, ne)
+    return (mesh, synth.lognormal(rng, ne), beta_scale * synth.lognormal(rng, ne, 0.5),
+            synth.element_loads(rng, ne))
 
 
 def _mixed(torch, mesh, k, a, b, f, sweeps=None):
@@ -51,11 +58,11 @@ def _mixed(torch, mesh, k, a, b, f, sweeps=None):
     return plan
 
 
-@pytest.mark.parametrize("k,N,jit,rot", CASES)
-def test_mixed_H_r_u_refined_and_unrefined(k, N, jit, rot):
+@pytest.mark.parametrize("k,N,jit,rot,bscale", CASES)
+def test_mixed_H_r_u_refined_and_unrefined(k, N, jit, rot, bscale):
     torch = require_gpu()
-    print(f"case k={k} N={N} jitter={jit} rotate={rot}", flush=True)
-    mesh, a, b, f = _problem(k, N, jit, rot, 3000 + 10 * k + N)
+    print(f"case k={k} N={N} jitter={jit} rotate={rot} beta x {bscale:g}", flush=True)
+    mesh, a, b, f = _problem(k, N, jit, rot, 3000 + 10 * k + N, bscale)
     ref = ohyb.hybridize(k, mesh.xyz, mesh.e2v, a, b, f)
     lam = np.random.default_rng(8).standard_normal(ref.r.size)
     Hld, rld, U = oext.hybridize_ld(k, mesh.xyz, mesh.e2v, a, b, f, ref.topo, np.arange(mesh.ne), lam)
@@ -77,8 +84,16 @@ def test_mixed_H_r_u_refined_and_unrefined(k, N, jit, rot):
         label = "unrefined" if sweeps == 0 else "refined"
         print(f"  {label}: vs long double: row-rel H {eH:.1e} r {er:.1e}; normwise H {nH:.1e} r {nr:.1e}; "
               f"u entrywise {eu:.1e} normwise {nu:.1e}", flush=True)
-    assert errs[None] <= REFINED
-    assert errs[None] < errs[0] <= UNREFINED_MAX
+    # the FP64 oracle's own error on the same entries: where kappa(M_T) is
+    # large no FP64 method gets below about kappa 2^-53
+    eHo, ero = ld_row_errors(Hld, rld, rows, ref.H, ref.r)
+    uo = ohyb.recover(ref, mesh.xyz, mesh.e2v, a, b, f, lam)
+    eo = max(eHo, ero, norm_rel(Hl, ref.H.toarray()), norm_rel(rl, ref.r), rel_inf(ul, uo), norm_rel(ul, uo))
+    print(f"  FP64 oracle vs long double: {eo:.1e}", flush=True)
+    assert errs[None] <= max(REFINED, 2.0 * eo)
+    # unrefined: about kappa 2^-24 = (kappa 2^-53) 2^29, kappa 2^-53 read off
+    # the oracle's error (factor 4 for the constants)
+    assert errs[None] < errs[0] <= max(UNREFINED_MAX, 4.0 * 2.0**29 * eo)
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
@@ -108,6 +123,24 @@ def test_mixed_end_to_end_solve(k):
     err = rel_inf(uref, u)
     print(f"k={k}: mixed end to end, u vs oracle {err:.1e} ({info['iters']} PCG iterations)", flush=True)
     assert err <= 1e-9
+
+
+def test_mixed_reports_what_fp32_cannot_factor():
+    """beta / alpha ~ 1e6 on RT_2: kappa(S M_T S) 2^-24 > 1, the FP32 factor
+    breaks down; the mixed form reports HYB_E_REFINE with the element, the
+    plain FP64 form handles the same input."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Plan
+    from paper_1801_08914_amd._abi import HYB_E_REFINE
+    mesh, a, b, f = _problem(2, 2, 0.2, False, 3300, 1e6)
+    pm = Plan(mesh.xyz, mesh.e2v, 2, precision="mixed").bind()
+    pm.setup(a, b, f)
+    rc, det = pm.status()
+    print(f"mixed: status {rc}, element {det}", flush=True)
+    assert rc == HYB_E_REFINE and 0 <= det < mesh.ne
+    pp = Plan(mesh.xyz, mesh.e2v, 2).bind()
+    pp.setup(a, b, f)
+    assert pp.status()[0] == 0
 
 
 def test_mixed_argument_errors():
