@@ -243,10 +243,14 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
   element_qd<K, TEAM>(mp, es, al, be, fv, need_matrix, rhs, xe, qd, lane, live, a.status, e);
 
   if (matrix) {
-    for (int p = lane; p < R::npk; p += TEAM) {
-      int i, j;
-      unpk_f(p, i, j);
-      M[p] = m_entry<K>(mp, qd, i, j);
+    if constexpr (TEAM % 64 == 0) {
+      assemble_mfma<K, TEAM>(mp, qd, lane, [&](int i, int j, double v) { M[pk(i, j)] = v; });
+    } else {
+      for (int p = lane; p < R::npk; p += TEAM) {
+        int i, j;
+        unpk_f(p, i, j);
+        M[p] = m_entry<K>(mp, qd, i, j);
+      }
     }
     __syncthreads();
   } else {

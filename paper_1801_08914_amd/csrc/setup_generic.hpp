@@ -5,6 +5,7 @@
 #pragma once
 
 #include "kernels_common.hpp"
+#include "mfma.hpp"
 
 namespace hyb {
 
@@ -33,12 +34,6 @@ struct RecoverArgs {
   const double* lambda;
   double* u;
 };
-
-// index of the symmetric 3x3 pair (d, e) in (00, 01, 02, 11, 12, 22)
-__device__ __forceinline__ int gidx(int d, int e) {
-  int lo = d < e ? d : e, hi = d < e ? e : d;
-  return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
-}
 
 // Per-element LDS layout.  From k = 3 on the packed element matrix (231 KB)
 // does not fit in LDS: it is then assembled and factored in place in its
@@ -175,10 +170,14 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   // must not overwrite it, and computes the entries it needs directly)
   const bool store_matrix = need_matrix && (!Lay::kGlobal || (a.mode & MODE_MATRIX));
   if (store_matrix) {
-    for (int p = lane; p < R::npk; p += TEAM) {
-      int i, j;
-      unpk(p, i, j);
-      A[p] = mij(i, j);
+    if constexpr (TEAM % 64 == 0) {
+      assemble_mfma<K, TEAM>(mp, qd, lane, [&](int i, int j, double v) { A[pk(i, j)] = v; });
+    } else {
+      for (int p = lane; p < R::npk; p += TEAM) {
+        int i, j;
+        unpk(p, i, j);
+        A[p] = mij(i, j);
+      }
     }
     __syncthreads();
   }
