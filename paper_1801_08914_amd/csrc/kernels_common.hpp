@@ -27,13 +27,24 @@ struct RT {
 // Packed row-major lower triangle index, j <= i.
 __device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// Inverse of pk: linear index t -> (i, j) with j <= i.
+// Inverse of pk: linear index t -> (i, j) with j <= i (an FP32 estimate,
+// exact after the correction steps for t < 2^24).
 __device__ __forceinline__ void unpk(int t, int& i, int& j) {
-  int r = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
   while (r * (r + 1) / 2 > t) --r;
   while ((r + 1) * (r + 2) / 2 <= t) ++r;
   i = r;
   j = t - r * (r + 1) / 2;
+}
+
+// Advance a packed lower-triangle position (i, j) by d entries (row i holds
+// i + 1 entries): the incremental form of unpk for strided loops.
+__device__ __forceinline__ void pk_advance(int& i, int& j, int d) {
+  j += d;
+  while (j > i) {
+    j -= i + 1;
+    ++i;
+  }
 }
 
 // Neighbour frame -> owner frame on face dof indices (j0, j1) in 0..K:

@@ -40,7 +40,10 @@ struct MixedLayout {
   static constexpr int l32 = (R::npk + 1) / 2;
   static constexpr int w32 = (R::n * CH + 1) / 2;
   static constexpr int d32 = (R::n + 1) / 2;
+  // the assembly stages its tables in W (free until the solves): QC points
+  static constexpr int QC = (2 * w32) / (4 * R::n) >= 1 ? (2 * w32) / (4 * R::n) : 1;
   static constexpr int per = l32 + w32 + d32 + (kGlobal ? 0 : R::npk + XS * R::nb) + R::Q * 10 + 3 * R::n + 24 + 10;
+  static_assert(2 * R::n * QC <= w32, "assembly staging fits in W");
   static_assert(!kGlobal || EPB == 1, "an HBM-resident element matrix needs one element per block");
   static_assert(R::nb % CH == 0, "whole column chunks");
 };
@@ -244,7 +247,8 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
 
   if (matrix) {
     if constexpr (TEAM % 64 == 0) {
-      assemble_mfma<K, TEAM>(mp, qd, lane, [&](int i, int j, double v) { M[pk(i, j)] = v; });
+      assemble_mfma<K, TEAM, Lay::QC>(mp, qd, reinterpret_cast<double*>(W), lane,
+                                      [&](int i, int j, double v) { M[pk(i, j)] = v; });
     } else {
       for (int p = lane; p < R::npk; p += TEAM) {
         int i, j;
@@ -311,13 +315,30 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
         d = 1.0f;
       }
       const float inv = 1.0f / d;
-      const int m1 = n - c - 1;
-      const int tri = m1 * (m1 + 1) / 2;
-      for (int t = lane; t < tri; t += TEAM) {
-        int ii, jj;
-        unpk_f(t, ii, jj);
-        const int i = c + 1 + ii, j = c + 1 + jj;
-        L[pk(i, j)] -= L[pk(i, c)] * (L[pk(j, c)] * inv);
+      // trailing update by rows: S lanes per row (see the FP64 kernel)
+      constexpr int S = TEAM / n > 0 ? TEAM / n : 1;
+      for (int i = c + 1 + lane / S; i < n && lane / S < TEAM / S; i += TEAM / S) {
+        float* Li = L + i * (i + 1) / 2;
+        const float lic = Li[c] * inv;
+        int j = c + 1 + lane % S;
+        int pjc = j * (j + 1) / 2 + c;
+        for (; j + 3 * S <= i; j += 4 * S) {
+          float lc4[4], li4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            lc4[u] = L[pjc];
+            li4[u] = Li[j + u * S];
+#pragma unroll
+            for (int s = 1; s <= S; ++s) pjc += j + u * S + s;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) Li[j + u * S] = li4[u] - lic * lc4[u];
+        }
+        for (; j <= i; j += S) {
+          Li[j] -= lic * L[pjc];
+#pragma unroll
+          for (int s = 1; s <= S; ++s) pjc += j + s;
+        }
       }
       __syncthreads();
       const float sq = sqrtf(d), is = 1.0f / sq;

@@ -44,7 +44,8 @@ struct GenericLayout {
   using R = RT<K>;
   static constexpr bool kGlobal = K >= 3;
   static constexpr int QD = 10;  // per-qp: 6 weighted metric terms, div weight, 3 load weights
-  static constexpr int per = (kGlobal ? 0 : R::npk + R::nbpk) + R::Q * QD + R::n + 24 + R::nb;
+  static constexpr int stage = TEAM % 64 == 0 ? 2 * R::n * kAsmQC : 0;   // assembly tables
+  static constexpr int per = (kGlobal ? 0 : R::npk + R::nbpk) + R::Q * QD + R::n + 24 + R::nb + stage;
 };
 
 // Geometry at the Gauss points of one element (team of TEAM lanes): the
@@ -136,6 +137,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   double* fh = qd + Q * QD;
   double* xe = fh + n;
   double* tb = xe + 24;
+  double* stg = tb + nb;
   // packed inverse of the face block: its own LDS array, or (global matrix)
   // the face block of A, inverted in place
   auto LI = [&](int i, int j) -> double& { return Lay::kGlobal ? A[pk(ni + i, ni + j)] : Li[pk(i, j)]; };
@@ -171,7 +173,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   const bool store_matrix = need_matrix && (!Lay::kGlobal || (a.mode & MODE_MATRIX));
   if (store_matrix) {
     if constexpr (TEAM % 64 == 0) {
-      assemble_mfma<K, TEAM>(mp, qd, lane, [&](int i, int j, double v) { A[pk(i, j)] = v; });
+      assemble_mfma<K, TEAM, kAsmQC>(mp, qd, stg, lane, [&](int i, int j, double v) { A[pk(i, j)] = v; });
     } else {
       for (int p = lane; p < R::npk; p += TEAM) {
         int i, j;
@@ -218,13 +220,32 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
         d = 1.0;
       }
       const double inv = 1.0 / d;
-      const int m1 = n - c - 1;
-      const int tri = m1 * (m1 + 1) / 2;
-      for (int t = lane; t < tri; t += TEAM) {
-        int ii, jj;
-        unpk(t, ii, jj);
-        const int i = c + 1 + ii, j = c + 1 + jj;
-        A[pk(i, j)] -= A[pk(i, c)] * (A[pk(j, c)] * inv);
+      // trailing update by rows: S lanes per row, lane h of a row takes the
+      // columns c+1+h, c+1+h+S, ... (no packed-index arithmetic per entry)
+      constexpr int S = TEAM / n > 0 ? TEAM / n : 1;
+      for (int i = c + 1 + lane / S; i < n && lane / S < TEAM / S; i += TEAM / S) {
+        double* Ai = A + i * (i + 1) / 2;
+        const double aic = Ai[c] * inv;
+        int j = c + 1 + lane % S;
+        int pjc = j * (j + 1) / 2 + c;
+        // four columns at a time, loads first (row i and column c never alias)
+        for (; j + 3 * S <= i; j += 4 * S) {
+          double lc4[4], ai4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            lc4[u] = A[pjc];
+            ai4[u] = Ai[j + u * S];
+#pragma unroll
+            for (int s = 1; s <= S; ++s) pjc += j + u * S + s;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) Ai[j + u * S] = ai4[u] - aic * lc4[u];
+        }
+        for (; j <= i; j += S) {
+          Ai[j] -= aic * A[pjc];
+#pragma unroll
+          for (int s = 1; s <= S; ++s) pjc += j + s;
+        }
       }
       __syncthreads();
       const double sq = sqrt(d), is = 1.0 / sq;
