@@ -85,6 +85,15 @@ enum hyb_precision {
                            f_hat_T in the y buffer) */
 };
 
+/* Reduced system a plan assembles (Sec. 3.1 of the paper: hybridization
+ * assembles the inverses of the element Schur complements onto the face
+ * multipliers, static condensation the complements themselves onto the face
+ * dofs, S = [I; W]^T S_hat [I; W] with W = -I for outward-flux copies). */
+enum hyb_system {
+  HYB_HYBRID = 0,
+  HYB_STATIC = 1
+};
+
 typedef struct hyb_mesh {
   int64_t nv;             /* number of vertices */
   int64_t ne;             /* number of hexahedra */
@@ -108,6 +117,11 @@ typedef struct hyb_opts {
                              0 automatic (by size), 1 inside the consuming
                              kernels, 2 in separate one-block kernels; the
                              results are the same bits either way */
+  int system;             /* HYB_HYBRID: the multiplier system H lambda = r
+                             (default); HYB_STATIC: the static condensation
+                             S x = r on the same face dofs (x = the owner's
+                             outward flux), with the same CSR pattern, solve
+                             and recovery calls (HYB_FP64, generic kernels) */
 } hyb_opts;
 
 /* Sizes of the caller-owned device buffers, filled by hyb_plan_create. */
@@ -276,8 +290,8 @@ typedef struct {
 } hyb_batch_tiles;
 
 /* plans: count bound plans (the batch keeps pointers, it does not own them),
- * launched on plans[0]'s stream.  Errors: HYB_E_ARG (also for a HYB_MIXED
- * plan: batches run the FP64 element kernels), HYB_E_STATE (unbound),
+ * launched on plans[0]'s stream.  Errors: HYB_E_ARG (also for a HYB_MIXED or
+ * HYB_STATIC plan: batches run the FP64 hybridization kernels), HYB_E_STATE (unbound),
  * HYB_E_NOMEM, HYB_E_HIP. */
 int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out);
 

@@ -37,7 +37,8 @@ class Plan:
     """One hybridization problem: mesh + order, its topology and device buffers."""
 
     def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None, generic: bool = False,
-                 pcg_reduce: int = 0, precision: str = "fp64", sweeps: int | None = None):
+                 pcg_reduce: int = 0, precision: str = "fp64", sweeps: int | None = None,
+                 system: str = "hybrid"):
         lib = load_library()
         self._lib = lib
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -49,10 +50,13 @@ class Plan:
         self._stream_obj = stream
         if precision not in ("fp64", "mixed"):
             raise ValueError(f"precision must be 'fp64' or 'mixed', not {precision!r}")
-        self.precision = precision
+        if system not in ("hybrid", "static"):
+            raise ValueError(f"system must be 'hybrid' or 'static', not {system!r}")
+        self.precision, self.system = precision, system
         opts = _abi.HybOpts(_abi.HYB_MIXED if precision == "mixed" else _abi.HYB_FP64,
                             ctypes.c_void_p(self._stream_handle()), 1 if generic else 0,
-                            -1 if sweeps is None else int(sweeps), int(pcg_reduce))
+                            -1 if sweeps is None else int(sweeps), int(pcg_reduce),
+                            _abi.HYB_STATIC if system == "static" else _abi.HYB_HYBRID)
         self._plan = ctypes.c_void_p()
         sz = _abi.HybSizes()
         rc = lib.hyb_plan_create(ctypes.byref(mesh), self.k, ctypes.byref(opts), ctypes.byref(self._plan),

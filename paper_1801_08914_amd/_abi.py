@@ -19,6 +19,8 @@ HYB_E_INTERNAL = -9
 HYB_E_REFINE = -10
 HYB_FP64 = 0
 HYB_MIXED = 1
+HYB_HYBRID = 0
+HYB_STATIC = 1
 
 # Every extern "C" symbol declared in include/hyb.h.
 EXPORTS = [
@@ -48,7 +50,7 @@ class HybMesh(ctypes.Structure):
 
 class HybOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("kernel_variant", ctypes.c_int),
-                ("refine_sweeps", ctypes.c_int), ("pcg_reduce", ctypes.c_int)]
+                ("refine_sweeps", ctypes.c_int), ("pcg_reduce", ctypes.c_int), ("system", ctypes.c_int)]
 
 
 class HybSizes(ctypes.Structure):

@@ -259,7 +259,9 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   if (!out) return HYB_E_ARG;
   *out = nullptr;
   if (opt && ((opt->precision != HYB_FP64 && opt->precision != HYB_MIXED) || opt->pcg_reduce < 0 ||
-              opt->pcg_reduce > 2 || opt->refine_sweeps > 16))
+              opt->pcg_reduce > 2 || opt->refine_sweeps > 16 ||
+              (opt->system != HYB_HYBRID && opt->system != HYB_STATIC) ||
+              (opt->system == HYB_STATIC && opt->precision != HYB_FP64)))
     return HYB_E_ARG;
   hyb_plan* p = new (std::nothrow) hyb_plan;
   if (!p) return HYB_E_NOMEM;
@@ -273,8 +275,9 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   if (opt) p->P.opts = *opt;
   hyb::Plan& P = p->P;
   P.mixed = P.opts.precision == HYB_MIXED;
+  P.stat = P.opts.system == HYB_STATIC;
   P.sweeps = P.opts.refine_sweeps < 0 ? -1 : P.opts.refine_sweeps;
-  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0 && !P.mixed;
+  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0 && !P.mixed && !P.stat;
   if (P.fast_k1) P.factor_len = hyb::k1::REC;
   if (P.mixed) P.factor_len = mixed_record_len(k);
   // PCG grids, multiples of the 8 XCDs: vector kernels about one row per
@@ -403,6 +406,7 @@ int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta, const d
   a.r = P.buf.r;
   a.status = P.buf.status;
   a.mode = hyb::MODE_MATRIX | (f ? hyb::MODE_RHS : 0);
+  a.stat = P.stat ? 1 : 0;
   mark(P, P.ev_setup);
   int rc = HYB_OK;
   if (P.fast_k1) {
@@ -461,6 +465,7 @@ int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g) {
     a.r = P.buf.r;
     a.status = P.buf.status;
     a.mode = hyb::MODE_RHS;
+    a.stat = P.stat ? 1 : 0;
     rc = P.mixed ? dispatch_setup_mixed(P.ord.k, a, P.sweeps, s) : dispatch_setup(P.ord.k, a, s);
   }
   if (rc) return rc;
@@ -561,6 +566,7 @@ int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u) {
   a.y = P.buf.y;
   a.lambda = lambda;
   a.u = u;
+  a.stat = P.stat ? 1 : 0;
   mark(P, P.ev_recover);
   int rc = HYB_OK;
   if (P.fast_k1) {
@@ -796,7 +802,7 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
     if (!plans[i]) return HYB_E_ARG;
   for (int32_t i = 0; i < count; ++i) {
     if (!plans[i]->P.bound) return HYB_E_STATE;
-    if (plans[i]->P.mixed) return HYB_E_ARG;   // batches run the FP64 element kernels
+    if (plans[i]->P.mixed || plans[i]->P.stat) return HYB_E_ARG;   // FP64 hybridization only
   }
   hyb_batch* b = new (std::nothrow) hyb_batch;
   if (!b) return HYB_E_NOMEM;

@@ -69,6 +69,7 @@ struct Plan {
   bool all_affine = false;            // every element is a parallelepiped
   bool fast_k1 = false;               // RT_1 affine kernels (own factor record layout)
   bool mixed = false;                 // HYB_MIXED element kernels (own factor record layout)
+  bool stat = false;                  // HYB_STATIC: static condensation S instead of H
   int sweeps = 0;                     // HYB_MIXED refinement sweeps
   // reference tables at the Gauss points (axis 0 fastest)
   std::vector<double> tab_s;        // Q x n: basis value (its only nonzero component)

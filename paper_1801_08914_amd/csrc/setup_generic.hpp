@@ -24,6 +24,7 @@ struct SetupArgs {
   double* r;
   int32_t* status;
   int mode;
+  int stat;              // 1: static condensation (S, its load) instead of H, r
 };
 
 struct RecoverArgs {
@@ -31,8 +32,9 @@ struct RecoverArgs {
   int64_t ne;
   const double* factor;
   const double* y;
-  const double* lambda;
+  const double* lambda;  // multipliers, or (static condensation) the face dofs
   double* u;
+  int stat;
 };
 
 // Per-element LDS layout.  From k = 3 on the packed element matrix (231 KB)
@@ -120,6 +122,11 @@ __device__ __forceinline__ double m_entry(const DeviceMaps& mp, const double* qd
 // Local assembly (Gauss quadrature), essential-face masking, packed
 // Cholesky in i-first order, inversion of the face block, H_T scatter, and
 // the right-hand side y = L^{-1} f_hat, r_T = D L_bb^{-T} y_b.
+// Static condensation (a.stat): the element Schur complement
+// S_hat_T = A_bb - A_bi A_ii^{-1} A_ib = L_bb L_bb^T is scattered instead,
+// each face-dof copy signed by sigma = eps_f (owner) or -eps_f (neighbour),
+// the global face dof being the owner's outward flux, with the load
+// sigma (f_b - L_bi L_ii^{-1} f_i); the face block is not inverted.
 template <int K, int TEAM, int EPB>
 __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* smem, int64_t blk) {
   using R = RT<K>;
@@ -150,6 +157,12 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     pic[f] = mp.elem_pi[es * 8 + f];
   }
   auto is_ess = [&](int i) { return i >= ni && fid[(i - ni) / K2] < 0; };
+  // static condensation: sign of face dof b's copy of the owner's outward flux
+  auto sigma = [&](int b) {
+    const int f = b / K2;
+    const double eps = (f & 1) ? 1.0 : -1.0;
+    return mp.face_owner[fid[f]] == e ? eps : -eps;
+  };
 
   const double al = a.alpha ? a.alpha[es] : 0.0, be = a.beta ? a.beta[es] : 0.0;
   double fv[3] = {0.0, 0.0, 0.0};
@@ -253,7 +266,36 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       if (lane == 0) A[pk(c, c)] = sq;
     }
     __syncthreads();
-    if constexpr (!Lay::kGlobal) {
+    if (a.stat) {
+      // S_hat_T = L_bb L_bb^T (lower triangle), sigma-signed, into S
+      if (live) {
+        for (int t = lane; t < R::nbpk; t += TEAM) {
+          int aa, bb;
+          unpk(t, aa, bb);
+          const int fa = aa / K2, fb = bb / K2;
+          if (fid[fa] < 0 || fid[fb] < 0) continue;
+          double h = 0.0;
+          for (int c = 0; c <= bb; ++c) h += A[pk(ni + aa, ni + c)] * A[pk(ni + bb, ni + c)];
+          const double v = sigma(aa) * sigma(bb) * h;
+          int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
+          frame_map(pic[fa], K, a0, a1);
+          frame_map(pic[fb], K, b0, b1);
+          const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
+          const int Fa = fid[fa], Fb = fid[fb];
+          const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
+                              mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
+          const int64_t pba = mp.face_rowbase[Fb] + int64_t(jb) * mp.face_nslots[Fb] * K2 +
+                              mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
+          if (fa == fb) {
+            atomicAdd(&a.Hval[pab], v);
+            if (aa != bb) atomicAdd(&a.Hval[pba], v);
+          } else {
+            a.Hval[pab] = v;
+            a.Hval[pba] = v;
+          }
+        }
+      }
+    } else if constexpr (!Lay::kGlobal) {
       // Inverse of the face block L_bb, one column per thread.
       for (int col = lane; col < nb; col += TEAM) {
         Li[pk(col, col)] = 1.0 / A[pk(ni + col, ni + col)];
@@ -285,7 +327,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     __syncthreads();
     // H_T = D L_bb^{-T} L_bb^{-1} D, scattered into H (lower triangle computed,
     // mirrored; same-face blocks receive two element terms by atomic add).
-    if (live) {
+    if (live && !a.stat) {
       for (int t = lane; t < R::nbpk; t += TEAM) {
         int aa, bb;
         unpk(t, aa, bb);
@@ -341,21 +383,30 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       tb[b] = s;
     }
     __syncthreads();
+    // static condensation keeps f_b - L_bi y_i (on boundary faces: their data g)
     for (int b = lane; b < nb; b += TEAM) {
-      double s = 0.0;
-      for (int c = 0; c <= b; ++c) s += LI(b, c) * tb[c];
+      double s = tb[b];
+      if (!a.stat) {
+        s = 0.0;
+        for (int c = 0; c <= b; ++c) s += LI(b, c) * tb[c];
+      }
       fh[ni + b] = s;
     }
     __syncthreads();
     if (live) {
       for (int i = lane; i < n; i += TEAM) a.y[e * n + i] = fh[i];
-      // r_T = D L_bb^{-T} y_b
+      // r_T = D L_bb^{-T} y_b, or (static condensation) sigma (f_b - L_bi y_i)
       for (int b = lane; b < nb; b += TEAM) {
         const int fb = b / K2;
         if (fid[fb] < 0) continue;
-        double s = 0.0;
-        for (int c = b; c < nb; ++c) s += LI(c, b) * fh[ni + c];
-        if (!(fb & 1)) s = -s;
+        double s;
+        if (a.stat) {
+          s = sigma(b) * fh[ni + b];
+        } else {
+          s = 0.0;
+          for (int c = b; c < nb; ++c) s += LI(c, b) * fh[ni + c];
+          if (!(fb & 1)) s = -s;
+        }
         int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
         frame_map(pic[fb], K, b0, b1);
         atomicAdd(&a.r[int64_t(fid[fb]) * K2 + b0 + K1 * b1], s);
@@ -368,7 +419,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       for (int p = lane; p < R::npk; p += TEAM) {
         int i, j;
         unpk(p, i, j);
-        a.factor[e * R::npk + p] = (i >= ni && j >= ni) ? Li[pk(i - ni, j - ni)] : A[p];
+        a.factor[e * R::npk + p] = (i >= ni && j >= ni && !a.stat) ? Li[pk(i - ni, j - ni)] : A[p];
       }
     }
   }
@@ -380,7 +431,8 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
   setup_generic_body<K, TEAM, EPB>(a, smem, blockIdx.x);
 }
 
-// u_T = L^{-T} (y - [0; L_bb^{-1} D lambda_b]) from the stored factor.
+// u_T = L^{-T} (y - [0; L_bb^{-1} D lambda_b]) from the stored factor; with
+// static condensation u_b = sigma x_b and u_i = L_ii^{-T} (y_i - L_bi^T u_b).
 template <int K>
 constexpr int recover_per() { return 2 * RT<K>::n + RT<K>::nb; }
 
@@ -407,23 +459,33 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
       int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
       frame_map(mp.elem_pi[es * 8 + fb], K, b0, b1);
       v = a.lambda[int64_t(F_) * K2 + b0 + K1 * b1];
-      if (!(fb & 1)) v = -v;
+      if (a.stat) {
+        // u_b = sigma x: the face dof is the owner's outward flux
+        const double eps = (fb & 1) ? 1.0 : -1.0;
+        v = mp.face_owner[F_] == es ? eps * v : -eps * v;
+      } else if (!(fb & 1)) {
+        v = -v;
+      }
+    } else if (a.stat) {
+      v = yv[ni + b];  // boundary data
     }
     tl[b] = v;
   }
   __syncthreads();
-  for (int b = lane; b < nb; b += TEAM) {
-    double s = yv[ni + b];
-    for (int c = 0; c <= b; ++c) s -= F[pk(ni + b, ni + c)] * tl[c];
-    zb[b] = s;
+  if (!a.stat) {
+    for (int b = lane; b < nb; b += TEAM) {
+      double s = yv[ni + b];
+      for (int c = 0; c <= b; ++c) s -= F[pk(ni + b, ni + c)] * tl[c];
+      zb[b] = s;
+    }
+    __syncthreads();
+    for (int b = lane; b < nb; b += TEAM) {
+      double s = 0.0;
+      for (int c = b; c < nb; ++c) s += F[pk(ni + c, ni + b)] * zb[c];
+      tl[b] = s;  // u_b
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int b = lane; b < nb; b += TEAM) {
-    double s = 0.0;
-    for (int c = b; c < nb; ++c) s += F[pk(ni + c, ni + b)] * zb[c];
-    tl[b] = s;  // u_b
-  }
-  __syncthreads();
   for (int j = lane; j < ni; j += TEAM) {
     double s = yv[j];
     for (int b = 0; b < nb; ++b) s -= F[pk(ni + b, j)] * tl[b];
