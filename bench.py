@@ -190,6 +190,34 @@ def mixed_leg(args, prob, lam, plain_value):
     return out
 
 
+def static_leg(args, prob, plain_value, u_hyb):
+    """Static condensation (Sec. 3.1) on the same workload: setup of S and its
+    load + recovery throughput, the PCG iterations on S (against those on H)
+    and the distance of its u from the hybridized u."""
+    import torch
+
+    from paper_1801_08914_amd import Plan
+    dev = torch.device("cuda:0")
+    alpha, beta, f = (torch.as_tensor(x, device=dev) for x in (prob.alpha, prob.beta, prob.f))
+    plan = Plan(prob.mesh.xyz, prob.mesh.e2v, prob.k, system="static").bind("cuda:0")
+    plan.setup(alpha, beta, f)
+    t0 = time.perf_counter()
+    x, info = plan.solve(1e-12, 20000)
+    torch.cuda.synchronize()
+    pcg_ms = (time.perf_counter() - t0) * 1e3
+    u = torch.empty((prob.mesh.ne, plan.n), dtype=torch.float64, device=dev)
+    step_s, setup_ms, rec_ms = time_plan(plan, alpha, beta, f, x, u, args.steps, args.warmup)
+    uh = u_hyb.cpu().numpy()
+    du = float(np.abs(u.cpu().numpy() - uh).max() / np.abs(uh).max())
+    out = {"value": prob.mesh.ne / step_s, "unit": "elements/s", "ms_per_step": step_s * 1e3,
+           "setup_kernel_ms": setup_ms, "recover_kernel_ms": rec_ms, "vs_hybridization": prob.mesh.ne / step_s / plain_value,
+           "pcg": {"iters": info["iters"], "rel_res": info["rel_res"], "ms": pcg_ms},
+           "u_vs_hybridized_rel": du}
+    del plan, u
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_c4(args):
     """The uneven batch (64 jittered problems, n in 8..24, k in 0..3): setup +
     recovery of every problem in one persistent launch each, tiles from the
@@ -270,8 +298,10 @@ def run_single(args, prob, label):
     ts = np.array(ts)
     parity = None if args.no_parity else parity_sample(prob, plan, lam.cpu().numpy())
     m_, nnz_ = plan.m, plan.nnz
+    value = ne * len(ts) / ts.sum()
+    stat = None if args.no_static else static_leg(args, prob, value, plan.recover(lam))
     del plan, u
-    mixed = None if args.no_mixed else mixed_leg(args, prob, lam, ne * len(ts) / ts.sum())
+    mixed = None if args.no_mixed else mixed_leg(args, prob, lam, value)
     out = {"metric": METRIC, "value": ne * len(ts) / ts.sum(), "unit": "elements/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * ts.mean(), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -285,6 +315,8 @@ def run_single(args, prob, label):
         out["error_vs_oracle"] = parity
     if mixed is not None:
         out["mixed"] = mixed
+    if stat is not None:
+        out["static_condensation"] = stat
     print(json.dumps(out), flush=True)
 
 
@@ -329,6 +361,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-static", action="store_true", help="skip the static-condensation leg")
     ap.add_argument("--skip-solve", action="store_true",
                     help="recover from a seeded random lambda instead of the PCG solution (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -446,6 +479,8 @@ def main():
         out["error_vs_oracle"] = parity_sample(prob, plan, lam.cpu().numpy())
     if not args.no_mixed:
         out["mixed"] = mixed_leg(args, prob, lam, value)
+    if not args.no_static:
+        out["static_condensation"] = static_leg(args, prob, value, u)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
