@@ -205,3 +205,52 @@ def serving_requests(nreq: int, qps: float, seed: int = 5, nmin: int = 16, nmax:
         alpha = 1.0 / sigma
         fs = [element_loads(rng, ne) for _ in range(R)]
         yield t, Problem(f"req{r}_rt{k}_{n}", mesh, k, alpha, np.ones(ne), fs[0]), fs
+
+
+# The paper's soft-hard materials test (Sec. 6.1): the unit cube, the two
+# inclusion cubes [1/4,1/2]^3 and [1/2,3/4]^3, and the initial meshes of its
+# weak-scaling runs per order (equal problem sizes across orders).
+SOFTHARD_MESHES = {0: (64, 64, 32), 1: (32, 32, 16), 3: (16, 16, 8)}
+SOFTHARD_EXPONENTS = (-8, -4, 0, 4, 8)
+
+
+def config_softhard(k: int, p: int, dims: tuple[int, int, int] | None = None) -> Problem:
+    """Soft-hard materials: the mass coefficient alpha = 10^p on elements whose
+    centroid lies in the inclusions and 1 elsewhere, the div-div coefficient
+    beta = 1, the load f = (1, 1, 1) (no random draws); mesh ``dims`` (default
+    the paper's initial mesh for order k, structured on the unit cube)."""
+    dims = dims or SOFTHARD_MESHES[k]
+    mesh = structured_hex(0, dims=dims)
+    c = mesh.xyz[mesh.e2v].mean(axis=1)
+    inc = np.all((c > 0.25) & (c < 0.5), axis=1) | np.all((c > 0.5) & (c < 0.75), axis=1)
+    ne = mesh.ne
+    alpha = np.where(inc, 10.0 ** p, 1.0)
+    return Problem(f"softhard_rt{k}_{dims[0]}x{dims[1]}x{dims[2]}_p{p}", mesh, k, alpha, np.ones(ne),
+                   np.ones((ne, 3)))
+
+
+SPE10_DIMS = (60, 220, 85)
+SPE10_CELL = (20.0, 10.0, 2.0)
+
+
+def config_spe10_standin(dims: tuple[int, int, int] = SPE10_DIMS, seed: int = 10) -> Problem:
+    """A synthetic stand-in for the SPE10 problem of Sec. 6.4 (the SPE10 data
+    are not available): RT0 on the 60 x 220 x 85 grid of 20 x 10 x 2 cells
+    (``dims`` scales the cell count, not the cell size), beta = 1, and a
+    layered heavy-tailed mass coefficient in the spirit of the SPE10
+    permeability: per z-layer l a mean m_l ~ N(0, 1), per element
+    ln alpha = m_l + s_l N(0, 1) with s_l = 1.0 in the top 35/85 of the layers
+    and 2.0 below (a smooth and a channelized formation; about 8 decades
+    over the grid), f ~ N(0, 1).
+    Draws, in order: the layer means, the element normals, the loads."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    mesh = structured_hex(0, dims=dims)
+    mesh.xyz *= np.array([nx * SPE10_CELL[0], ny * SPE10_CELL[1], nz * SPE10_CELL[2]])
+    ne = mesh.ne
+    layer = np.arange(ne) // (nx * ny)
+    means = rng.standard_normal(nz)
+    sig = np.where(layer < (35 * nz) // 85, 1.0, 2.0)
+    alpha = np.exp(means[layer] + sig * rng.standard_normal(ne))
+    f = element_loads(rng, ne)
+    return Problem(f"spe10_standin_{nx}x{ny}x{nz}", mesh, 0, alpha, np.ones(ne), f)

@@ -1,0 +1,96 @@
+"""The paper's workload shapes at test size: soft-hard materials (Sec. 6.1,
+coefficient jumps of 10^+-8 on two inclusion cubes) and the SPE10-shaped
+stand-in (Sec. 6.4: RT0 on a 20 x 10 x 2-cell grid with a layered heavy-tailed
+coefficient).  H and r against the long-double reference: at least as
+accurate as the FP64 oracle (as in the parity tests), or, where the element
+matrices are nearly singular (soft inclusions: alpha = 1e-8 against beta = 1
+gives kappa(M_T) ~ 1e10, and every FP64 method is then ~kappa 2^-53 off, with
+algorithm-dependent constants: LU solves in the oracle, Cholesky inverses
+here), within the worst-case bound 10 n_b kappa_max 2^-53 of an inverse from
+a Cholesky factor (kappa_max: the largest condition number of the element
+matrices, computed by the oracle).  The full solve against the oracle's
+direct solution (normwise): within 1e-6 (Jacobi-PCG stops at ||r|| <= 1e-12
+||r_0||, with kappa(H) up to ~1e5 here), or within the perturbation bound
+4 kappa(H) (dH + dr) + 2 x the element bound above, dH and dr the relative
+differences of the GPU's H and r from the oracle's, where that is larger."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import element as oelem
+from oracle import extended as oext
+from oracle import hybrid as ohyb
+from tests.gpu_common import accuracy_bound, gpu_setup, ld_dense, norm_rel, rel_inf, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("softhard", 0, -8, (8, 8, 4)), ("softhard", 0, 8, (8, 8, 4)), ("softhard", 1, 8, (4, 4, 4)),
+         ("softhard", 1, -4, (4, 4, 4)), ("softhard", 3, 8, (4, 4, 4)), ("spe10", 0, None, (6, 22, 9))]
+
+
+def _prob(kind, k, p, dims):
+    if kind == "softhard":
+        return synth.config_softhard(k, p, dims)
+    return synth.config_spe10_standin(dims)
+
+
+def _kappa_max(prob, ref):
+    """Largest 2-norm condition number of the element matrices on their kept
+    dofs (boundary faces eliminated), by the oracle."""
+    k, mesh = prob.k, prob.mesh
+    worst = 0.0
+    for s, t, M, _ in oelem.element_system_chunked(k, mesh.xyz, mesh.e2v, prob.alpha, prob.beta):
+        codes = ohyb._ess_code_of(ref.topo, np.arange(s, t))
+        for i in range(t - s):
+            keep, _, _ = ohyb._split(k, int(codes[i]))
+            worst = max(worst, np.linalg.cond(M[i][np.ix_(keep, keep)]))
+    return worst
+
+
+@pytest.mark.parametrize("kind,k,p,dims", CASES)
+def test_workload_matches_oracle(kind, k, p, dims):
+    torch = require_gpu()
+    prob = _prob(kind, k, p, dims)
+    print(f"{prob.name}: {prob.mesh.ne} elements", flush=True)
+    mesh = prob.mesh
+    plan = gpu_setup(mesh, k, prob.alpha, prob.beta, prob.f)
+    rp, ci, val = [t.cpu().numpy() for t in plan.csr()]
+    rg = plan.r().cpu().numpy()
+    ref = ohyb.hybridize(k, mesh.xyz, mesh.e2v, prob.alpha, prob.beta, prob.f)
+    assert np.array_equal(ref.H.indptr, rp) and np.array_equal(ref.H.indices, ci)
+    if k < 3:
+        Hld, rld, _ = oext.hybridize_ld(k, mesh.xyz, mesh.e2v, prob.alpha, prob.beta, prob.f, ref.topo,
+                                        np.arange(mesh.ne))
+        Hl, rl = ld_dense(Hld, rld, plan.m)
+        Hg = sp.csr_matrix((val, ci, rp), shape=ref.H.shape).toarray()
+        nH, nHo = norm_rel(Hl, Hg), norm_rel(Hl, ref.H.toarray())
+        nr, nro = norm_rel(rl, rg), norm_rel(rl, ref.r)
+        kap = _kappa_max(prob, ref)
+        nb = 6 * (k + 1) ** 2
+        floor = 10 * nb * kap * 2.0**-53
+        print(f"  vs long double, GPU / FP64 oracle: H {nH:.1e} / {nHo:.1e}, r {nr:.1e} / {nro:.1e}; "
+              f"kappa_max(M_T) {kap:.1e}, bound {floor:.1e}", flush=True)
+        assert nH <= max(accuracy_bound(nHo), floor) and nr <= max(accuracy_bound(nro), floor)
+    else:
+        floor = 0.0
+        e = norm_rel(ref.H.data, val)
+        print(f"  GPU vs FP64 oracle: H {e:.1e}", flush=True)
+        assert e <= 1e-10
+    lam, info = plan.solve(1e-12, 50000)
+    assert info["converged"], info
+    u = plan.recover(lam).cpu().numpy()
+    lref = ohyb.solve_reduced(ref.H, ref.r)
+    uref = ohyb.recover(ref, mesh.xyz, mesh.e2v, prob.alpha, prob.beta, prob.f, lref)
+    eu = norm_rel(uref, u)
+    # perturbation bound: H and r of the two FP64 paths differ by dH, dr
+    # (relative), so their solutions by up to kappa(H) (dH + dr); the
+    # recovery adds the element conditioning floor
+    Hd = ref.H.toarray()
+    kH = np.linalg.cond(Hd)
+    dH = norm_rel(Hd, sp.csr_matrix((val, ci, rp), shape=ref.H.shape).toarray())
+    dr = norm_rel(ref.r, rg)
+    bound = max(1e-6, 4.0 * kH * (dH + dr) + 2.0 * floor)
+    print(f"  solve: {info['iters']} Jacobi-PCG iterations, u vs oracle direct {eu:.1e} (normwise); "
+          f"kappa(H) {kH:.1e}, bound {bound:.1e}", flush=True)
+    assert eu <= bound
