@@ -320,6 +320,79 @@ def run_single(args, prob, label):
     print(json.dumps(out), flush=True)
 
 
+def solve_phases(prob, steps=3):
+    """Setup (matrix and load), Jacobi-PCG (rtol 1e-12) and recovery of one
+    problem: HIP-event kernel times of setup and recovery (mean over steps),
+    PCG wall time and iterations, and the time to solution (the paper's
+    tables: formation of the reduced system + solve + back substitution)."""
+    import torch
+
+    from paper_1801_08914_amd import Plan
+    dev = torch.device("cuda:0")
+    alpha, beta, f = (torch.as_tensor(x, device=dev) for x in (prob.alpha, prob.beta, prob.f))
+    plan = Plan(prob.mesh.xyz, prob.mesh.e2v, prob.k).bind("cuda:0")
+    plan.setup(alpha, beta, f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, info = plan.solve(1e-12, 200000)
+    torch.cuda.synchronize()
+    pcg_s = time.perf_counter() - t0
+    u = torch.empty((prob.mesh.ne, plan.n), dtype=torch.float64, device=dev)
+    step_s, setup_ms, rec_ms = time_plan(plan, alpha, beta, f, lam, u, steps, 1)
+    out = {"elements": prob.mesh.ne, "k": prob.k, "m": plan.m, "setup_ms": setup_ms, "recover_ms": rec_ms,
+           "pcg_ms": pcg_s * 1e3, "pcg_iters": info["iters"], "converged": info["converged"],
+           "time_to_solution_ms": setup_ms + pcg_s * 1e3 + rec_ms,
+           "elements_per_s": prob.mesh.ne / ((setup_ms + rec_ms) * 1e-3)}
+    del plan, u
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_softhard(args):
+    """The soft-hard materials study of Sec. 6.1 on one GPU: RT0 64x64x32,
+    RT1 32x32x16 and RT3 16x16x8 (the paper's initial meshes), alpha = 10^p
+    in the inclusions for p in {-8, -4, 0, 4, 8}; Jacobi-PCG (the paper's AMG
+    is out of scope, so iteration counts are not comparable)."""
+    import synth
+    rows = []
+    for k in (0, 1, 3):
+        for p in synth.SOFTHARD_EXPONENTS:
+            r = solve_phases(synth.config_softhard(k, p), steps=args.steps)
+            r["p"] = p
+            rows.append(r)
+            print(json.dumps({"progress": f"RT{k} p={p}", **{x: r[x] for x in ("pcg_iters", "time_to_solution_ms")}}),
+                  file=sys.stderr, flush=True)
+    el = sum(r["elements"] for r in rows)
+    t = sum((r["setup_ms"] + r["recover_ms"]) * 1e-3 for r in rows)
+    out = {"metric": METRIC, "value": el / t, "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": 1e3 * t / len(rows), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "soft-hard materials: RT0 64x64x32, RT1 32x32x16, RT3 16x16x8, alpha = 10^p "
+                                  "in [1/4,1/2]^3 u [1/2,3/4]^3, p in {-8,-4,0,4,8}, beta = 1, f = (1,1,1)",
+                      "precision": "fp64-plain", "preconditioner": "Jacobi"},
+           "runs": rows}
+    print(json.dumps(out), flush=True)
+
+
+def run_spe10(args):
+    """The SPE10-shaped stand-in of Sec. 6.4 (RT0, 60x220x85 cells of
+    20x10x2, layered heavy-tailed coefficient): the per-phase times of the
+    paper's table (hybridize, PCG solve, back substitution, total)."""
+    import synth
+    prob = synth.config_spe10_standin()
+    r = solve_phases(prob, steps=args.steps)
+    out = {"metric": METRIC, "value": r["elements_per_s"], "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "ms_per_step": r["setup_ms"] + r["recover_ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "SPE10-shaped stand-in: RT0 60x220x85, cells 20x10x2, layered lognormal alpha "
+                                  "(sigma 1 / 2), beta = 1, seed 10", "precision": "fp64-plain",
+                      "preconditioner": "Jacobi"},
+           "phases_ms": {"hybridize": r["setup_ms"], "pcg_solve": r["pcg_ms"], "back_substitution": r["recover_ms"],
+                         "total": r["time_to_solution_ms"]},
+           "pcg": {"iters": r["pcg_iters"], "converged": r["converged"]}, "m": r["m"]}
+    print(json.dumps(out), flush=True)
+
+
 def run_c5(args):
     """The serving stream: Poisson arrivals of hybridization requests (jittered
     meshes, k in 1..3, 1..8 right-hand sides reusing the factors).  First the
@@ -366,9 +439,10 @@ def main():
                     help="recover from a seeded random lambda instead of the PCG solution (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "softhard", "spe10"],
                     help="c2: the RT1 32^3 workload (default line); c1: RT0 4^3 latency; c3: RT2 48^3 jittered; "
-                         "c4: the uneven 64-problem batch; c5: the serving stream")
+                         "c4: the uneven 64-problem batch; c5: the serving stream; softhard: the soft-hard "
+                         "materials study; spe10: the SPE10-shaped stand-in")
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the stream")
     ap.add_argument("--nmin", type=int, default=8, help="c5: smallest mesh edge")
     ap.add_argument("--nmax", type=int, default=16, help="c5: largest mesh edge")
@@ -382,6 +456,12 @@ def main():
 
     if args.config == "c4":
         run_c4(args)
+        return
+    if args.config == "softhard":
+        run_softhard(args)
+        return
+    if args.config == "spe10":
+        run_spe10(args)
         return
     if args.config == "c5":
         run_c5(args)
