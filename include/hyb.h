@@ -122,6 +122,11 @@ typedef struct hyb_opts {
                              S x = r on the same face dofs (x = the owner's
                              outward flux), with the same CSR pattern, solve
                              and recovery calls (HYB_FP64, generic kernels) */
+  int weighted_c;         /* 1: the constraint from the bilinear form
+                             (Example 2.3 of the paper), C = M_s C_0 with
+                             M_s the face mass matrix of the multiplier
+                             space: H' = M_s H M_s, r' = M_s r, lambda' =
+                             M_s^{-1} lambda, u unchanged (HYB_HYBRID) */
 } hyb_opts;
 
 /* Sizes of the caller-owned device buffers, filled by hyb_plan_create. */

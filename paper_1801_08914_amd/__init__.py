@@ -38,7 +38,7 @@ class Plan:
 
     def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None, generic: bool = False,
                  pcg_reduce: int = 0, precision: str = "fp64", sweeps: int | None = None,
-                 system: str = "hybrid"):
+                 system: str = "hybrid", weighted_c: bool = False):
         lib = load_library()
         self._lib = lib
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -56,7 +56,7 @@ class Plan:
         opts = _abi.HybOpts(_abi.HYB_MIXED if precision == "mixed" else _abi.HYB_FP64,
                             ctypes.c_void_p(self._stream_handle()), 1 if generic else 0,
                             -1 if sweeps is None else int(sweeps), int(pcg_reduce),
-                            _abi.HYB_STATIC if system == "static" else _abi.HYB_HYBRID)
+                            _abi.HYB_STATIC if system == "static" else _abi.HYB_HYBRID, 1 if weighted_c else 0)
         self._plan = ctypes.c_void_p()
         sz = _abi.HybSizes()
         rc = lib.hyb_plan_create(ctypes.byref(mesh), self.k, ctypes.byref(opts), ctypes.byref(self._plan),

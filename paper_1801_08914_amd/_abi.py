@@ -50,7 +50,8 @@ class HybMesh(ctypes.Structure):
 
 class HybOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("kernel_variant", ctypes.c_int),
-                ("refine_sweeps", ctypes.c_int), ("pcg_reduce", ctypes.c_int), ("system", ctypes.c_int)]
+                ("refine_sweeps", ctypes.c_int), ("pcg_reduce", ctypes.c_int), ("system", ctypes.c_int),
+                ("weighted_c", ctypes.c_int)]
 
 
 class HybSizes(ctypes.Structure):

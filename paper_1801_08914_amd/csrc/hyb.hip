@@ -47,6 +47,7 @@ hyb::DeviceMaps device_maps(const hyb::Plan& P) {
   m.face_owner = reinterpret_cast<const int32_t*>(base + L.face_owner);
   m.k1_geo = reinterpret_cast<const double*>(base + L.k1_geo);
   m.k1_meta = base + L.k1_meta;
+  m.face_w = reinterpret_cast<const double*>(base + L.face_w);
   return m;
 }
 
@@ -261,7 +262,8 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   if (opt && ((opt->precision != HYB_FP64 && opt->precision != HYB_MIXED) || opt->pcg_reduce < 0 ||
               opt->pcg_reduce > 2 || opt->refine_sweeps > 16 ||
               (opt->system != HYB_HYBRID && opt->system != HYB_STATIC) ||
-              (opt->system == HYB_STATIC && opt->precision != HYB_FP64)))
+              (opt->system == HYB_STATIC && opt->precision != HYB_FP64) ||
+              (opt->weighted_c && opt->system == HYB_STATIC)))
     return HYB_E_ARG;
   hyb_plan* p = new (std::nothrow) hyb_plan;
   if (!p) return HYB_E_NOMEM;
@@ -277,7 +279,16 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   P.mixed = P.opts.precision == HYB_MIXED;
   P.stat = P.opts.system == HYB_STATIC;
   P.sweeps = P.opts.refine_sweeps < 0 ? -1 : P.opts.refine_sweeps;
-  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0 && !P.mixed && !P.stat;
+  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0 && !P.mixed && !P.stat && !P.opts.weighted_c;
+  if (P.opts.weighted_c) {
+    // M_s of the weighted constraint: the face dofs' tangential nodes are the
+    // k+1 Gauss-Legendre points, so the face mass matrix of their Lagrange
+    // basis is diagonal, w_a0 w_a1 at position a0 + (k+1) a1
+    std::vector<double> x, w;
+    hyb::gauss_legendre_01(k + 1, x, w);
+    for (int a1 = 0; a1 <= k; ++a1)
+      for (int a0 = 0; a0 <= k; ++a0) P.face_w[size_t(a0 + (k + 1) * a1)] = w[size_t(a0)] * w[size_t(a1)];
+  }
   if (P.fast_k1) P.factor_len = hyb::k1::REC;
   if (P.mixed) P.factor_len = mixed_record_len(k);
   // PCG grids, multiples of the 8 XCDs: vector kernels about one row per
@@ -375,6 +386,7 @@ int hyb_bind(hyb_plan_t* plan, const hyb_buffers* buf) {
   }
   put(L.k1_geo, P.k1_geo.data(), 8 * P.k1_geo.size());
   put(L.k1_meta, P.k1_meta.data(), P.k1_meta.size());
+  put(L.face_w, P.face_w.data(), 8 * P.face_w.size());
   HYB_HIP(hipMemcpyAsync(buf->maps, host.data(), host.size(), hipMemcpyHostToDevice, s));
   if (P.m > 0) {
     HYB_HIP(hipMemcpyAsync(buf->row_ptr, P.row_ptr.data(), 8 * P.row_ptr.size(), hipMemcpyHostToDevice, s));

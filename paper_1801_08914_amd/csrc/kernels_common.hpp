@@ -72,6 +72,7 @@ struct DeviceMaps {
   const int32_t* face_owner;   // owner element of every interior face
   const double* k1_geo;        // RT_1 affine: per-element edge vectors (9)
   const uint8_t* k1_meta;      // RT_1 affine: per-element face data (144 B)
+  const double* face_w;        // multiplier weight per face-dof position (K2)
 };
 
 // Sticky device error: the first (code, element) pair wins.

@@ -373,16 +373,17 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
         frame_map(pic[fb], K, b0, b1);
         const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
         const int Fa = fid[fa], Fb = fid[fb];
+        const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
         const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
                             mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
         const int64_t pba = mp.face_rowbase[Fb] + int64_t(jb) * mp.face_nslots[Fb] * K2 +
                             mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
         if (fa == fb) {
-          atomicAdd(&a.Hval[pab], v);
-          if (aa != bb) atomicAdd(&a.Hval[pba], v);
+          atomicAdd(&a.Hval[pab], vw);
+          if (aa != bb) atomicAdd(&a.Hval[pba], vw);
         } else {
-          a.Hval[pab] = v;
-          a.Hval[pba] = v;
+          a.Hval[pab] = vw;
+          a.Hval[pba] = vw;
         }
       }
     }
@@ -403,7 +404,7 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
         if (fid[fb] < 0) continue;
         int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
         frame_map(pic[fb], K, b0, b1);
-        atomicAdd(&a.r[int64_t(fid[fb]) * K2 + b0 + K1 * b1], eps(b) * yv[ni + b]);
+        atomicAdd(&a.r[int64_t(fid[fb]) * K2 + b0 + K1 * b1], eps(b) * yv[ni + b] * mp.face_w[b0 + K1 * b1]);
       }
     }
   }
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(TEAM* EPB) void k_recover_mixed(RecoverArgs a) {
     if (F >= 0) {
       int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
       frame_map(mp.elem_pi[es * 8 + fb], K, b0, b1);
-      v = a.lambda[int64_t(F) * K2 + b0 + K1 * b1];
+      v = a.lambda[int64_t(F) * K2 + b0 + K1 * b1] * mp.face_w[b0 + K1 * b1];
     }
     tl[b] = v;
   }

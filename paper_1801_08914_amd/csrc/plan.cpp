@@ -410,6 +410,8 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
   }
   L.k1_geo = off;       off = align256(off + sizeof(double) * P.k1_geo.size());
   L.k1_meta = off;      off = align256(off + P.k1_meta.size());
+  P.face_w.assign(size_t(o.K2), 1.0);
+  L.face_w = off;       off = align256(off + sizeof(double) * P.face_w.size());
   L.total = off;
   P.factor_len = int64_t(o.n) * (o.n + 1) / 2;
   return HYB_OK;

@@ -44,7 +44,8 @@ static_assert(sizeof(K1Meta) == K1Meta::kBytes, "K1Meta layout");
 struct MapLayout {
   size_t e2v = 0, xyz = 0, elem_face = 0, elem_pi = 0, elem_slot = 0,
          face_rowbase = 0, face_nslots = 0, tab_s = 0, tab_d = 0, tab_w = 0,
-         tab_ref = 0, tab_x = 0, face_selfslot = 0, face_owner = 0, k1_geo = 0, k1_meta = 0, total = 0;
+         tab_ref = 0, tab_x = 0, face_selfslot = 0, face_owner = 0, k1_geo = 0, k1_meta = 0, face_w = 0,
+         total = 0;
 };
 
 struct Plan {
@@ -81,6 +82,9 @@ struct Plan {
   // J[r][c] = x_{v_c}[r] - x_0[r] for vertices v = 1, 2, 4) and the element's
   // face data for the scatter into H (K1Meta, 144 bytes)
   std::vector<double> k1_geo;
+  // multiplier weights per face-dof position (K2): the diagonal of the face
+  // mass matrix M_s of the weighted constraint C = M_s C_0, or all ones
+  std::vector<double> face_w;
   std::vector<uint8_t> k1_meta;
   MapLayout lay;
   int64_t factor_len = 0;

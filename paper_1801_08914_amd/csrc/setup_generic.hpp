@@ -345,12 +345,13 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
                             mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
         const int64_t pba = mp.face_rowbase[Fb] + int64_t(jb) * mp.face_nslots[Fb] * K2 +
                             mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
+        const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
         if (fa == fb) {
-          atomicAdd(&a.Hval[pab], v);
-          if (aa != bb) atomicAdd(&a.Hval[pba], v);
+          atomicAdd(&a.Hval[pab], vw);
+          if (aa != bb) atomicAdd(&a.Hval[pba], vw);
         } else {
-          a.Hval[pab] = v;
-          a.Hval[pba] = v;
+          a.Hval[pab] = vw;
+          a.Hval[pba] = vw;
         }
       }
     }
@@ -409,6 +410,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
         }
         int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
         frame_map(pic[fb], K, b0, b1);
+        if (!a.stat) s *= mp.face_w[b0 + K1 * b1];   // M_s r_T (weighted C)
         atomicAdd(&a.r[int64_t(fid[fb]) * K2 + b0 + K1 * b1], s);
       }
     }
@@ -463,8 +465,9 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
         // u_b = sigma x: the face dof is the owner's outward flux
         const double eps = (fb & 1) ? 1.0 : -1.0;
         v = mp.face_owner[F_] == es ? eps * v : -eps * v;
-      } else if (!(fb & 1)) {
-        v = -v;
+      } else {
+        v *= mp.face_w[b0 + K1 * b1];   // C^T M_s lambda (weighted C)
+        if (!(fb & 1)) v = -v;
       }
     } else if (a.stat) {
       v = yv[ni + b];  // boundary data
