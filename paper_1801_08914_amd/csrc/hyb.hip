@@ -93,7 +93,7 @@ int dispatch_setup(int k, const hyb::SetupArgs& a, hipStream_t s) {
   switch (k) {
     case 0: return launch_setup<0, 16, 16>(a, s);
     case 1: return launch_setup<1, 64, 4>(a, s);
-    case 2: return launch_setup<2, 256, 1>(a, s);
+    case 2: return launch_setup<2, 512, 1>(a, s);
     case 3: return launch_setup<3, 256, 1>(a, s);
     default: return HYB_E_ARG;
   }

@@ -304,48 +304,9 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
       L[p] = float(Sv[i] * M[p] * Sv[j]);
     }
     __syncthreads();
-    // FP32 right-looking Cholesky, one barrier per column (trailing update
-    // with the unscaled column, the column scaled afterwards)
-    for (int c = 0; c < n; ++c) {
-      float d = L[pk(c, c)];
-      if (!(d > 0.0f)) {
-        // the FP32 factor broke down: kappa(S M_T S) 2^-24 >= 1 (or M_T is
-        // not SPD); the plain FP64 form is the one to use for this element
-        if (live && lane == 0) report_error(a.status, HYB_E_REFINE, e);
-        d = 1.0f;
-      }
-      const float inv = 1.0f / d;
-      // trailing update by rows: S lanes per row (see the FP64 kernel)
-      constexpr int S = TEAM / n > 0 ? TEAM / n : 1;
-      for (int i = c + 1 + lane / S; i < n && lane / S < TEAM / S; i += TEAM / S) {
-        float* Li = L + i * (i + 1) / 2;
-        const float lic = Li[c] * inv;
-        int j = c + 1 + lane % S;
-        int pjc = j * (j + 1) / 2 + c;
-        for (; j + 3 * S <= i; j += 4 * S) {
-          float lc4[4], li4[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            lc4[u] = L[pjc];
-            li4[u] = Li[j + u * S];
-#pragma unroll
-            for (int s = 1; s <= S; ++s) pjc += j + u * S + s;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) Li[j + u * S] = li4[u] - lic * lc4[u];
-        }
-        for (; j <= i; j += S) {
-          Li[j] -= lic * L[pjc];
-#pragma unroll
-          for (int s = 1; s <= S; ++s) pjc += j + s;
-        }
-      }
-      __syncthreads();
-      const float sq = sqrtf(d), is = 1.0f / sq;
-      for (int i = c + 1 + lane; i < n; i += TEAM) L[pk(i, c)] *= is;
-      if (lane == 0) L[pk(c, c)] = sq;
-    }
-    __syncthreads();
+    // FP32 Cholesky; a breakdown means kappa(S M_T S) 2^-24 >= 1 (or M_T is
+    // not SPD): the plain FP64 form is the one to use for this element
+    if (chol_packed<float, n, TEAM>(L, lane) && live && lane == 0) report_error(a.status, HYB_E_REFINE, e);
     for (int c = lane; c < n; c += TEAM) dinv[c] = 1.0f / L[pk(c, c)];
     __syncthreads();
 

@@ -119,6 +119,59 @@ __device__ __forceinline__ double m_entry(const DeviceMaps& mp, const double* qd
   return s;
 }
 
+// Packed lower Cholesky factorization in place (LDS or global), right-
+// looking by panels of NB columns: each panel column is factored and applied
+// to the panel's later columns (one barrier per column; the column is scaled
+// after the barrier, it is not read again within the panel), then one
+// rank-NB update of the trailing triangle reads and writes every trailing
+// entry once per panel.  In the trailing update S = TEAM / N lanes share a
+// row and each keeps the row's NB panel entries in registers.  Returns true
+// (in every lane) when a pivot was not positive (replaced by 1).
+template <class T, int N, int TEAM>
+__device__ __forceinline__ bool chol_packed(T* A, int lane) {
+  constexpr int NB = N >= 64 ? 8 : 4;
+  constexpr int S = TEAM / N > 0 ? TEAM / N : 1;
+  bool bad = false;
+  for (int c0 = 0; c0 < N; c0 += NB) {
+    const int w = N - c0 < NB ? N - c0 : NB;
+    for (int c = c0; c < c0 + w; ++c) {
+      T d = A[pk(c, c)];
+      if (!(d > T(0))) {
+        bad = true;
+        d = T(1);
+      }
+      const T inv = T(1) / d;
+      for (int i = c + 1 + lane; i < N; i += TEAM) {
+        T* Ai = A + i * (i + 1) / 2;
+        const T aic = Ai[c] * inv;
+        const int jend = i < c0 + w - 1 ? i : c0 + w - 1;
+        for (int j = c + 1; j <= jend; ++j) Ai[j] -= aic * A[pk(j, c)];
+      }
+      __syncthreads();
+      const T sq = sqrt(d), is = T(1) / sq;
+      for (int i = c + 1 + lane; i < N; i += TEAM) A[pk(i, c)] *= is;
+      if (lane == 0) A[pk(c, c)] = sq;
+    }
+    __syncthreads();
+    for (int i = c0 + w + lane / S; i < N && lane / S < TEAM / S; i += TEAM / S) {
+      T* Ai = A + i * (i + 1) / 2;
+      T li[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) li[t] = t < w ? Ai[c0 + t] : T(0);
+      for (int j = c0 + w + lane % S; j <= i; j += S) {
+        const T* Aj = A + j * (j + 1) / 2 + c0;
+        T acc = Ai[j];
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+          if (t < w) acc -= li[t] * Aj[t];
+        Ai[j] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  return bad;
+}
+
 // Local assembly (Gauss quadrature), essential-face masking, packed
 // Cholesky in i-first order, inversion of the face block, H_T scatter, and
 // the right-hand side y = L^{-1} f_hat, r_T = D L_bb^{-T} y_b.
@@ -223,48 +276,9 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       if (is_ess(i) || is_ess(j)) A[p] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    // Right-looking Cholesky, one barrier per column: the trailing update
-    // uses the unscaled column; the column is scaled afterwards (it is never
-    // read again by later steps).
-    for (int c = 0; c < n; ++c) {
-      double d = A[pk(c, c)];
-      if (!(d > 0.0)) {
-        if (live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
-        d = 1.0;
-      }
-      const double inv = 1.0 / d;
-      // trailing update by rows: S lanes per row, lane h of a row takes the
-      // columns c+1+h, c+1+h+S, ... (no packed-index arithmetic per entry)
-      constexpr int S = TEAM / n > 0 ? TEAM / n : 1;
-      for (int i = c + 1 + lane / S; i < n && lane / S < TEAM / S; i += TEAM / S) {
-        double* Ai = A + i * (i + 1) / 2;
-        const double aic = Ai[c] * inv;
-        int j = c + 1 + lane % S;
-        int pjc = j * (j + 1) / 2 + c;
-        // four columns at a time, loads first (row i and column c never alias)
-        for (; j + 3 * S <= i; j += 4 * S) {
-          double lc4[4], ai4[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            lc4[u] = A[pjc];
-            ai4[u] = Ai[j + u * S];
-#pragma unroll
-            for (int s = 1; s <= S; ++s) pjc += j + u * S + s;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) Ai[j + u * S] = ai4[u] - aic * lc4[u];
-        }
-        for (; j <= i; j += S) {
-          Ai[j] -= aic * A[pjc];
-#pragma unroll
-          for (int s = 1; s <= S; ++s) pjc += j + s;
-        }
-      }
-      __syncthreads();
-      const double sq = sqrt(d), is = 1.0 / sq;
-      for (int i = c + 1 + lane; i < n; i += TEAM) A[pk(i, c)] *= is;
-      if (lane == 0) A[pk(c, c)] = sq;
-    }
+    // Cholesky (interior block first, so L_bb L_bb^T is the element's Schur
+    // complement onto its face dofs)
+    if (chol_packed<double, n, TEAM>(A, lane) && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
     __syncthreads();
     if (a.stat) {
       // S_hat_T = L_bb L_bb^T (lower triangle), sigma-signed, into S
