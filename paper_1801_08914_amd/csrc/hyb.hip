@@ -140,8 +140,8 @@ int dispatch_setup_mixed(int k, const hyb::SetupArgs& a, int sweeps, hipStream_t
   switch (k) {
     case 0: return launch_setup_mixed<0, 16, 16>(a, sweeps, s);
     case 1: return launch_setup_mixed<1, 64, 4>(a, sweeps, s);
-    case 2: return launch_setup_mixed<2, 256, 1>(a, sweeps, s);
-    case 3: return launch_setup_mixed<3, 256, 1>(a, sweeps, s);
+    case 2: return launch_setup_mixed<2, 512, 1>(a, sweeps, s);
+    case 3: return launch_setup_mixed<3, 512, 1>(a, sweeps, s);
     default: return HYB_E_ARG;
   }
 }
