@@ -596,14 +596,34 @@ struct SimtArgs {
 // and hold the overhang of the last, partial chunk of a record.
 constexpr int REC_CHUNKS = (REC * 8 + 1023) / 1024;   // 6
 constexpr int RSLOT = REC_CHUNKS * 128 + 2;           // doubles per slot
+// the recovery reads only E and S^{-1} (doubles OFF_E .. OFF_SI + 300)
+constexpr int REC_CHUNKS_R = ((OFF_SI + 300 - OFF_E) * 8 + 1023) / 1024;   // 5
+constexpr int RSLOT_R = REC_CHUNKS_R * 128 + 2;
+static_assert((OFF_E * 8) % 16 == 0, "16-byte aligned copy start");
 
-struct alignas(16) SolveLds {
-  double rec[SOLVE_EPW * RSLOT];
+template <int SLOT>
+struct alignas(16) SolveLdsT {
+  double rec[SOLVE_EPW * SLOT];
   double v[SOLVE_EPW + 1][49];   // per-team exchange vectors
+};
+using SolveLds = SolveLdsT<RSLOT>;
+
+// Recovery: the exchange vector of a team lives in its slot's tail (past the
+// 588 doubles of E and S^{-1}, written once the copies have landed), so the
+// wave needs 26 KB of LDS and six waves fit on a CU.
+constexpr int RTAIL = OFF_SI + 300 - OFF_E;   // 588
+static_assert(RSLOT_R - RTAIL >= 49, "exchange vector fits in the slot tail");
+struct alignas(16) RecoverLds {
+  double rec[SOLVE_EPW * RSLOT_R];
+  double vspare[49];             // the wave's idle lanes
 };
 
 // Record of element min(e0 + k, ne - 1) into slot k; lane i of chunk q moves
 // bytes q KB + 16 i of the record, clamped to its last 16 bytes.
+// Copy doubles FIRST .. of each of the wave's SOLVE_EPW element records into
+// LDS slots of SLOT doubles, CHUNKS x 1 KB per record (the last chunk's
+// lanes past the record's end re-read its last 16 bytes).
+template <int FIRST, int CHUNKS, int SLOT>
 __device__ __forceinline__ void stage_records(double* dst, const double* factor, int64_t e0, int64_t ne) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -612,11 +632,11 @@ __device__ __forceinline__ void stage_records(double* dst, const double* factor,
     el = el < ne ? el : ne - 1;
     const char* base = reinterpret_cast<const char*>(factor + el * REC);
 #pragma unroll
-    for (int q = 0; q < REC_CHUNKS; ++q) {
-      int off = q * 1024 + 16 * lane;
+    for (int q = 0; q < CHUNKS; ++q) {
+      int off = FIRST * 8 + q * 1024 + 16 * lane;
       off = off < REC * 8 - 16 ? off : REC * 8 - 16;
       __builtin_amdgcn_global_load_lds(base + off,
-                                       (__attribute__((address_space(3))) void*)(dst + k * RSLOT + 128 * q), 16, 0, 0);
+                                       (__attribute__((address_space(3))) void*)(dst + k * SLOT + 128 * q), 16, 0, 0);
     }
   }
   __builtin_amdgcn_s_waitcnt(0);   // all counters: the LDS copies have landed
@@ -630,7 +650,7 @@ __global__ __launch_bounds__(64) void k_rhs_k1(SimtArgs a) {
   const bool live = tau < SOLVE_EPW && e < a.ne;
   const int64_t es = live ? e : 0;
   const DeviceMaps& mp = a.mp;
-  stage_records(L.rec, a.factor, e0, a.ne);
+  stage_records<0, REC_CHUNKS, RSLOT>(L.rec, a.factor, e0, a.ne);
   const double* gb = a.g ? a.g + es * NB : nullptr;
   Elem el;
   el.load(mp, es, a.alpha, a.beta, a.f, gb != nullptr);
@@ -680,16 +700,16 @@ __global__ __launch_bounds__(64) void k_rhs_k1(SimtArgs a) {
 }
 
 __global__ __launch_bounds__(64) void k_recover_k1(SimtArgs a) {
-  __shared__ SolveLds L;
+  __shared__ RecoverLds L;
   const int lane = threadIdx.x, tau = lane / TEAM, t = lane - tau * TEAM;
   const int64_t e0 = xcd_block() * SOLVE_EPW;
   const int64_t e = e0 + tau;
   const bool live = tau < SOLVE_EPW && e < a.ne;
   const int64_t es = live ? e : 0;
   const DeviceMaps& mp = a.mp;
-  stage_records(L.rec, a.factor, e0, a.ne);
-  // D lambda on the two face rows of this lane
-  double* v = L.v[tau];
+  // D lambda on the two face rows of this lane and y, loaded before the
+  // record copies are issued so that both are in flight together
+  double lam2[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int arow = 12 * h + t;
@@ -700,18 +720,24 @@ __global__ __launch_bounds__(64) void k_recover_k1(SimtArgs a) {
       x = a.lambda[int64_t(F) * 4 + own_idx(mp.elem_pi[es * 8 + fc], arow & 3)];
       if (!(fc & 1)) x = -x;
     }
-    v[arow] = x;
+    lam2[h] = x;
   }
   const double yi = a.y[es * N + t], ya = a.y[es * N + 12 + t], yb = a.y[es * N + 24 + t];
+  stage_records<OFF_E, REC_CHUNKS_R, RSLOT_R>(L.rec, a.factor, e0, a.ne);
+  double* v = tau < SOLVE_EPW ? L.rec + tau * RSLOT_R + RTAIL : L.vspare;
+  v[t] = lam2[0];
+  v[12 + t] = lam2[1];
   __syncthreads();
-  const double* rec = L.rec + (live ? tau : 0) * RSLOT;
+  // the slot starts at E (record offset OFF_E); S^{-1} follows at OFF_SI - OFF_E
+  const double* slot = L.rec + (live ? tau : 0) * RSLOT_R;
+  const double* Si = slot + (OFF_SI - OFF_E);
   // u_b = y_b - S^{-1} D lambda
   double ua = ya, ub = yb;
 #pragma unroll
   for (int b = 0; b < 24; ++b) {
     const double tl = v[b];
-    ua = fma(-rec[OFF_SI + spk(t, b)], tl, ua);
-    ub = fma(-rec[OFF_SI + spk(12 + t, b)], tl, ub);
+    ua = fma(-Si[spk(t, b)], tl, ua);
+    ub = fma(-Si[spk(12 + t, b)], tl, ub);
   }
   v[24 + t] = ua;
   v[36 + t] = ub;
@@ -719,7 +745,7 @@ __global__ __launch_bounds__(64) void k_recover_k1(SimtArgs a) {
   // u_i = y_i - E u_b
   double ui = yi;
 #pragma unroll
-  for (int b = 0; b < 24; ++b) ui = fma(-rec[OFF_E + 24 * t + b], v[24 + b], ui);
+  for (int b = 0; b < 24; ++b) ui = fma(-slot[24 * t + b], v[24 + b], ui);
   if (!live) return;
   a.u[e * N + t] = ui;
   a.u[e * N + 12 + t] = ua;
