@@ -23,9 +23,13 @@ struct BatchItem {
   int64_t blk0;      // first element block (blocks of the order's EPB elements)
 };
 
-// Element blocks per order (teams x lanes = 256 threads for every order).
-__host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 16 : (k == 1 ? 4 : 1); }
-constexpr int kBatchThreads = 256;
+// Element blocks per order (teams x lanes = 512 threads for every order:
+// 32 x 16, 8 x 64, one element on 512 lanes for k = 2, 3).  Team sizes match
+// the single-plan kernels where the per-element arithmetic depends on them
+// (it does not: every entry is summed in a fixed order), so a batch gives
+// the single plans' bits.
+__host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 32 : (k == 1 ? 8 : 1); }
+constexpr int kBatchThreads = 512;
 
 // Zero the same-face blocks of H (and r) of every problem: blockIdx.y is the
 // problem.
@@ -55,10 +59,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* 
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
       switch (P.k) {
-        case 0: setup_generic_body<0, 16, 16>(P.s, smem, blk); break;
-        case 1: setup_generic_body<1, 64, 4>(P.s, smem, blk); break;
-        case 2: setup_generic_body<2, 256, 1>(P.s, smem, blk); break;
-        default: setup_generic_body<3, 256, 1>(P.s, smem, blk); break;
+        case 0: setup_generic_body<0, 16, 32>(P.s, smem, blk); break;
+        case 1: setup_generic_body<1, 64, 8>(P.s, smem, blk); break;
+        case 2: setup_generic_body<2, 512, 1>(P.s, smem, blk); break;
+        default: setup_generic_body<3, 512, 1>(P.s, smem, blk); break;
       }
       __syncthreads();   // the next block reuses the LDS
     }
@@ -74,10 +78,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
       switch (P.k) {
-        case 0: recover_generic_body<0, 16, 16>(P.r, smem, blk); break;
-        case 1: recover_generic_body<1, 64, 4>(P.r, smem, blk); break;
-        case 2: recover_generic_body<2, 256, 1>(P.r, smem, blk); break;
-        default: recover_generic_body<3, 256, 1>(P.r, smem, blk); break;
+        case 0: recover_generic_body<0, 16, 32>(P.r, smem, blk); break;
+        case 1: recover_generic_body<1, 64, 8>(P.r, smem, blk); break;
+        case 2: recover_generic_body<2, 512, 1>(P.r, smem, blk); break;
+        default: recover_generic_body<3, 512, 1>(P.r, smem, blk); break;
       }
       __syncthreads();
     }
@@ -87,16 +91,16 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
 // LDS bytes of one block of the batch kernels for order k.
 inline size_t batch_setup_lds(int k) {
   switch (k) {
-    case 0: return 8 * 16 * size_t(GenericLayout<0, 16, 16>::per);
-    case 1: return 8 * 4 * size_t(GenericLayout<1, 64, 4>::per);
-    case 2: return 8 * size_t(GenericLayout<2, 256, 1>::per);
-    default: return 8 * size_t(GenericLayout<3, 256, 1>::per);
+    case 0: return 8 * 32 * size_t(GenericLayout<0, 16, 32>::per);
+    case 1: return 8 * 8 * size_t(GenericLayout<1, 64, 8>::per);
+    case 2: return 8 * size_t(GenericLayout<2, 512, 1>::per);
+    default: return 8 * size_t(GenericLayout<3, 512, 1>::per);
   }
 }
 inline size_t batch_recover_lds(int k) {
   switch (k) {
-    case 0: return 8 * 16 * size_t(recover_per<0>());
-    case 1: return 8 * 4 * size_t(recover_per<1>());
+    case 0: return 8 * 32 * size_t(recover_per<0>());
+    case 1: return 8 * 8 * size_t(recover_per<1>());
     case 2: return 8 * size_t(recover_per<2>());
     default: return 8 * size_t(recover_per<3>());
   }
