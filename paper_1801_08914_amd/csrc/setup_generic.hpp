@@ -172,6 +172,68 @@ __device__ __forceinline__ bool chol_packed(T* A, int lane) {
   return bad;
 }
 
+// chol_packed for a matrix in HBM (the element's record): each panel is
+// copied into LDS (P: (N - c0) x NB doubles), factored there and written
+// back, and the trailing update reads the panel from LDS, so the only HBM
+// traffic per trailing entry and panel is its read-modify-write.  The
+// operations and their order are those of chol_packed.
+template <class T, int N, int TEAM>
+__device__ __forceinline__ bool chol_packed_staged(T* A, T* P, int lane) {
+  constexpr int NB = N >= 64 ? 8 : 4;
+  constexpr int S = TEAM / N > 0 ? TEAM / N : 1;
+  bool bad = false;
+  for (int c0 = 0; c0 < N; c0 += NB) {
+    const int w = N - c0 < NB ? N - c0 : NB;
+    // panel rows c0..N-1, columns c0..c0+w-1 (row i holds min(w, i - c0 + 1))
+    for (int t = lane; t < (N - c0) * NB; t += TEAM) {
+      const int r = t / NB, q = t % NB;
+      P[t] = (q < w && q <= r) ? A[pk(c0 + r, c0 + q)] : T(0);
+    }
+    __syncthreads();
+    for (int c = c0; c < c0 + w; ++c) {
+      const int cc = c - c0;
+      T d = P[cc * NB + cc];
+      if (!(d > T(0))) {
+        bad = true;
+        d = T(1);
+      }
+      const T inv = T(1) / d;
+      for (int i = c + 1 + lane; i < N; i += TEAM) {
+        T* Pi = P + (i - c0) * NB;
+        const T aic = Pi[cc] * inv;
+        const int jend = i < c0 + w - 1 ? i : c0 + w - 1;
+        for (int j = c + 1; j <= jend; ++j) Pi[j - c0] -= aic * P[(j - c0) * NB + cc];
+      }
+      __syncthreads();
+      const T sq = sqrt(d), is = T(1) / sq;
+      for (int i = c + 1 + lane; i < N; i += TEAM) P[(i - c0) * NB + cc] *= is;
+      if (lane == 0) P[cc * NB + cc] = sq;
+    }
+    __syncthreads();
+    for (int t = lane; t < (N - c0) * NB; t += TEAM) {
+      const int r = t / NB, q = t % NB;
+      if (q < w && q <= r) A[pk(c0 + r, c0 + q)] = P[t];
+    }
+    for (int i = c0 + w + lane / S; i < N && lane / S < TEAM / S; i += TEAM / S) {
+      T* Ai = A + i * (i + 1) / 2;
+      const T* Pi = P + (i - c0) * NB;
+      T li[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) li[t] = t < w ? Pi[t] : T(0);
+      for (int j = c0 + w + lane % S; j <= i; j += S) {
+        const T* Pj = P + (j - c0) * NB;
+        T acc = Ai[j];
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+          if (t < w) acc -= li[t] * Pj[t];
+        Ai[j] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  return bad;
+}
+
 // Local assembly (Gauss quadrature), essential-face masking, packed
 // Cholesky in i-first order, inversion of the face block, H_T scatter, and
 // the right-hand side y = L^{-1} f_hat, r_T = D L_bb^{-T} y_b.
@@ -278,7 +340,14 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     __syncthreads();
     // Cholesky (interior block first, so L_bb L_bb^T is the element's Schur
     // complement onto its face dofs)
-    if (chol_packed<double, n, TEAM>(A, lane) && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
+    bool notspd;
+    if constexpr (Lay::kGlobal) {
+      static_assert(Lay::stage >= (n + 7) / 8 * 8 * 8, "the panel fits in the assembly staging area");
+      notspd = chol_packed_staged<double, n, TEAM>(A, stg, lane);
+    } else {
+      notspd = chol_packed<double, n, TEAM>(A, lane);
+    }
+    if (notspd && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
     __syncthreads();
     if (a.stat) {
       // S_hat_T = L_bb L_bb^T (lower triangle), sigma-signed, into S
