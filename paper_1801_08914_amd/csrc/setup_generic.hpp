@@ -262,7 +262,12 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   double* stg = tb + nb;
   // packed inverse of the face block: its own LDS array, or (global matrix)
   // the face block of A, inverted in place
-  auto LI = [&](int i, int j) -> double& { return Lay::kGlobal ? A[pk(ni + i, ni + j)] : Li[pk(i, j)]; };
+  // (an HBM-resident matrix has its face block copied to the staging area
+  // of LDS for the inversion and what reads the inverse in the same call)
+  bool fb_lds = false;
+  auto LI = [&](int i, int j) -> double& {
+    return Lay::kGlobal ? (fb_lds ? stg[pk(i, j)] : A[pk(ni + i, ni + j)]) : Li[pk(i, j)];
+  };
   const DeviceMaps& mp = a.mp;
 
   int fid[6], pic[6];
@@ -389,23 +394,38 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
         }
       }
     } else {
-      // In place, columns right to left: X_ij = -(sum_{c=j+1..i} X_ic L_cj) / L_jj
-      // reads the original column j and the finished columns c > j.
+      // the face block into LDS, inverted in place there, written back
+      static_assert(Lay::stage >= R::nbpk, "the face block fits in the staging area");
+      double* Fb = stg;
+      for (int t = lane; t < R::nbpk; t += TEAM) {
+        int i, j;
+        unpk(t, i, j);
+        Fb[t] = A[pk(ni + i, ni + j)];
+      }
+      __syncthreads();
+      // columns right to left: X_ij = -(sum_{c=j+1..i} X_ic L_cj) / L_jj reads
+      // the original column j and the finished columns c > j
       for (int j = nb - 1; j >= 0; --j) {
-        const double ljj = A[pk(ni + j, ni + j)];
+        const double ljj = Fb[pk(j, j)];
         double xs[(nb + TEAM - 1) / TEAM];
         int q = 0;
         for (int i = j + 1 + lane; i < nb; i += TEAM, ++q) {
           double s = 0.0;
-          for (int c = j + 1; c <= i; ++c) s += A[pk(ni + i, ni + c)] * A[pk(ni + c, ni + j)];
+          for (int c = j + 1; c <= i; ++c) s += Fb[pk(i, c)] * Fb[pk(c, j)];
           xs[q] = -s / ljj;
         }
         __syncthreads();
         q = 0;
-        for (int i = j + 1 + lane; i < nb; i += TEAM, ++q) A[pk(ni + i, ni + j)] = xs[q];
-        if (lane == 0) A[pk(ni + j, ni + j)] = 1.0 / ljj;
+        for (int i = j + 1 + lane; i < nb; i += TEAM, ++q) Fb[pk(i, j)] = xs[q];
+        if (lane == 0) Fb[pk(j, j)] = 1.0 / ljj;
         __syncthreads();
       }
+      for (int t = lane; t < R::nbpk; t += TEAM) {
+        int i, j;
+        unpk(t, i, j);
+        A[pk(ni + i, ni + j)] = Fb[t];
+      }
+      fb_lds = true;
     }
     __syncthreads();
     // H_T = D L_bb^{-T} L_bb^{-1} D, scattered into H (lower triangle computed,
