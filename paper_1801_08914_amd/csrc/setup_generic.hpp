@@ -234,6 +234,77 @@ __device__ __forceinline__ bool chol_packed_staged(T* A, T* P, int lane) {
   return bad;
 }
 
+// Triangular solves with the leading NI x NI block of a packed lower factor
+// L in LDS, by the team's first wave: its lanes keep the vector in registers
+// (rows lane + 64 r) and every solved entry reaches them by a shuffle, so
+// there is no block barrier per column.  Per entry the operations and their
+// order are those of the column-oriented loops (y_c = y_c / L_cc, then
+// y_i -= L_ic y_c).  Both end with a barrier.
+template <int NI>
+__device__ __forceinline__ void wave_forward(const double* L, double* y, int lane) {
+  constexpr int RPL = (NI + 63) / 64;
+  if (RPL > 0 && lane < 64) {
+    double yr[RPL > 0 ? RPL : 1];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      yr[r] = i < NI ? y[i] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int cend = NI < 64 * (s + 1) ? NI : 64 * (s + 1);
+      for (int c = 64 * s; c < cend; ++c) {
+        const double yc = __shfl(yr[s], c - 64 * s) / L[pk(c, c)];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int i = lane + 64 * r;
+          if (i > c && i < NI) yr[r] -= L[pk(i, c)] * yc;
+        }
+        if (lane == c - 64 * s) yr[s] = yc;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      if (i < NI) y[i] = yr[r];
+    }
+  }
+  __syncthreads();
+}
+
+// z := L^{-T} z with the same leading block (back substitution).
+template <int NI>
+__device__ __forceinline__ void wave_backward(const double* L, double* z, int lane) {
+  constexpr int RPL = (NI + 63) / 64;
+  if (RPL > 0 && lane < 64) {
+    double zr[RPL > 0 ? RPL : 1];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int j = lane + 64 * r;
+      zr[r] = j < NI ? z[j] : 0.0;
+    }
+#pragma unroll
+    for (int s = RPL - 1; s >= 0; --s) {
+      const int cend = NI < 64 * (s + 1) ? NI : 64 * (s + 1);
+      for (int c = cend - 1; c >= 64 * s; --c) {
+        const double uc = __shfl(zr[s], c - 64 * s) / L[pk(c, c)];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int j = lane + 64 * r;
+          if (j < c) zr[r] -= L[pk(c, j)] * uc;
+        }
+        if (lane == c - 64 * s) zr[s] = uc;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int j = lane + 64 * r;
+      if (j < NI) z[j] = zr[r];
+    }
+  }
+  __syncthreads();
+}
+
 // Local assembly (Gauss quadrature), essential-face masking, packed
 // Cholesky in i-first order, inversion of the face block, H_T scatter, and
 // the right-hand side y = L^{-1} f_hat, r_T = D L_bb^{-T} y_b.
@@ -472,14 +543,19 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   }
 
   if (a.mode & MODE_RHS) {
-    // y_i = L_ii^{-1} f_i (column-oriented, one barrier per column)
-    for (int c = 0; c < ni; ++c) {
-      const double yc = fh[c] / A[pk(c, c)];
-      for (int i = c + 1 + lane; i < ni; i += TEAM) fh[i] -= A[pk(i, c)] * yc;
+    // y_i = L_ii^{-1} f_i
+    if constexpr (TEAM >= 64 && !Lay::kGlobal) {
+      wave_forward<ni>(A, fh, lane);
+    } else {
+      // (column-oriented, one barrier per column)
+      for (int c = 0; c < ni; ++c) {
+        const double yc = fh[c] / A[pk(c, c)];
+        for (int i = c + 1 + lane; i < ni; i += TEAM) fh[i] -= A[pk(i, c)] * yc;
+        __syncthreads();
+        if (lane == 0) fh[c] = yc;
+      }
       __syncthreads();
-      if (lane == 0) fh[c] = yc;
     }
-    __syncthreads();
     // y_b = L_bb^{-1} (f_b - L_bi y_i)
     for (int b = lane; b < nb; b += TEAM) {
       double s = fh[ni + b];
@@ -538,8 +614,14 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
 
 // u_T = L^{-T} (y - [0; L_bb^{-1} D lambda_b]) from the stored factor; with
 // static condensation u_b = sigma x_b and u_i = L_ii^{-T} (y_i - L_bi^T u_b).
+// (k <= 2 also stage the factor's interior block for a wave-level back
+// substitution; for k = 3 it would take 83 KB of LDS per element)
 template <int K>
-constexpr int recover_per() { return 2 * RT<K>::n + RT<K>::nb; }
+constexpr bool recover_stages() { return K <= 2; }
+template <int K>
+constexpr int recover_per() {
+  return 2 * RT<K>::n + RT<K>::nb + (recover_stages<K>() ? RT<K>::ni * (RT<K>::ni + 1) / 2 : 0);
+}
 
 template <int K, int TEAM, int EPB>
 __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, double* smem, int64_t blk) {
@@ -553,9 +635,12 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
   double* yv = smem + team * per;   // y, then v / u
   double* zb = yv + n;              // z_b, then u_b
   double* tl = zb + n;              // D lambda_b
+  double* Lii = tl + nb;             // the factor's interior block (packed, leading)
   const double* F = a.factor + es * R::npk;
   const DeviceMaps& mp = a.mp;
   for (int i = lane; i < n; i += TEAM) yv[i] = a.y[es * n + i];
+  if constexpr (recover_stages<K>())
+    for (int t = lane; t < ni * (ni + 1) / 2; t += TEAM) Lii[t] = F[t];
   for (int b = lane; b < nb; b += TEAM) {
     const int fb = b / K2;
     const int F_ = mp.elem_face[es * 6 + fb];
@@ -598,13 +683,18 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
     zb[j] = s;
   }
   __syncthreads();
-  for (int c = ni - 1; c >= 0; --c) {
-    const double uc = zb[c] / F[pk(c, c)];
-    for (int j = lane; j < c; j += TEAM) zb[j] -= F[pk(c, j)] * uc;
+  if constexpr (TEAM >= 64 && recover_stages<K>()) {
+    wave_backward<ni>(Lii, zb, lane);
+  } else {
+    const double* Lb = recover_stages<K>() ? Lii : F;
+    for (int c = ni - 1; c >= 0; --c) {
+      const double uc = zb[c] / Lb[pk(c, c)];
+      for (int j = lane; j < c; j += TEAM) zb[j] -= Lb[pk(c, j)] * uc;
+      __syncthreads();
+      if (lane == 0) zb[c] = uc;
+    }
     __syncthreads();
-    if (lane == 0) zb[c] = uc;
   }
-  __syncthreads();
   if (live)
     for (int i = lane; i < n; i += TEAM) a.u[e * n + i] = i < ni ? zb[i] : tl[i - ni];
 }
