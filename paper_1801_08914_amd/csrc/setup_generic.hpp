@@ -4,6 +4,8 @@
 // it for particular k.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels_common.hpp"
 #include "mfma.hpp"
 
@@ -127,8 +129,74 @@ __device__ __forceinline__ double m_entry(const DeviceMaps& mp, const double* qd
 // entry once per panel.  In the trailing update S = TEAM / N lanes share a
 // row and each keeps the row's NB panel entries in registers.  Returns true
 // (in every lane) when a pivot was not positive (replaced by 1).
+// The FP64 form for LDS-resident matrices and teams of whole waves: panels of
+// 16 columns aligned with 16 x 16 tiles, and the trailing update of every
+// lower tile (I, J) as C -= L_I L_J^T over the panel on the FP64 matrix
+// cores (four v_mfma_f64_16x16x4 per tile; the team's waves share out the
+// tiles; each trailing entry belongs to one tile).
+template <int N, int TEAM>
+__device__ __forceinline__ bool chol_packed_mfma(double* A, int lane) {
+  constexpr int NB = 16, NT = (N + 15) / 16, NW = TEAM / 64;
+  static_assert(TEAM % 64 == 0, "whole waves per team");
+  const int w_id = lane / 64, l = lane % 64, li = l % 16, lc = l / 16;
+  bool bad = false;
+  for (int c0 = 0; c0 < N; c0 += NB) {
+    const int w = N - c0 < NB ? N - c0 : NB;
+    for (int c = c0; c < c0 + w; ++c) {
+      double d = A[pk(c, c)];
+      if (!(d > 0.0)) {
+        bad = true;
+        d = 1.0;
+      }
+      const double inv = 1.0 / d;
+      for (int i = c + 1 + lane; i < N; i += TEAM) {
+        double* Ai = A + i * (i + 1) / 2;
+        const double aic = Ai[c] * inv;
+        const int jend = i < c0 + w - 1 ? i : c0 + w - 1;
+        for (int j = c + 1; j <= jend; ++j) Ai[j] -= aic * A[pk(j, c)];
+      }
+      __syncthreads();
+      const double sq = sqrt(d), is = 1.0 / sq;
+      for (int i = c + 1 + lane; i < N; i += TEAM) A[pk(i, c)] *= is;
+      if (lane == 0) A[pk(c, c)] = sq;
+    }
+    __syncthreads();
+    // trailing tiles I >= J >= T0 (c0 + w = 16 T0 except after the last panel,
+    // which leaves none)
+    const int T0 = (c0 + w + 15) / 16, m = NT - T0;
+    for (int t = w_id; t < m * (m + 1) / 2; t += NW) {
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      const int J = T0 + (t - I * (I + 1) / 2);
+      I += T0;
+      dx4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + lc + 4 * r, j = 16 * J + li;
+        acc[r] = (i < N && j <= i) ? A[pk(i, j)] : 0.0;
+      }
+      const int ia = 16 * I + li, jb = 16 * J + li;
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk) {
+        const int q = 4 * kk + lc;
+        const double av = (ia < N && q < w) ? -A[pk(ia, c0 + q)] : 0.0;
+        const double bv = (jb < N && q < w) ? A[pk(jb, c0 + q)] : 0.0;
+        acc = mfma16x16x4(av, bv, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + lc + 4 * r, j = 16 * J + li;
+        if (i < N && j <= i) A[pk(i, j)] = acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  return bad;
+}
+
 template <class T, int N, int TEAM>
 __device__ __forceinline__ bool chol_packed(T* A, int lane) {
+  if constexpr (std::is_same<T, double>::value && TEAM % 64 == 0 && N >= 32) return chol_packed_mfma<N, TEAM>(A, lane);
   constexpr int NB = N >= 64 ? 8 : 4;
   constexpr int S = TEAM / N > 0 ? TEAM / N : 1;
   bool bad = false;
