@@ -49,7 +49,10 @@ struct GenericLayout {
   static constexpr bool kGlobal = K >= 3;
   static constexpr int QD = 10;  // per-qp: 6 weighted metric terms, div weight, 3 load weights
   static constexpr int stage = TEAM % 64 == 0 ? 2 * R::n * kAsmQC : 0;   // assembly tables
-  static constexpr int per = (kGlobal ? 0 : R::npk + R::nbpk) + R::Q * QD + R::n + 24 + R::nb + stage;
+  // the last area holds the assembly tables and, once the element matrix is
+  // assembled, the inverse face block (LDS-resident matrices)
+  static constexpr int area = kGlobal ? stage : (stage > R::nbpk ? stage : R::nbpk);
+  static constexpr int per = (kGlobal ? 0 : R::npk) + R::Q * QD + R::n + 24 + R::nb + area;
 };
 
 // Geometry at the Gauss points of one element (team of TEAM lanes): the
@@ -121,16 +124,71 @@ __device__ __forceinline__ double m_entry(const DeviceMaps& mp, const double* qd
   return s;
 }
 
-// Packed lower Cholesky factorization in place (LDS or global), right-
-// looking by panels of NB columns: each panel column is factored and applied
-// to the panel's later columns (one barrier per column; the column is scaled
-// after the barrier, it is not read again within the panel), then one
-// rank-NB update of the trailing triangle reads and writes every trailing
-// entry once per panel.  In the trailing update S = TEAM / N lanes share a
-// row and each keeps the row's NB panel entries in registers.  Returns true
-// (in every lane) when a pivot was not positive (replaced by 1).
-// The FP64 form for LDS-resident matrices and teams of whole waves: panels of
-// 16 columns aligned with 16 x 16 tiles, and the trailing update of every
+// The w x w (w <= 16) diagonal block at (c0, c0) of a packed lower triangle,
+// factored on one wave: lane l < w holds row c0 + l in registers, pivots and
+// column entries come by shuffle (no barrier).  A non-positive pivot is
+// replaced by 1 and reported.
+template <class T>
+__device__ __forceinline__ bool chol_diag16(T* A, int c0, int w, int l) {
+  T d[16];
+  const int i = c0 + l;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) d[j] = (l < w && j <= l) ? A[pk(i, c0 + j)] : T(0);
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    if (c < w) {
+      T piv = __shfl(d[c], c);
+      if (!(piv > T(0))) {
+        bad = true;
+        piv = T(1);
+      }
+      const T s = sqrt(piv), is = T(1) / s;
+      d[c] = l == c ? s : (l > c ? d[c] * is : d[c]);
+#pragma unroll
+      for (int j = c + 1; j < 16; ++j) {
+        const T ljc = __shfl(d[c], j);
+        if (l >= j) d[j] -= d[c] * ljc;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (l < w && j <= l) A[pk(i, c0 + j)] = d[j];
+  return bad;
+}
+
+// Rows c0 + w .. N - 1 of the panel: L_21 = A_21 L_11^{-T} with the factored
+// diagonal block L_11, one row per lane (its w entries in registers).
+template <class T, int N, int TEAM>
+__device__ __forceinline__ void chol_panel_rows(T* A, int c0, int w, int lane) {
+  for (int i = c0 + w + lane; i < N; i += TEAM) {
+    T* Ai = A + i * (i + 1) / 2 + c0;
+    T x[16], r[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      x[c] = c < w ? Ai[c] : T(0);
+      r[c] = c < w ? T(1) / A[pk(c0 + c, c0 + c)] : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c < w) {
+        const T* Lc = A + pk(c0 + c, c0);
+        T s = x[c];
+#pragma unroll
+        for (int q = 0; q < c; ++q) s -= x[q] * Lc[q];
+        x[c] = s * r[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < w) Ai[c] = x[c];
+  }
+}
+
+// The FP64 form for LDS-resident matrices and teams of whole waves, by panels
+// of 16 columns aligned with 16 x 16 tiles: the panel's diagonal block on one
+// wave, the rows below it one per lane, and the trailing update of every
 // lower tile (I, J) as C -= L_I L_J^T over the panel on the FP64 matrix
 // cores (four v_mfma_f64_16x16x4 per tile; the team's waves share out the
 // tiles; each trailing entry belongs to one tile).
@@ -142,24 +200,9 @@ __device__ __forceinline__ bool chol_packed_mfma(double* A, int lane) {
   bool bad = false;
   for (int c0 = 0; c0 < N; c0 += NB) {
     const int w = N - c0 < NB ? N - c0 : NB;
-    for (int c = c0; c < c0 + w; ++c) {
-      double d = A[pk(c, c)];
-      if (!(d > 0.0)) {
-        bad = true;
-        d = 1.0;
-      }
-      const double inv = 1.0 / d;
-      for (int i = c + 1 + lane; i < N; i += TEAM) {
-        double* Ai = A + i * (i + 1) / 2;
-        const double aic = Ai[c] * inv;
-        const int jend = i < c0 + w - 1 ? i : c0 + w - 1;
-        for (int j = c + 1; j <= jend; ++j) Ai[j] -= aic * A[pk(j, c)];
-      }
-      __syncthreads();
-      const double sq = sqrt(d), is = 1.0 / sq;
-      for (int i = c + 1 + lane; i < N; i += TEAM) A[pk(i, c)] *= is;
-      if (lane == 0) A[pk(c, c)] = sq;
-    }
+    if (w_id == 0) bad |= chol_diag16(A, c0, w, l);
+    __syncthreads();
+    chol_panel_rows<double, N, TEAM>(A, c0, w, lane);
     __syncthreads();
     // trailing tiles I >= J >= T0 (c0 + w = 16 T0 except after the last panel,
     // which leaves none)
@@ -194,6 +237,15 @@ __device__ __forceinline__ bool chol_packed_mfma(double* A, int lane) {
   return bad;
 }
 
+// Packed lower Cholesky factorization in place (LDS or global), right-
+// looking by panels of NB columns: each panel column is factored and applied
+// to the panel's later columns (one barrier per column; the column is scaled
+// after the barrier, it is not read again within the panel), then one
+// rank-NB update of the trailing triangle reads and writes every trailing
+// entry once per panel.  In the trailing update S = TEAM / N lanes share a
+// row and each keeps the row's NB panel entries in registers.  Returns true
+// (in every lane) when a pivot was not positive (replaced by 1).  FP64 on
+// LDS with teams of whole waves takes chol_packed_mfma.
 template <class T, int N, int TEAM>
 __device__ __forceinline__ bool chol_packed(T* A, int lane) {
   if constexpr (std::is_same<T, double>::value && TEAM % 64 == 0 && N >= 32) return chol_packed_mfma<N, TEAM>(A, lane);
@@ -393,12 +445,12 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   const int64_t es = live ? e : 0;  // safe index for loads of padding teams
   double* base = smem + team * Lay::per;
   double* A = Lay::kGlobal ? a.factor + es * R::npk : base;
-  double* Li = Lay::kGlobal ? nullptr : base + R::npk;
-  double* qd = Lay::kGlobal ? base : base + R::npk + R::nbpk;
+  double* qd = Lay::kGlobal ? base : base + R::npk;
   double* fh = qd + Q * QD;
   double* xe = fh + n;
   double* tb = xe + 24;
   double* stg = tb + nb;
+  double* Li = Lay::kGlobal ? nullptr : stg;   // written after the assembly
   // packed inverse of the face block: its own LDS array, or (global matrix)
   // the face block of A, inverted in place
   // (an HBM-resident matrix has its face block copied to the staging area
@@ -459,6 +511,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     for (int i = lane; i < n; i += TEAM) {
       const int d = R::comp(i);
       double s = 0.0;
+#pragma unroll 8
       for (int q = 0; q < Q; ++q) s += mp.tab_s[q * n + i] * qd[q * QD + 7 + d];
       if (is_ess(i)) {
         s = a.g ? a.g[es * nb + (i - ni)] : 0.0;
