@@ -24,11 +24,11 @@ struct BatchItem {
 };
 
 // Element blocks per order (teams x lanes = 512 threads for every order:
-// 32 x 16, 8 x 64, one element on 512 lanes for k = 2, 3).  Team sizes match
-// the single-plan kernels where the per-element arithmetic depends on them
-// (it does not: every entry is summed in a fixed order), so a batch gives
-// the single plans' bits.
-__host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 32 : (k == 1 ? 8 : 1); }
+// 32 x 16, 8 x 64, one element on 512 lanes for k = 2, two elements on 256
+// lanes each for k = 3, the team of the single-plan RT3 kernels).  The
+// per-element arithmetic does not depend on the team size (every entry is
+// summed in a fixed order), so a batch gives the single plans' bits.
+__host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 32 : (k == 1 ? 8 : (k == 2 ? 1 : 2)); }
 constexpr int kBatchThreads = 512;
 
 // Zero the same-face blocks of H (and r) of every problem: blockIdx.y is the
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* 
         case 0: setup_generic_body<0, 16, 32>(P.s, smem, blk); break;
         case 1: setup_generic_body<1, 64, 8>(P.s, smem, blk); break;
         case 2: setup_generic_body<2, 512, 1>(P.s, smem, blk); break;
-        default: setup_generic_body<3, 512, 1>(P.s, smem, blk); break;
+        default: setup_generic_body<3, 256, 2>(P.s, smem, blk); break;
       }
       __syncthreads();   // the next block reuses the LDS
     }
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
         case 0: recover_generic_body<0, 16, 32>(P.r, smem, blk); break;
         case 1: recover_generic_body<1, 64, 8>(P.r, smem, blk); break;
         case 2: recover_generic_body<2, 512, 1>(P.r, smem, blk); break;
-        default: recover_generic_body<3, 512, 1>(P.r, smem, blk); break;
+        default: recover_generic_body<3, 256, 2>(P.r, smem, blk); break;
       }
       __syncthreads();
     }
@@ -94,7 +94,7 @@ inline size_t batch_setup_lds(int k) {
     case 0: return 8 * 32 * size_t(GenericLayout<0, 16, 32>::per);
     case 1: return 8 * 8 * size_t(GenericLayout<1, 64, 8>::per);
     case 2: return 8 * size_t(GenericLayout<2, 512, 1>::per);
-    default: return 8 * size_t(GenericLayout<3, 512, 1>::per);
+    default: return 8 * 2 * size_t(GenericLayout<3, 256, 2>::per);
   }
 }
 inline size_t batch_recover_lds(int k) {
@@ -102,7 +102,7 @@ inline size_t batch_recover_lds(int k) {
     case 0: return 8 * 32 * size_t(recover_per<0>());
     case 1: return 8 * 8 * size_t(recover_per<1>());
     case 2: return 8 * size_t(recover_per<2>());
-    default: return 8 * size_t(recover_per<3>());
+    default: return 8 * 2 * size_t(recover_per<3>());
   }
 }
 

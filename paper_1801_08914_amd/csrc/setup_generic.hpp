@@ -292,61 +292,96 @@ __device__ __forceinline__ bool chol_packed(T* A, int lane) {
   return bad;
 }
 
-// chol_packed for a matrix in HBM (the element's record): each panel is
-// copied into LDS (P: (N - c0) x NB doubles), factored there and written
-// back, and the trailing update reads the panel from LDS, so the only HBM
-// traffic per trailing entry and panel is its read-modify-write.  The
-// operations and their order are those of chol_packed.
-template <class T, int N, int TEAM>
-__device__ __forceinline__ bool chol_packed_staged(T* A, T* P, int lane) {
-  constexpr int NB = N >= 64 ? 8 : 4;
-  constexpr int S = TEAM / N > 0 ? TEAM / N : 1;
+// chol_packed for an FP64 matrix in HBM (the element's record), teams of
+// whole waves, by panels of 16 columns staged column-major in LDS
+// (P[q * LD + r] = A[c0 + r][c0 + q], LD odd for conflict-free lanes): the
+// panel's diagonal block on one wave (registers and shuffles), the rows below
+// it one per lane, the finished panel written back, then the trailing update
+// A_ij -= sum_q L_iq L_jq over chunks of 64 columns: a lane keeps its column's
+// panel entries in registers and the team's waves take the chunk's rows in
+// turn, each row read and written as 64 consecutive entries.  With own false
+// (a padding team) nothing is written to A.
+template <int N, int TEAM>
+__device__ __forceinline__ bool chol_hbm16(double* A, double* P, int lane, bool own) {
+  constexpr int NB = 16, NW = TEAM / 64, LD = N | 1;
+  static_assert(TEAM % 64 == 0, "whole waves per team");
+  const int wv = lane / 64, l = lane % 64;
   bool bad = false;
   for (int c0 = 0; c0 < N; c0 += NB) {
-    const int w = N - c0 < NB ? N - c0 : NB;
-    // panel rows c0..N-1, columns c0..c0+w-1 (row i holds min(w, i - c0 + 1))
-    for (int t = lane; t < (N - c0) * NB; t += TEAM) {
+    const int w = N - c0 < NB ? N - c0 : NB, R = N - c0;
+    for (int t = lane; t < R * NB; t += TEAM) {
       const int r = t / NB, q = t % NB;
-      P[t] = (q < w && q <= r) ? A[pk(c0 + r, c0 + q)] : T(0);
+      P[q * LD + r] = (q < w && q <= r) ? A[pk(c0 + r, c0 + q)] : 0.0;
     }
     __syncthreads();
-    for (int c = c0; c < c0 + w; ++c) {
-      const int cc = c - c0;
-      T d = P[cc * NB + cc];
-      if (!(d > T(0))) {
-        bad = true;
-        d = T(1);
+    if (wv == 0) {
+      double d[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) d[j] = (l < w && j <= l) ? P[j * LD + l] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        if (c < w) {
+          double piv = __shfl(d[c], c);
+          if (!(piv > 0.0)) {
+            bad = true;
+            piv = 1.0;
+          }
+          const double sq = sqrt(piv), is = 1.0 / sq;
+          d[c] = l == c ? sq : (l > c ? d[c] * is : d[c]);
+#pragma unroll
+          for (int j = c + 1; j < 16; ++j) {
+            const double ljc = __shfl(d[c], j);
+            if (l >= j) d[j] -= d[c] * ljc;
+          }
+        }
       }
-      const T inv = T(1) / d;
-      for (int i = c + 1 + lane; i < N; i += TEAM) {
-        T* Pi = P + (i - c0) * NB;
-        const T aic = Pi[cc] * inv;
-        const int jend = i < c0 + w - 1 ? i : c0 + w - 1;
-        for (int j = c + 1; j <= jend; ++j) Pi[j - c0] -= aic * P[(j - c0) * NB + cc];
-      }
-      __syncthreads();
-      const T sq = sqrt(d), is = T(1) / sq;
-      for (int i = c + 1 + lane; i < N; i += TEAM) P[(i - c0) * NB + cc] *= is;
-      if (lane == 0) P[cc * NB + cc] = sq;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (l < w && j <= l) P[j * LD + l] = d[j];
     }
     __syncthreads();
-    for (int t = lane; t < (N - c0) * NB; t += TEAM) {
-      const int r = t / NB, q = t % NB;
-      if (q < w && q <= r) A[pk(c0 + r, c0 + q)] = P[t];
+    for (int r = w + lane; r < R; r += TEAM) {
+      double x[16], rc[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        x[c] = c < w ? P[c * LD + r] : 0.0;
+        rc[c] = c < w ? 1.0 / P[c * LD + c] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        if (c < w) {
+          double sum = x[c];
+#pragma unroll
+          for (int q = 0; q < c; ++q) sum -= x[q] * P[q * LD + c];
+          x[c] = sum * rc[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < w) P[c * LD + r] = x[c];
     }
-    for (int i = c0 + w + lane / S; i < N && lane / S < TEAM / S; i += TEAM / S) {
-      T* Ai = A + i * (i + 1) / 2;
-      const T* Pi = P + (i - c0) * NB;
-      T li[NB];
+    __syncthreads();
+    for (int t = lane; t < R * NB; t += TEAM) {
+      const int r = t / NB, q = t % NB;
+      if (own && q < w && q <= r) A[pk(c0 + r, c0 + q)] = P[q * LD + r];
+    }
+    for (int j0 = w; j0 < R; j0 += 64) {
+      const int jr = j0 + l;   // the lane's column, relative to c0
+      double pj[16];
 #pragma unroll
-      for (int t = 0; t < NB; ++t) li[t] = t < w ? Pi[t] : T(0);
-      for (int j = c0 + w + lane % S; j <= i; j += S) {
-        const T* Pj = P + (j - c0) * NB;
-        T acc = Ai[j];
+      for (int q = 0; q < 16; ++q) pj[q] = (q < w && jr < R) ? P[q * LD + jr] : 0.0;
+      for (int ir = j0 + wv; ir < R; ir += NW) {
+        double li[16];
 #pragma unroll
-        for (int t = 0; t < NB; ++t)
-          if (t < w) acc -= li[t] * Pj[t];
-        Ai[j] = acc;
+        for (int q = 0; q < 16; ++q) li[q] = q < w ? P[q * LD + ir] : 0.0;
+        if (own && jr <= ir) {
+          double* a = A + pk(c0 + ir, c0 + jr);
+          double acc = *a;
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            if (q < w) acc -= li[q] * pj[q];
+          *a = acc;
+        }
       }
     }
     __syncthreads();
@@ -445,6 +480,9 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   const int64_t es = live ? e : 0;  // safe index for loads of padding teams
   double* base = smem + team * Lay::per;
   double* A = Lay::kGlobal ? a.factor + es * R::npk : base;
+  // a padding team (past the last element) of an HBM-resident matrix reads
+  // element 0's record, which another team factors: it writes nothing there
+  const bool own = !Lay::kGlobal || live;
   double* qd = Lay::kGlobal ? base : base + R::npk;
   double* fh = qd + Q * QD;
   double* xe = fh + n;
@@ -497,12 +535,14 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   const bool store_matrix = need_matrix && (!Lay::kGlobal || (a.mode & MODE_MATRIX));
   if (store_matrix) {
     if constexpr (TEAM % 64 == 0) {
-      assemble_mfma<K, TEAM, kAsmQC>(mp, qd, stg, lane, [&](int i, int j, double v) { A[pk(i, j)] = v; });
+      assemble_mfma<K, TEAM, kAsmQC>(mp, qd, stg, lane, [&](int i, int j, double v) {
+        if (own) A[pk(i, j)] = v;
+      });
     } else {
       for (int p = lane; p < R::npk; p += TEAM) {
         int i, j;
         unpk(p, i, j);
-        A[p] = mij(i, j);
+        if (own) A[p] = mij(i, j);
       }
     }
     __syncthreads();
@@ -532,15 +572,15 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     for (int p = lane; p < R::npk; p += TEAM) {
       int i, j;
       unpk(p, i, j);
-      if (is_ess(i) || is_ess(j)) A[p] = (i == j) ? 1.0 : 0.0;
+      if (own && (is_ess(i) || is_ess(j))) A[p] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
     // Cholesky (interior block first, so L_bb L_bb^T is the element's Schur
     // complement onto its face dofs)
     bool notspd;
     if constexpr (Lay::kGlobal) {
-      static_assert(Lay::stage >= (n + 7) / 8 * 8 * 8, "the panel fits in the assembly staging area");
-      notspd = chol_packed_staged<double, n, TEAM>(A, stg, lane);
+      static_assert(Lay::stage >= 16 * (n | 1), "the panel fits in the assembly staging area");
+      notspd = chol_hbm16<n, TEAM>(A, stg, lane, own);
     } else {
       notspd = chol_packed<double, n, TEAM>(A, lane);
     }
@@ -615,7 +655,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       for (int t = lane; t < R::nbpk; t += TEAM) {
         int i, j;
         unpk(t, i, j);
-        A[pk(ni + i, ni + j)] = Fb[t];
+        if (own) A[pk(ni + i, ni + j)] = Fb[t];
       }
       fb_lds = true;
     }
@@ -727,8 +767,15 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   }
 }
 
+// Waves per SIMD the setup kernel is compiled for (registers): RT2 fits two
+// blocks of 512 lanes (LDS 81 KB each), four waves per SIMD, at no more than
+// 128 VGPRs.
+template <int K>
+constexpr int setup_min_waves() { return K == 2 ? 4 : 1; }
+
 template <int K, int TEAM, int EPB>
-__global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
+__global__ __launch_bounds__(TEAM* EPB) __attribute__((amdgpu_waves_per_eu(setup_min_waves<K>())))
+void k_setup_generic(SetupArgs a) {
   __shared__ double smem[EPB * GenericLayout<K, TEAM, EPB>::per];
   setup_generic_body<K, TEAM, EPB>(a, smem, blockIdx.x);
 }

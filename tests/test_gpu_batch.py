@@ -107,3 +107,34 @@ def test_batch_graph_replays_and_autotune():
     tuned = _outputs(torch, b, plans)
     for i in range(len(plans)):
         assert all(torch.equal(x, y) for x, y in zip(eager[i], tuned[i])), i
+
+
+def test_batch_padding_teams_leave_rt3_records_alone():
+    """RT3 runs two elements per block in a batch: with an odd element count
+    the last block has a padding team, whose safe element index is 0 and
+    whose matrix would be element 0's HBM record.  One- and 27-element RT3
+    problems (and an RT2 one between them) give the single plans' bits."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Plan
+    rng = np.random.default_rng(45)
+    probs = []
+    for n, k in ((1, 3), (3, 2), (3, 3)):
+        mesh = synth.structured_hex(n, jitter=0.2 if n > 1 else 0.0, rng=rng)
+        probs.append(synth.Problem(f"pad_k{k}_n{n}", mesh, k, synth.lognormal(rng, mesh.ne),
+                                   synth.lognormal(rng, mesh.ne, 0.5), synth.element_loads(rng, mesh.ne)))
+    b, plans, lams = _batch(torch, probs)
+    for rep in range(2):
+        b.setup()
+        b.recover()
+        got = _outputs(torch, b, plans)
+        for i, p in enumerate(probs):
+            single = Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True).bind()
+            single.setup(p.alpha, p.beta, p.f)
+            u = single.recover(torch.as_tensor(lams[i], device="cuda")).cpu()
+            torch.cuda.synchronize()
+            assert single.status()[0] == 0
+            val, r, ub = got[i]
+            print(f"  replay {rep} problem {i} k={p.k} ne={p.mesh.ne}", flush=True)
+            assert torch.equal(val.cpu(), single.csr()[2].cpu()), i
+            assert torch.equal(r.cpu(), single.r().cpu()), i
+            assert torch.equal(ub.cpu(), u), i
