@@ -280,7 +280,10 @@ void hyb_destroy(hyb_plan_t* plan);
  * Every order uses the generic element routines (Gauss quadrature, packed
  * Cholesky, inverse of the face block), so a batch sets its plans to that
  * record layout; H, r, y and u of each problem equal those of the plan's own
- * calls.  With graphs enabled the launch sequences are captured into hipGraphs
+ * calls.  HYB_MIXED plans run the mixed-precision element routines (the
+ * same as their own calls, so again the same bits) in a second persistent
+ * launch per phase over their work items, after the FP64 problems' launch.
+ * With graphs enabled the launch sequences are captured into hipGraphs
  * on the batch's own stream (ordered after and before the plans' stream by
  * events) and replayed; descriptors are device copies, so new coefficient
  * values written into the same buffers need no re-capture.
@@ -295,9 +298,9 @@ typedef struct {
 } hyb_batch_tiles;
 
 /* plans: count bound plans (the batch keeps pointers, it does not own them),
- * launched on plans[0]'s stream.  Errors: HYB_E_ARG (also for a HYB_MIXED or
- * HYB_STATIC plan: batches run the FP64 hybridization kernels), HYB_E_STATE (unbound),
- * HYB_E_NOMEM, HYB_E_HIP. */
+ * launched on plans[0]'s stream; FP64 and HYB_MIXED plans may be mixed.
+ * Errors: HYB_E_ARG (also for a HYB_STATIC plan: batches run the
+ * hybridization kernels), HYB_E_STATE (unbound), HYB_E_NOMEM, HYB_E_HIP. */
 int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out);
 
 /* Device inputs of problem p: alpha, beta (ne), f (ne x 3, NULL: matrix

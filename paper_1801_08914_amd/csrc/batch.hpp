@@ -4,6 +4,7 @@
 #pragma once
 
 #include "kernels_common.hpp"
+#include "mixed.hpp"
 #include "setup_generic.hpp"
 
 namespace hyb {
@@ -13,6 +14,8 @@ struct BatchProb {
   RecoverArgs r;     // recovery of the problem
   int32_t k;
   int32_t K2;        // (k+1)^2
+  int32_t mixed;     // HYB_MIXED problem (the mixed element routines)
+  int32_t sweeps;    // its refinement sweeps (< 0: adaptive)
   int64_t nfaces;
   int64_t m;
 };
@@ -29,6 +32,10 @@ struct BatchItem {
 // per-element arithmetic does not depend on the team size (every entry is
 // summed in a fixed order), so a batch gives the single plans' bits.
 __host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 32 : (k == 1 ? 8 : (k == 2 ? 1 : 2)); }
+// Mixed-precision problems: 32 x 16, 4 x 128 (eight RT1 mixed layouts
+// would exceed the LDS), then one element per block (the RT3 mixed record
+// holds M_T and X in HBM: one element per block).
+__host__ __device__ constexpr int batch_epb_mixed(int k) { return k == 0 ? 32 : (k == 1 ? 4 : 1); }
 constexpr int kBatchThreads = 512;
 
 // Zero the same-face blocks of H (and r) of every problem: blockIdx.y is the
@@ -88,6 +95,47 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
   }
 }
 
+// The same two phases for the batch's mixed-precision problems (their work
+// items follow the FP64 ones in the list; a separate launch, so the FP64
+// kernels keep their own LDS size).
+__global__ __launch_bounds__(kBatchThreads) void k_setup_batch_mixed(const BatchProb* probs, const BatchItem* items,
+                                                                     int64_t nitems) {
+  extern __shared__ double smem[];
+  for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const BatchItem it = items[w];
+    const BatchProb& P = probs[it.prob];
+    for (int b = 0; b < it.nblk; ++b) {
+      const int64_t blk = it.blk0 + b;
+      switch (P.k) {
+        case 0: setup_mixed_body<0, 16, 32>(P.s, smem, blk, P.sweeps); break;
+        case 1: setup_mixed_body<1, 128, 4>(P.s, smem, blk, P.sweeps); break;
+        case 2: setup_mixed_body<2, 512, 1>(P.s, smem, blk, P.sweeps); break;
+        default: setup_mixed_body<3, 512, 1>(P.s, smem, blk, P.sweeps); break;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBatchThreads) void k_recover_batch_mixed(const BatchProb* probs,
+                                                                       const BatchItem* items, int64_t nitems) {
+  extern __shared__ double smem[];
+  for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const BatchItem it = items[w];
+    const BatchProb& P = probs[it.prob];
+    for (int b = 0; b < it.nblk; ++b) {
+      const int64_t blk = it.blk0 + b;
+      switch (P.k) {
+        case 0: recover_mixed_body<0, 16, 32>(P.r, smem, blk); break;
+        case 1: recover_mixed_body<1, 128, 4>(P.r, smem, blk); break;
+        case 2: recover_mixed_body<2, 512, 1>(P.r, smem, blk); break;
+        default: recover_mixed_body<3, 512, 1>(P.r, smem, blk); break;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // LDS bytes of one block of the batch kernels for order k.
 inline size_t batch_setup_lds(int k) {
   switch (k) {
@@ -103,6 +151,23 @@ inline size_t batch_recover_lds(int k) {
     case 1: return 8 * 8 * size_t(recover_per<1>());
     case 2: return 8 * size_t(recover_per<2>());
     default: return 8 * 2 * size_t(recover_per<3>());
+  }
+}
+
+inline size_t batch_setup_lds_mixed(int k) {
+  switch (k) {
+    case 0: return 8 * 32 * size_t(MixedLayout<0, 16, 32>::per);
+    case 1: return 8 * 4 * size_t(MixedLayout<1, 128, 4>::per);
+    case 2: return 8 * size_t(MixedLayout<2, 512, 1>::per);
+    default: return 8 * size_t(MixedLayout<3, 512, 1>::per);
+  }
+}
+inline size_t batch_recover_lds_mixed(int k) {
+  switch (k) {
+    case 0: return 8 * 32 * size_t(RT<0>::nb);
+    case 1: return 8 * 4 * size_t(RT<1>::nb);
+    case 2: return 8 * size_t(RT<2>::nb);
+    default: return 8 * size_t(RT<3>::nb);
   }
 }
 

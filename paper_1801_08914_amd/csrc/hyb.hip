@@ -669,11 +669,12 @@ struct hyb_batch {
   int cus = 0;
   hyb_batch_tiles tiles{0, 0};
   std::vector<hyb::BatchProb> probs;       // host copy of the descriptors
-  std::vector<hyb::BatchItem> items;       // cost-sorted work list
+  std::vector<hyb::BatchItem> items;       // cost-sorted work list: FP64 problems' items, then mixed
+  size_t n64 = 0;                          // items of FP64 problems (the first n64)
   hyb::BatchProb* d_probs = nullptr;
   hyb::BatchItem* d_items = nullptr;
   size_t cap_items = 0;
-  size_t lds_setup = 0, lds_recover = 0;
+  size_t lds_setup = 0, lds_recover = 0, lds_setup_mx = 0, lds_recover_mx = 0;
   bool dirty = true;                       // descriptors or items changed since upload
   bool use_graph = false;
   hipGraphExec_t g_setup = nullptr, g_recover = nullptr;
@@ -683,11 +684,14 @@ struct hyb_batch {
 
 namespace {
 
-// Relative cost of one element block of order k (flops of assembly and
-// factorization of the batch kernels, per block of batch_epb(k) elements).
-double batch_block_cost(int k) {
+int batch_epb_of(const hyb::Plan& P) { return P.mixed ? hyb::batch_epb_mixed(P.ord.k) : hyb::batch_epb(P.ord.k); }
+
+// Relative cost of one element block of a plan (flops of assembly and
+// factorization of the batch kernels, per block of its elements).
+double batch_block_cost(const hyb::Plan& P) {
+  const int k = P.ord.k;
   const double n = 3.0 * (k + 1) * (k + 1) * (k + 2), Q = double((k + 2) * (k + 2) * (k + 2));
-  return hyb::batch_epb(k) * (2.0 * n * n * Q / 2 + n * n * n / 3);
+  return batch_epb_of(P) * (2.0 * n * n * Q / 2 + n * n * n / 3);
 }
 
 int batch_tiles_effective(const hyb_batch* b, int& bpc, int& ipb) {
@@ -702,7 +706,7 @@ void batch_build_items(hyb_batch* b) {
   b->items.clear();
   for (size_t p = 0; p < b->plans.size(); ++p) {
     const hyb::Plan& P = b->plans[p]->P;
-    const int epb = hyb::batch_epb(P.ord.k);
+    const int epb = batch_epb_of(P);
     const int64_t nblk = (P.ne + epb - 1) / epb;
     for (int64_t q = 0; q < nblk; q += ipb) {
       hyb::BatchItem it{};
@@ -712,10 +716,15 @@ void batch_build_items(hyb_batch* b) {
       b->items.push_back(it);
     }
   }
-  // most expensive first (orders descending), stable: deterministic order
+  // FP64 problems' items first, then the mixed ones; within each most
+  // expensive first (orders descending), stable: deterministic order
   std::stable_sort(b->items.begin(), b->items.end(), [&](const hyb::BatchItem& x, const hyb::BatchItem& y) {
-    return batch_block_cost(b->plans[x.prob]->P.ord.k) * x.nblk > batch_block_cost(b->plans[y.prob]->P.ord.k) * y.nblk;
+    const hyb::Plan &px = b->plans[x.prob]->P, &py = b->plans[y.prob]->P;
+    if (px.mixed != py.mixed) return !px.mixed;
+    return batch_block_cost(px) * x.nblk > batch_block_cost(py) * y.nblk;
   });
+  b->n64 = 0;
+  while (b->n64 < b->items.size() && !b->plans[b->items[b->n64].prob]->P.mixed) ++b->n64;
   b->dirty = true;
 }
 
@@ -742,12 +751,11 @@ int batch_upload(hyb_batch* b) {
   return HYB_OK;
 }
 
-unsigned batch_grid(const hyb_batch* b) {
+unsigned batch_grid(const hyb_batch* b, size_t nitems) {
   int bpc, ipb;
   batch_tiles_effective(b, bpc, ipb);
   const int64_t want = int64_t(bpc) * b->cus;
-  const int64_t n = int64_t(b->items.size());
-  return unsigned(std::max<int64_t>(1, std::min(want, n)));
+  return unsigned(std::max<int64_t>(1, std::min(want, int64_t(nitems))));
 }
 
 int batch_launch_setup(hyb_batch* b, hipStream_t st) {
@@ -756,18 +764,30 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
   const unsigned zx = unsigned(std::min<int64_t>((zmax + 255) / 256, 1024));
   hipLaunchKernelGGL(hyb::k_batch_zero, dim3(zx, unsigned(b->probs.size())), dim3(256), 0, st, b->d_probs);
   HYB_HIP(hipGetLastError());
-  if (!b->items.empty()) {
-    hipLaunchKernelGGL(hyb::k_setup_batch, dim3(batch_grid(b)), dim3(hyb::kBatchThreads), b->lds_setup, st,
-                       b->d_probs, b->d_items, int64_t(b->items.size()));
+  const size_t nmx = b->items.size() - b->n64;
+  if (b->n64) {
+    hipLaunchKernelGGL(hyb::k_setup_batch, dim3(batch_grid(b, b->n64)), dim3(hyb::kBatchThreads), b->lds_setup, st,
+                       b->d_probs, b->d_items, int64_t(b->n64));
+    HYB_HIP(hipGetLastError());
+  }
+  if (nmx) {
+    hipLaunchKernelGGL(hyb::k_setup_batch_mixed, dim3(batch_grid(b, nmx)), dim3(hyb::kBatchThreads),
+                       b->lds_setup_mx, st, b->d_probs, b->d_items + b->n64, int64_t(nmx));
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
 }
 
 int batch_launch_recover(hyb_batch* b, hipStream_t st) {
-  if (!b->items.empty()) {
-    hipLaunchKernelGGL(hyb::k_recover_batch, dim3(batch_grid(b)), dim3(hyb::kBatchThreads), b->lds_recover, st,
-                       b->d_probs, b->d_items, int64_t(b->items.size()));
+  const size_t nmx = b->items.size() - b->n64;
+  if (b->n64) {
+    hipLaunchKernelGGL(hyb::k_recover_batch, dim3(batch_grid(b, b->n64)), dim3(hyb::kBatchThreads), b->lds_recover,
+                       st, b->d_probs, b->d_items, int64_t(b->n64));
+    HYB_HIP(hipGetLastError());
+  }
+  if (nmx) {
+    hipLaunchKernelGGL(hyb::k_recover_batch_mixed, dim3(batch_grid(b, nmx)), dim3(hyb::kBatchThreads),
+                       b->lds_recover_mx, st, b->d_probs, b->d_items + b->n64, int64_t(nmx));
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
@@ -814,7 +834,7 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
     if (!plans[i]) return HYB_E_ARG;
   for (int32_t i = 0; i < count; ++i) {
     if (!plans[i]->P.bound) return HYB_E_STATE;
-    if (plans[i]->P.mixed || plans[i]->P.stat) return HYB_E_ARG;   // FP64 hybridization only
+    if (plans[i]->P.stat) return HYB_E_ARG;   // hybridization (FP64 or mixed) only
   }
   hyb_batch* b = new (std::nothrow) hyb_batch;
   if (!b) return HYB_E_NOMEM;
@@ -833,6 +853,8 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
     pr = hyb::BatchProb{};
     pr.k = P.ord.k;
     pr.K2 = P.ord.K2;
+    pr.mixed = P.mixed ? 1 : 0;
+    pr.sweeps = P.sweeps;
     pr.nfaces = P.nfaces;
     pr.m = P.m;
     pr.s.mp = device_maps(P);
@@ -847,8 +869,13 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
     pr.r.ne = P.ne;
     pr.r.factor = P.buf.factor;
     pr.r.y = P.buf.y;
-    b->lds_setup = std::max(b->lds_setup, hyb::batch_setup_lds(P.ord.k));
-    b->lds_recover = std::max(b->lds_recover, hyb::batch_recover_lds(P.ord.k));
+    if (P.mixed) {
+      b->lds_setup_mx = std::max(b->lds_setup_mx, hyb::batch_setup_lds_mixed(P.ord.k));
+      b->lds_recover_mx = std::max(b->lds_recover_mx, hyb::batch_recover_lds_mixed(P.ord.k));
+    } else {
+      b->lds_setup = std::max(b->lds_setup, hyb::batch_setup_lds(P.ord.k));
+      b->lds_recover = std::max(b->lds_recover, hyb::batch_recover_lds(P.ord.k));
+    }
   }
   hipError_t e1 = hipMalloc(&b->d_probs, sizeof(hyb::BatchProb) * b->probs.size());
   if (e1 == hipSuccess) e1 = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
@@ -860,6 +887,12 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
   if (e1 == hipSuccess)
     e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(hyb::k_recover_batch),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_recover));
+  if (e1 == hipSuccess && b->lds_setup_mx)
+    e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(hyb::k_setup_batch_mixed),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_setup_mx));
+  if (e1 == hipSuccess && b->lds_recover_mx)
+    e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(hyb::k_recover_batch_mixed),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_recover_mx));
   if (e1 != hipSuccess) {
     hyb_batch_destroy(b);
     return hip_fail(e1);

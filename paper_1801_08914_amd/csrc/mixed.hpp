@@ -388,18 +388,18 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_mixed(SetupArgs a, int swee
 }
 
 // u_T = y - X lambda_T, lambda_T the element's face multipliers in its own
-// frame (0 on boundary faces); X carries the signs of C_T.
+// frame (0 on boundary faces); X carries the signs of C_T.  smem: EPB * nb
+// doubles.
 template <int K, int TEAM, int EPB>
-__global__ __launch_bounds__(TEAM* EPB) void k_recover_mixed(RecoverArgs a) {
+__device__ __forceinline__ void recover_mixed_body(const RecoverArgs& a, double* smem, int64_t blk) {
   using R = RT<K>;
   using Rec = MixedRec<K>;
   constexpr int n = R::n, nb = R::nb, K1 = R::K1, K2 = R::K2;
-  __shared__ double tl_all[EPB * nb];
   const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
-  const int64_t e = int64_t(blockIdx.x) * EPB + team;
+  const int64_t e = blk * EPB + team;
   const bool live = e < a.ne;
   const int64_t es = live ? e : 0;
-  double* tl = tl_all + team * nb;
+  double* tl = smem + team * nb;
   const DeviceMaps& mp = a.mp;
   for (int b = lane; b < nb; b += TEAM) {
     const int fb = b / K2;
@@ -413,13 +413,20 @@ __global__ __launch_bounds__(TEAM* EPB) void k_recover_mixed(RecoverArgs a) {
     tl[b] = v;
   }
   __syncthreads();
-  if (!live) return;
-  const double* X = a.factor + es * Rec::len + Rec::x;
-  for (int i = lane; i < n; i += TEAM) {
-    double s = a.y[es * n + i];
-    for (int b = 0; b < nb; ++b) s -= X[int64_t(b) * n + i] * tl[b];
-    a.u[es * n + i] = s;
+  if (live) {
+    const double* X = a.factor + es * Rec::len + Rec::x;
+    for (int i = lane; i < n; i += TEAM) {
+      double s = a.y[es * n + i];
+      for (int b = 0; b < nb; ++b) s -= X[int64_t(b) * n + i] * tl[b];
+      a.u[es * n + i] = s;
+    }
   }
+}
+
+template <int K, int TEAM, int EPB>
+__global__ __launch_bounds__(TEAM* EPB) void k_recover_mixed(RecoverArgs a) {
+  __shared__ double tl_all[EPB * RT<K>::nb];
+  recover_mixed_body<K, TEAM, EPB>(a, tl_all, blockIdx.x);
 }
 
 }  // namespace hyb

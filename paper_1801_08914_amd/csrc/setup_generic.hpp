@@ -767,15 +767,8 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   }
 }
 
-// Waves per SIMD the setup kernel is compiled for (registers): RT2 fits two
-// blocks of 512 lanes (LDS 81 KB each), four waves per SIMD, at no more than
-// 128 VGPRs.
-template <int K>
-constexpr int setup_min_waves() { return K == 2 ? 4 : 1; }
-
 template <int K, int TEAM, int EPB>
-__global__ __launch_bounds__(TEAM* EPB) __attribute__((amdgpu_waves_per_eu(setup_min_waves<K>())))
-void k_setup_generic(SetupArgs a) {
+__global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
   __shared__ double smem[EPB * GenericLayout<K, TEAM, EPB>::per];
   setup_generic_body<K, TEAM, EPB>(a, smem, blockIdx.x);
 }

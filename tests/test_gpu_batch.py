@@ -138,3 +138,56 @@ def test_batch_padding_teams_leave_rt3_records_alone():
             assert torch.equal(val.cpu(), single.csr()[2].cpu()), i
             assert torch.equal(r.cpu(), single.r().cpu()), i
             assert torch.equal(ub.cpu(), u), i
+
+
+def test_batch_mixed_and_fp64_plans_together():
+    """A batch of FP64 and mixed-precision (HYB_MIXED) problems of every
+    order: the mixed problems run in their own persistent launch per phase;
+    every problem gives its single plan's bits, on eager launches and on
+    every graph replay, and the mixed ones stay within the refined bound of
+    the oracle's solution."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Batch, Plan
+    probs = synth.config_c4(nprob=8, nmin=2, nmax=3, seed=47)
+    ks = [p.k for p in probs]
+    print("orders", ks, "elements", [p.mesh.ne for p in probs], flush=True)
+    assert sorted(set(ks)) == [0, 1, 2, 3]
+    # per order: the first problem mixed, the rest FP64
+    mixed = [ks.index(k) == i for i, k in enumerate(ks)]
+    prec = ["mixed" if mx else "fp64" for mx in mixed]
+    plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True, precision=pc).bind() for p, pc in zip(probs, prec)]
+    b = Batch(plans)
+    rng = np.random.default_rng(48)
+    lams = [rng.standard_normal(max(pl.m, 1)) for pl in plans]
+    for i, p in enumerate(probs):
+        b.set(i, p.alpha, p.beta, p.f, lam=lams[i])
+    singles = []
+    for i, p in enumerate(probs):
+        single = Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True, precision=prec[i]).bind()
+        single.setup(p.alpha, p.beta, p.f)
+        u = single.recover(torch.as_tensor(lams[i], device="cuda")).cpu()
+        torch.cuda.synchronize()
+        assert single.status()[0] == 0, (i, single.status())
+        singles.append((single.csr()[2].cpu(), single.r().cpu(), u))
+    for graph in (False, True, True):
+        b.graph(graph)
+        b.setup()
+        b.recover()
+        got = _outputs(torch, b, plans)
+        for i in range(len(probs)):
+            val, r, ub = got[i]
+            print(f"  graph={graph} problem {i} k={ks[i]} {prec[i]}", flush=True)
+            assert torch.equal(val.cpu(), singles[i][0]), i
+            assert torch.equal(r.cpu(), singles[i][1]), i
+            assert torch.equal(ub.cpu(), singles[i][2]), i
+        torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        if not mixed[i]:
+            continue
+        args = (p.k, p.mesh.xyz, p.mesh.e2v, p.alpha, p.beta, p.f)
+        ref = ohyb.hybridize(*args)
+        Hg = sp.csr_matrix((singles[i][0].numpy(), ref.H.indices, ref.H.indptr), shape=ref.H.shape)
+        eH = norm_rel(ref.H.toarray(), Hg.toarray())
+        er = norm_rel(ref.r, singles[i][1].numpy())
+        print(f"  mixed problem {i} k={p.k}: H {eH:.1e} r {er:.1e} vs the FP64 oracle", flush=True)
+        assert max(eH, er) <= 1e-10

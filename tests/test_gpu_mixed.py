@@ -145,10 +145,7 @@ def test_mixed_reports_what_fp32_cannot_factor():
 
 def test_mixed_argument_errors():
     require_gpu()
-    from paper_1801_08914_amd import Batch, HybError, Plan
+    from paper_1801_08914_amd import HybError, Plan
     mesh = synth.structured_hex(2)
     with pytest.raises(HybError):
         Plan(mesh.xyz, mesh.e2v, 1, precision="mixed", sweeps=99)
-    plan = Plan(mesh.xyz, mesh.e2v, 1, precision="mixed").bind()
-    with pytest.raises(HybError):
-        Batch([plan])
