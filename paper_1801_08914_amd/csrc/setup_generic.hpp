@@ -615,6 +615,33 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
           }
         }
       }
+    } else if constexpr (!Lay::kGlobal && TEAM % 64 == 0 && nb <= 64) {
+      // Inverse of the face block L_bb, its columns dealt to the waves: lane
+      // l holds row l of RC columns in registers, forward substitution row by
+      // row, each solved entry broadcast by shuffle (no block barrier); per
+      // entry the sum runs over c = col..i-1 in order, as in the loop below.
+      constexpr int NW = TEAM / 64, RC = (nb + NW - 1) / NW;
+      const int wv = lane / 64, l = lane % 64;
+      double x[RC];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) x[r] = (l == wv + NW * r) ? 1.0 : 0.0;
+      for (int c = 0; c < nb; ++c) {
+        const double lcc = A[pk(ni + c, ni + c)];
+        const double lic = (l > c && l < nb) ? A[pk(ni + l, ni + c)] : 0.0;
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+          if (wv + NW * r <= c) {   // uniform across the wave
+            if (l == c) x[r] = x[r] / lcc;
+            const double xc = __shfl(x[r], c);
+            if (l > c) x[r] -= lic * xc;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+        const int col = wv + NW * r;
+        if (col < nb && l >= col && l < nb) Li[pk(l, col)] = x[r];
+      }
     } else if constexpr (!Lay::kGlobal) {
       // Inverse of the face block L_bb, one column per thread.
       for (int col = lane; col < nb; col += TEAM) {
