@@ -48,7 +48,9 @@ struct GenericLayout {
   using R = RT<K>;
   static constexpr bool kGlobal = K >= 3;
   static constexpr int QD = 10;  // per-qp: 6 weighted metric terms, div weight, 3 load weights
-  static constexpr int stage = TEAM % 64 == 0 ? 2 * R::n * kAsmQC : 0;   // assembly tables
+  // assembly tables (and, HBM-resident matrices, the Cholesky's 32-column panel)
+  static constexpr int stage_asm = TEAM % 64 == 0 ? 2 * R::n * kAsmQC : 0;
+  static constexpr int stage = kGlobal && stage_asm < 32 * (R::n | 1) ? 32 * (R::n | 1) : stage_asm;
   // the last area holds the assembly tables and, once the element matrix is
   // assembled, the inverse face block (LDS-resident matrices)
   static constexpr int area = kGlobal ? stage : (stage > R::nbpk ? stage : R::nbpk);
@@ -293,17 +295,19 @@ __device__ __forceinline__ bool chol_packed(T* A, int lane) {
 }
 
 // chol_packed for an FP64 matrix in HBM (the element's record), teams of
-// whole waves, by panels of 16 columns staged column-major in LDS
-// (P[q * LD + r] = A[c0 + r][c0 + q], LD odd for conflict-free lanes): the
-// panel's diagonal block on one wave (registers and shuffles), the rows below
-// it one per lane, the finished panel written back, then the trailing update
-// A_ij -= sum_q L_iq L_jq over chunks of 64 columns: a lane keeps its column's
-// panel entries in registers and the team's waves take the chunk's rows in
-// turn, each row read and written as 64 consecutive entries.  With own false
-// (a padding team) nothing is written to A.
+// whole waves, by panels of 32 columns staged column-major in LDS
+// (P[q * LD + r] = A[c0 + r][c0 + q], LD odd for conflict-free lanes).  The
+// panel is factored in LDS as two sub-panels of 16: each one's diagonal block
+// on one wave (registers and shuffles), the rows below it one per lane, the
+// second sub-panel first updated by the first.  The finished panel is written
+// back, then the trailing update A_ij -= sum_q L_iq L_jq runs over chunks of
+// 64 columns: a lane keeps its column's panel entries in registers and the
+// team's waves take the chunk's rows in turn, each row read and written as 64
+// consecutive entries (one HBM read-modify-write per trailing entry and
+// panel).  With own false (a padding team) nothing is written to A.
 template <int N, int TEAM>
-__device__ __forceinline__ bool chol_hbm16(double* A, double* P, int lane, bool own) {
-  constexpr int NB = 16, NW = TEAM / 64, LD = N | 1;
+__device__ __forceinline__ bool chol_hbm32(double* A, double* P, int lane, bool own) {
+  constexpr int NB = 32, NW = TEAM / 64, LD = N | 1;
   static_assert(TEAM % 64 == 0, "whole waves per team");
   const int wv = lane / 64, l = lane % 64;
   bool bad = false;
@@ -314,72 +318,90 @@ __device__ __forceinline__ bool chol_hbm16(double* A, double* P, int lane, bool 
       P[q * LD + r] = (q < w && q <= r) ? A[pk(c0 + r, c0 + q)] : 0.0;
     }
     __syncthreads();
-    if (wv == 0) {
-      double d[16];
+    for (int s0 = 0; s0 < w; s0 += 16) {
+      const int ws = w - s0 < 16 ? w - s0 : 16;
+      if (s0 > 0) {
+        // the second sub-panel's columns minus the first's contribution
+        for (int r = s0 + lane; r < R; r += TEAM) {
+          double x[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) d[j] = (l < w && j <= l) ? P[j * LD + l] : 0.0;
+          for (int t = 0; t < 16; ++t) x[t] = P[t * LD + r];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        if (c < w) {
-          double piv = __shfl(d[c], c);
-          if (!(piv > 0.0)) {
-            bad = true;
-            piv = 1.0;
-          }
-          const double sq = sqrt(piv), is = 1.0 / sq;
-          d[c] = l == c ? sq : (l > c ? d[c] * is : d[c]);
+          for (int q = 0; q < 16; ++q) {
+            if (q < ws && s0 + q <= r) {
+              double acc = P[(s0 + q) * LD + r];
 #pragma unroll
-          for (int j = c + 1; j < 16; ++j) {
-            const double ljc = __shfl(d[c], j);
-            if (l >= j) d[j] -= d[c] * ljc;
+              for (int t = 0; t < 16; ++t) acc -= x[t] * P[t * LD + s0 + q];
+              P[(s0 + q) * LD + r] = acc;
+            }
           }
         }
+        __syncthreads();
       }
+      if (wv == 0) {
+        double d[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (l < w && j <= l) P[j * LD + l] = d[j];
-    }
-    __syncthreads();
-    for (int r = w + lane; r < R; r += TEAM) {
-      double x[16], rc[16];
+        for (int j = 0; j < 16; ++j) d[j] = (l < ws && j <= l) ? P[(s0 + j) * LD + s0 + l] : 0.0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        x[c] = c < w ? P[c * LD + r] : 0.0;
-        rc[c] = c < w ? 1.0 / P[c * LD + c] : 0.0;
-      }
+        for (int c = 0; c < 16; ++c) {
+          if (c < ws) {
+            double piv = __shfl(d[c], c);
+            if (!(piv > 0.0)) {
+              bad = true;
+              piv = 1.0;
+            }
+            const double sq = sqrt(piv), is = 1.0 / sq;
+            d[c] = l == c ? sq : (l > c ? d[c] * is : d[c]);
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        if (c < w) {
-          double sum = x[c];
-#pragma unroll
-          for (int q = 0; q < c; ++q) sum -= x[q] * P[q * LD + c];
-          x[c] = sum * rc[c];
+            for (int j = c + 1; j < 16; ++j) {
+              const double ljc = __shfl(d[c], j);
+              if (l >= j) d[j] -= d[c] * ljc;
+            }
+          }
         }
-      }
 #pragma unroll
-      for (int c = 0; c < 16; ++c)
-        if (c < w) P[c * LD + r] = x[c];
+        for (int j = 0; j < 16; ++j)
+          if (l < ws && j <= l) P[(s0 + j) * LD + s0 + l] = d[j];
+      }
+      __syncthreads();
+      for (int r = s0 + ws + lane; r < R; r += TEAM) {
+        double x[16], rc[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          x[c] = c < ws ? P[(s0 + c) * LD + r] : 0.0;
+          rc[c] = c < ws ? 1.0 / P[(s0 + c) * LD + s0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c < ws) {
+            double sum = x[c];
+#pragma unroll
+            for (int q = 0; q < c; ++q) sum -= x[q] * P[(s0 + q) * LD + s0 + c];
+            x[c] = sum * rc[c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c < ws) P[(s0 + c) * LD + r] = x[c];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (int t = lane; t < R * NB; t += TEAM) {
       const int r = t / NB, q = t % NB;
       if (own && q < w && q <= r) A[pk(c0 + r, c0 + q)] = P[q * LD + r];
     }
     for (int j0 = w; j0 < R; j0 += 64) {
       const int jr = j0 + l;   // the lane's column, relative to c0
-      double pj[16];
+      double pj[NB];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) pj[q] = (q < w && jr < R) ? P[q * LD + jr] : 0.0;
+      for (int q = 0; q < NB; ++q) pj[q] = (q < w && jr < R) ? P[q * LD + jr] : 0.0;
       for (int ir = j0 + wv; ir < R; ir += NW) {
-        double li[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) li[q] = q < w ? P[q * LD + ir] : 0.0;
         if (own && jr <= ir) {
           double* a = A + pk(c0 + ir, c0 + jr);
           double acc = *a;
 #pragma unroll
-          for (int q = 0; q < 16; ++q)
-            if (q < w) acc -= li[q] * pj[q];
+          for (int q = 0; q < NB; ++q)
+            if (q < w) acc -= P[q * LD + ir] * pj[q];
           *a = acc;
         }
       }
@@ -579,8 +601,8 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     // complement onto its face dofs)
     bool notspd;
     if constexpr (Lay::kGlobal) {
-      static_assert(Lay::stage >= 16 * (n | 1), "the panel fits in the assembly staging area");
-      notspd = chol_hbm16<n, TEAM>(A, stg, lane, own);
+      static_assert(Lay::stage >= 32 * (n | 1), "the panel fits in the staging area");
+      notspd = chol_hbm32<n, TEAM>(A, stg, lane, own);
     } else {
       notspd = chol_packed<double, n, TEAM>(A, lane);
     }
