@@ -38,6 +38,22 @@ __host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 32 : (k == 
 __host__ __device__ constexpr int batch_epb_mixed(int k) { return k == 0 ? 32 : (k == 1 ? 4 : 1); }
 constexpr int kBatchThreads = 512;
 
+// The order-specific element routines as separate functions: inlined into
+// one persistent kernel, the four bodies share one register allocation (and
+// spill); called, each keeps its own.  A call per element block.
+template <int K, int TEAM, int EPB>
+__device__ __attribute__((noinline)) void batch_setup_fp64(const SetupArgs& a, double* smem, int64_t blk) {
+  setup_generic_body<K, TEAM, EPB>(a, smem, blk);
+}
+template <int K, int TEAM, int EPB>
+__device__ __attribute__((noinline)) void batch_recover_fp64(const RecoverArgs& a, double* smem, int64_t blk) {
+  recover_generic_body<K, TEAM, EPB>(a, smem, blk);
+}
+template <int K, int TEAM, int EPB>
+__device__ __attribute__((noinline)) void batch_setup_mx(const SetupArgs& a, double* smem, int64_t blk, int sweeps) {
+  setup_mixed_body<K, TEAM, EPB>(a, smem, blk, sweeps);
+}
+
 // Zero the same-face blocks of H (and r) of every problem: blockIdx.y is the
 // problem.
 __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
@@ -66,10 +82,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* 
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
       switch (P.k) {
-        case 0: setup_generic_body<0, 16, 32>(P.s, smem, blk); break;
-        case 1: setup_generic_body<1, 64, 8>(P.s, smem, blk); break;
-        case 2: setup_generic_body<2, 512, 1>(P.s, smem, blk); break;
-        default: setup_generic_body<3, 256, 2>(P.s, smem, blk); break;
+        case 0: batch_setup_fp64<0, 16, 32>(P.s, smem, blk); break;
+        case 1: batch_setup_fp64<1, 64, 8>(P.s, smem, blk); break;
+        case 2: batch_setup_fp64<2, 512, 1>(P.s, smem, blk); break;
+        default: batch_setup_fp64<3, 256, 2>(P.s, smem, blk); break;
       }
       __syncthreads();   // the next block reuses the LDS
     }
@@ -85,10 +101,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
       switch (P.k) {
-        case 0: recover_generic_body<0, 16, 32>(P.r, smem, blk); break;
-        case 1: recover_generic_body<1, 64, 8>(P.r, smem, blk); break;
-        case 2: recover_generic_body<2, 512, 1>(P.r, smem, blk); break;
-        default: recover_generic_body<3, 256, 2>(P.r, smem, blk); break;
+        case 0: batch_recover_fp64<0, 16, 32>(P.r, smem, blk); break;
+        case 1: batch_recover_fp64<1, 64, 8>(P.r, smem, blk); break;
+        case 2: batch_recover_fp64<2, 512, 1>(P.r, smem, blk); break;
+        default: batch_recover_fp64<3, 256, 2>(P.r, smem, blk); break;
       }
       __syncthreads();
     }
@@ -107,10 +123,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_setup_batch_mixed(const Batch
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
       switch (P.k) {
-        case 0: setup_mixed_body<0, 16, 32>(P.s, smem, blk, P.sweeps); break;
-        case 1: setup_mixed_body<1, 128, 4>(P.s, smem, blk, P.sweeps); break;
-        case 2: setup_mixed_body<2, 512, 1>(P.s, smem, blk, P.sweeps); break;
-        default: setup_mixed_body<3, 512, 1>(P.s, smem, blk, P.sweeps); break;
+        case 0: batch_setup_mx<0, 16, 32>(P.s, smem, blk, P.sweeps); break;
+        case 1: batch_setup_mx<1, 128, 4>(P.s, smem, blk, P.sweeps); break;
+        case 2: batch_setup_mx<2, 512, 1>(P.s, smem, blk, P.sweeps); break;
+        default: batch_setup_mx<3, 512, 1>(P.s, smem, blk, P.sweeps); break;
       }
       __syncthreads();
     }
