@@ -126,9 +126,22 @@ __device__ __forceinline__ double m_entry(const DeviceMaps& mp, const double* qd
   return s;
 }
 
+// Lane src's value of v in every lane of the wave, for a wave-uniform src and
+// all lanes active (the value __shfl(v, src) would give): two v_readlane
+// through scalar registers instead of an LDS-routed permute.
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ float wave_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // The w x w (w <= 16) diagonal block at (c0, c0) of a packed lower triangle,
 // factored on one wave: lane l < w holds row c0 + l in registers, pivots and
-// column entries come by shuffle (no barrier).  A non-positive pivot is
+// column entries come by wave broadcast (no barrier).  A non-positive pivot is
 // replaced by 1 and reported.
 template <class T>
 __device__ __forceinline__ bool chol_diag16(T* A, int c0, int w, int l) {
@@ -140,7 +153,7 @@ __device__ __forceinline__ bool chol_diag16(T* A, int c0, int w, int l) {
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     if (c < w) {
-      T piv = __shfl(d[c], c);
+      T piv = wave_bcast(d[c], c);
       if (!(piv > T(0))) {
         bad = true;
         piv = T(1);
@@ -149,7 +162,7 @@ __device__ __forceinline__ bool chol_diag16(T* A, int c0, int w, int l) {
       d[c] = l == c ? s : (l > c ? d[c] * is : d[c]);
 #pragma unroll
       for (int j = c + 1; j < 16; ++j) {
-        const T ljc = __shfl(d[c], j);
+        const T ljc = wave_bcast(d[c], j);
         if (l >= j) d[j] -= d[c] * ljc;
       }
     }
@@ -298,7 +311,7 @@ __device__ __forceinline__ bool chol_packed(T* A, int lane) {
 // whole waves, by panels of 32 columns staged column-major in LDS
 // (P[q * LD + r] = A[c0 + r][c0 + q], LD odd for conflict-free lanes).  The
 // panel is factored in LDS as two sub-panels of 16: each one's diagonal block
-// on one wave (registers and shuffles), the rows below it one per lane, the
+// on one wave (registers and wave broadcasts), the rows below it one per lane, the
 // second sub-panel first updated by the first.  The finished panel is written
 // back, then the trailing update A_ij -= sum_q L_iq L_jq runs over chunks of
 // 64 columns: a lane keeps its column's panel entries in registers and the
@@ -345,7 +358,7 @@ __device__ __forceinline__ bool chol_hbm32(double* A, double* P, int lane, bool 
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           if (c < ws) {
-            double piv = __shfl(d[c], c);
+            double piv = wave_bcast(d[c], c);
             if (!(piv > 0.0)) {
               bad = true;
               piv = 1.0;
@@ -354,7 +367,7 @@ __device__ __forceinline__ bool chol_hbm32(double* A, double* P, int lane, bool 
             d[c] = l == c ? sq : (l > c ? d[c] * is : d[c]);
 #pragma unroll
             for (int j = c + 1; j < 16; ++j) {
-              const double ljc = __shfl(d[c], j);
+              const double ljc = wave_bcast(d[c], j);
               if (l >= j) d[j] -= d[c] * ljc;
             }
           }
@@ -413,7 +426,7 @@ __device__ __forceinline__ bool chol_hbm32(double* A, double* P, int lane, bool 
 
 // Triangular solves with the leading NI x NI block of a packed lower factor
 // L in LDS, by the team's first wave: its lanes keep the vector in registers
-// (rows lane + 64 r) and every solved entry reaches them by a shuffle, so
+// (rows lane + 64 r) and every solved entry reaches them by a wave broadcast, so
 // there is no block barrier per column.  Per entry the operations and their
 // order are those of the column-oriented loops (y_c = y_c / L_cc, then
 // y_i -= L_ic y_c).  Both end with a barrier.
@@ -431,7 +444,7 @@ __device__ __forceinline__ void wave_forward(const double* L, double* y, int lan
     for (int s = 0; s < RPL; ++s) {
       const int cend = NI < 64 * (s + 1) ? NI : 64 * (s + 1);
       for (int c = 64 * s; c < cend; ++c) {
-        const double yc = __shfl(yr[s], c - 64 * s) / L[pk(c, c)];
+        const double yc = wave_bcast(yr[s], c - 64 * s) / L[pk(c, c)];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           const int i = lane + 64 * r;
@@ -464,7 +477,7 @@ __device__ __forceinline__ void wave_backward(const double* L, double* z, int la
     for (int s = RPL - 1; s >= 0; --s) {
       const int cend = NI < 64 * (s + 1) ? NI : 64 * (s + 1);
       for (int c = cend - 1; c >= 64 * s; --c) {
-        const double uc = __shfl(zr[s], c - 64 * s) / L[pk(c, c)];
+        const double uc = wave_bcast(zr[s], c - 64 * s) / L[pk(c, c)];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           const int j = lane + 64 * r;
@@ -640,7 +653,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     } else if constexpr (!Lay::kGlobal && TEAM % 64 == 0 && nb <= 64) {
       // Inverse of the face block L_bb, its columns dealt to the waves: lane
       // l holds row l of RC columns in registers, forward substitution row by
-      // row, each solved entry broadcast by shuffle (no block barrier); per
+      // row, each solved entry broadcast to the wave (no block barrier); per
       // entry the sum runs over c = col..i-1 in order, as in the loop below.
       constexpr int NW = TEAM / 64, RC = (nb + NW - 1) / NW;
       const int wv = lane / 64, l = lane % 64;
@@ -654,7 +667,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
         for (int r = 0; r < RC; ++r) {
           if (wv + NW * r <= c) {   // uniform across the wave
             if (l == c) x[r] = x[r] / lcc;
-            const double xc = __shfl(x[r], c);
+            const double xc = wave_bcast(x[r], c);
             if (l > c) x[r] -= lic * xc;
           }
         }
