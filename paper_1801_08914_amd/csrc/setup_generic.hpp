@@ -837,13 +837,15 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
 
 // u_T = L^{-T} (y - [0; L_bb^{-1} D lambda_b]) from the stored factor; with
 // static condensation u_b = sigma x_b and u_i = L_ii^{-T} (y_i - L_bi^T u_b).
-// (k <= 2 also stage the factor's interior block for a wave-level back
-// substitution; for k = 3 it would take 83 KB of LDS per element)
+// (k <= 2 also stage the factor's interior block, for a wave-level back
+// substitution, and its face block, read by rows and by columns, with
+// coalesced copies; for k = 3 the interior block alone would take 83 KB of
+// LDS per element)
 template <int K>
 constexpr bool recover_stages() { return K <= 2; }
 template <int K>
 constexpr int recover_per() {
-  return 2 * RT<K>::n + RT<K>::nb + (recover_stages<K>() ? RT<K>::ni * (RT<K>::ni + 1) / 2 : 0);
+  return 2 * RT<K>::n + RT<K>::nb + (recover_stages<K>() ? RT<K>::ni * (RT<K>::ni + 1) / 2 + RT<K>::nbpk : 0);
 }
 
 template <int K, int TEAM, int EPB>
@@ -859,11 +861,21 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
   double* zb = yv + n;              // z_b, then u_b
   double* tl = zb + n;              // D lambda_b
   double* Lii = tl + nb;             // the factor's interior block (packed, leading)
+  double* Lfb = Lii + ni * (ni + 1) / 2;   // its face block (packed)
   const double* F = a.factor + es * R::npk;
   const DeviceMaps& mp = a.mp;
+  // entry (b, c) of the face block: LDS copy (k <= 2) or the record
+  auto FB = [&](int b, int c) { return recover_stages<K>() ? Lfb[pk(b, c)] : F[pk(ni + b, ni + c)]; };
   for (int i = lane; i < n; i += TEAM) yv[i] = a.y[es * n + i];
-  if constexpr (recover_stages<K>())
+  if constexpr (recover_stages<K>()) {
     for (int t = lane; t < ni * (ni + 1) / 2; t += TEAM) Lii[t] = F[t];
+    // face rows b: their entries c = 0..b of the face block are contiguous
+    for (int t = lane; t < R::nbpk; t += TEAM) {
+      int b, c;
+      unpk(t, b, c);
+      Lfb[t] = F[pk(ni + b, ni + c)];
+    }
+  }
   for (int b = lane; b < nb; b += TEAM) {
     const int fb = b / K2;
     const int F_ = mp.elem_face[es * 6 + fb];
@@ -889,13 +901,13 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
   if (!a.stat) {
     for (int b = lane; b < nb; b += TEAM) {
       double s = yv[ni + b];
-      for (int c = 0; c <= b; ++c) s -= F[pk(ni + b, ni + c)] * tl[c];
+      for (int c = 0; c <= b; ++c) s -= FB(b, c) * tl[c];
       zb[b] = s;
     }
     __syncthreads();
     for (int b = lane; b < nb; b += TEAM) {
       double s = 0.0;
-      for (int c = b; c < nb; ++c) s += F[pk(ni + c, ni + b)] * zb[c];
+      for (int c = b; c < nb; ++c) s += FB(c, b) * zb[c];
       tl[b] = s;  // u_b
     }
     __syncthreads();
