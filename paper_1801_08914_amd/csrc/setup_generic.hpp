@@ -697,21 +697,59 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
         Fb[t] = A[pk(ni + i, ni + j)];
       }
       __syncthreads();
-      // columns right to left: X_ij = -(sum_{c=j+1..i} X_ic L_cj) / L_jj reads
-      // the original column j and the finished columns c > j
-      for (int j = nb - 1; j >= 0; --j) {
-        const double ljj = Fb[pk(j, j)];
-        double xs[(nb + TEAM - 1) / TEAM];
-        int q = 0;
-        for (int i = j + 1 + lane; i < nb; i += TEAM, ++q) {
-          double s = 0.0;
-          for (int c = j + 1; c <= i; ++c) s += Fb[pk(i, c)] * Fb[pk(c, j)];
-          xs[q] = -s / ljj;
+      // In place, by blocks of 16 columns right to left, from
+      // X_jj = 1 / L_jj and X_ij = -(sum_{c=j+1..i} X_ic L_cj) / L_jj: a lane per
+      // row i sums the terms of the finished columns c beyond the block into
+      // registers (reading the block's original columns), then, after a
+      // barrier, finishes its row of the block from right to left with the
+      // block's diagonal part of L kept in Dg (the block's columns are being
+      // overwritten).  Three barriers per block instead of two per column.
+      static_assert(Lay::stage >= R::nbpk + 136, "the face block and a diagonal block fit in the staging area");
+      static_assert(TEAM >= nb, "a lane per row of the face block");
+      double* Dg = Fb + R::nbpk;
+      for (int j0 = ((nb - 1) / 16) * 16; j0 >= 0; j0 -= 16) {
+        const int w = nb - j0 < 16 ? nb - j0 : 16;
+        for (int t = lane; t < w * (w + 1) / 2; t += TEAM) {
+          int aa, bb;
+          unpk(t, aa, bb);
+          Dg[t] = Fb[pk(j0 + aa, j0 + bb)];
         }
-        __syncthreads();
-        q = 0;
-        for (int i = j + 1 + lane; i < nb; i += TEAM, ++q) Fb[pk(i, j)] = xs[q];
-        if (lane == 0) Fb[pk(j, j)] = 1.0 / ljj;
+        const int i = j0 + lane;
+        double pr[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) pr[jj] = 0.0;
+        if (i >= j0 + w && i < nb) {
+          for (int c = j0 + w; c <= i; ++c) {
+            const double xic = Fb[pk(i, c)];
+            const double* Lc = Fb + pk(c, j0);
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj)
+              if (jj < w) pr[jj] += xic * Lc[jj];
+          }
+        }
+        __syncthreads();   // the block's columns of L are read, Dg is complete
+        if (i < nb) {
+          double x[16];
+#pragma unroll
+          for (int jj = 15; jj >= 0; --jj) {
+            x[jj] = 0.0;
+            const int j = j0 + jj;
+            if (jj < w && j <= i) {
+              if (j == i) {
+                x[jj] = 1.0 / Dg[pk(jj, jj)];
+              } else {
+                double sacc = pr[jj];
+#pragma unroll
+                for (int cc = jj + 1; cc < 16; ++cc)
+                  if (cc < w && j0 + cc <= i) sacc += x[cc] * Dg[pk(cc, jj)];
+                x[jj] = -sacc / Dg[pk(jj, jj)];
+              }
+            }
+          }
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj)
+            if (jj < w && j0 + jj <= i) Fb[pk(i, j0 + jj)] = x[jj];
+        }
         __syncthreads();
       }
       for (int t = lane; t < R::nbpk; t += TEAM) {
