@@ -60,28 +60,31 @@ __device__ __forceinline__ void unpk_f(int t, int& i, int& j) {
 
 // W (N x NC, row-major, FP32) := (L L^T)^{-1} W with the packed FP32 factor
 // L and the reciprocals dinv of its diagonal; one barrier per column in each
-// direction.  Expects W complete on entry, ends with a barrier.
+// direction.  Expects W complete on entry, ends with a barrier.  A team with
+// active false only takes part in the barriers.
 template <int N, int TEAM, int NC>
-__device__ __forceinline__ void chol_solve32(const float* L, const float* dinv, float* W, int lane) {
+__device__ __forceinline__ void chol_solve32(const float* L, const float* dinv, float* W, int lane,
+                                             bool active = true) {
+  const int l0 = active ? lane : (1 << 30);
   for (int c = 0; c < N; ++c) {
     const float rc = dinv[c];
-    for (int t = lane; t < (N - c - 1) * NC; t += TEAM) {
+    for (int t = l0; t < (N - c - 1) * NC; t += TEAM) {
       const int i = c + 1 + t / NC, col = t % NC;
       W[i * NC + col] -= L[pk(i, c)] * (W[c * NC + col] * rc);
     }
     __syncthreads();
     // row c is not touched by later forward steps
-    for (int col = lane; col < NC; col += TEAM) W[c * NC + col] *= rc;
+    for (int col = l0; col < NC; col += TEAM) W[c * NC + col] *= rc;
   }
   __syncthreads();
   for (int c = N - 1; c >= 0; --c) {
     const float rc = dinv[c];
-    for (int t = lane; t < c * NC; t += TEAM) {
+    for (int t = l0; t < c * NC; t += TEAM) {
       const int i = t / NC, col = t % NC;
       W[i * NC + col] -= L[pk(c, i)] * (W[c * NC + col] * rc);
     }
     __syncthreads();
-    for (int col = lane; col < NC; col += TEAM) W[c * NC + col] *= rc;
+    for (int col = l0; col < NC; col += TEAM) W[c * NC + col] *= rc;
   }
   __syncthreads();
 }
@@ -151,38 +154,48 @@ __device__ __forceinline__ bool refine_solve(const float* L, const float* dinv, 
     xel(i, c) = x;
     xm = fmax(xm, fabs(x));
   }
+  // A team whose refinement has ended keeps taking part in the block's
+  // barriers (its work masked off) until every team of the block is done:
+  // the block leaves the loop together, so barriers stay paired across teams
+  // (in a persistent batch block the teams go on to other work items, whose
+  // LDS layout may differ).
+  bool done = false, result = true;
   for (int sw = 1;; ++sw) {
     double* slot = red + 4 * (sw & 1);
-    if (adaptive) {
+    if (adaptive && !done) {
       team_max(slot + 1, xm);
       team_max(slot + 2, zm);
     }
     __syncthreads();  // x complete
     double rm = 0.0;
-    for (int t = lane; t < N * NC; t += TEAM) {
+    for (int t = done ? N * NC : lane; t < N * NC; t += TEAM) {
       const int i = t / NC, c = t % NC;
       double res = bcol(i, c);
       for (int j = 0; j < N; ++j) res -= mrow(i, j) * xel(j, c);
       rm = fmax(rm, fabs(res));
       W[i * NC + c] = float(Sv[i] * res);
     }
-    if (adaptive) team_max(slot, rm);
+    if (adaptive && !done) team_max(slot, rm);
     __syncthreads();
     // every lane has read the other slot in the previous sweep
     if (lane < 4) red[4 * ((sw + 1) & 1) + lane] = 0.0;
-    if (adaptive) {
-      // slot: residual and size of the current x, the correction that made it
-      const bool backward_ok = slot[0] <= tol * slot[1];
-      if (sw >= 2 && slot[2] <= 0x1p-53 * slot[1]) return backward_ok;
-      if (sw >= 3 && slot[2] > 0.5 * zprev) return backward_ok;
-      if (sw > cap) return backward_ok;
-      zprev = slot[2];
-    } else if (sw > cap) {
-      return true;
+    if (!done) {
+      if (adaptive) {
+        // slot: residual and size of the current x, the correction that made it
+        const bool backward_ok = slot[0] <= tol * slot[1];
+        if ((sw >= 2 && slot[2] <= 0x1p-53 * slot[1]) || (sw >= 3 && slot[2] > 0.5 * zprev) || sw > cap) {
+          done = true;
+          result = backward_ok;
+        }
+        zprev = slot[2];
+      } else if (sw > cap) {
+        done = true;
+      }
     }
-    chol_solve32<N, TEAM, NC>(L, dinv, W, lane);
+    if (!__syncthreads_or(done ? 0 : 1)) return result;
+    chol_solve32<N, TEAM, NC>(L, dinv, W, lane, !done);
     xm = zm = 0.0;
-    for (int t = lane; t < N * NC; t += TEAM) {
+    for (int t = done ? N * NC : lane; t < N * NC; t += TEAM) {
       const int i = t / NC, c = t % NC;
       const double z = Sv[i] * double(W[i * NC + c]);
       const double x = xel(i, c) + z;

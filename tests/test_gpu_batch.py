@@ -191,3 +191,30 @@ def test_batch_mixed_and_fp64_plans_together():
         er = norm_rel(ref.r, singles[i][1].numpy())
         print(f"  mixed problem {i} k={p.k}: H {eH:.1e} r {er:.1e} vs the FP64 oracle", flush=True)
         assert max(eH, er) <= 1e-10
+
+
+def test_batch_mixed_results_do_not_depend_on_tiles():
+    """All-mixed batch of every order: the refinement ends at different
+    sweeps in different teams of a block, and persistent blocks go on from
+    one order's items to another's (another LDS layout); H and r are the same
+    bits whatever the grid and items per block."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Batch, Plan
+    probs = synth.config_c4(nprob=10, nmin=3, nmax=6, seed=49)
+    assert sorted(set(p.k for p in probs)) == [0, 1, 2, 3]
+    outs = []
+    for tiles in ((1, 1), (8, 1), (2, 4)):
+        plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True, precision="mixed").bind() for p in probs]
+        b = Batch(plans)
+        for i, p in enumerate(probs):
+            b.set(i, p.alpha, p.beta, p.f)
+        b.tiles(*tiles)
+        b.setup()
+        torch.cuda.synchronize()
+        outs.append([(pl.csr()[2].cpu(), pl.r().cpu(), pl.status()[0]) for pl in plans])
+        print(f"  tiles {tiles}: statuses {[o[2] for o in outs[-1]]}", flush=True)
+    for o in outs[1:]:
+        for i in range(len(probs)):
+            assert o[i][2] == outs[0][i][2], i
+            assert torch.equal(o[i][0], outs[0][i][0]), i
+            assert torch.equal(o[i][1], outs[0][i][1]), i
