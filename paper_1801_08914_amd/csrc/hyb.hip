@@ -847,7 +847,11 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
   b->probs.resize(size_t(count));
   for (int32_t i = 0; i < count; ++i) {
     hyb::Plan& P = plans[i]->P;
-    // the batch kernels use the generic element routines and record layout
+    // the batch kernels use the generic element routines and record layout;
+    // factors and y left by the affine RT_1 kernels are in that kernel's own
+    // layout, so a plan switched here must be set up again (by the batch or
+    // hyb_setup) before hyb_rhs or hyb_recover
+    if (P.fast_k1) P.have_setup = P.have_rhs = false;
     P.fast_k1 = false;
     hyb::BatchProb& pr = b->probs[size_t(i)];
     pr = hyb::BatchProb{};

@@ -84,7 +84,38 @@ def ld_dense(Hld: dict, rld: dict, m: int):
     return H, r
 
 
-def accuracy_bound(e_oracle: float) -> float:
+U64 = 2.0 ** -53
+
+
+def kappa_of(k, mesh, alpha, beta, topo, elements=None, ess=None):
+    """kappa_s = max cond_2 of the equilibrated kept element blocks over the
+    given elements (all by default), from the oracle (``extended.kappa_scaled``)."""
+    from oracle import extended as oext
+    els = np.arange(mesh.ne) if elements is None else np.asarray(elements)
+    return oext.kappa_scaled(k, mesh.xyz, mesh.e2v, alpha, beta, topo, els, ess)
+
+
+def accuracy_bound(e_oracle: float, kappa: float) -> float:
     """The GPU must be at least as accurate as the FP64 oracle (factor 2 for
-    rounding-order luck), and never needs to beat 1e-12."""
+    rounding-order luck) against the long-double reference, and never needs
+    to beat 1e-12.  The oracle's own error is capped first: more than
+    10 kappa_s 2^-53 from the long-double reference means that one of the two
+    references is wrong, and the bound is refused rather than loosened."""
+    cap = 10.0 * kappa * U64
+    assert e_oracle <= cap, f"FP64 oracle {e_oracle:.2e} off the long-double reference, above 10 kappa_s u = {cap:.2e}"
     return max(1e-12, 2.0 * e_oracle)
+
+
+def oracle_gap_bound(kappa: float) -> float:
+    """Largest admissible distance between the GPU and the FP64 oracle
+    directly: both within 10 kappa_s 2^-53 of the exact values."""
+    return 20.0 * kappa * U64
+
+
+def mixed_bound(e_oracle: float, kappa: float) -> float:
+    """The mixed-precision form refined: within max(1e-10, 2 x the FP64
+    oracle's own error) of the long-double reference (the oracle's error
+    capped as in ``accuracy_bound``)."""
+    cap = 10.0 * kappa * U64
+    assert e_oracle <= cap, f"FP64 oracle {e_oracle:.2e} off the long-double reference, above 10 kappa_s u = {cap:.2e}"
+    return max(1e-10, 2.0 * e_oracle)

@@ -10,7 +10,7 @@ import scipy.sparse as sp
 import synth
 from oracle import extended as oext
 from oracle import weighted as ow
-from tests.gpu_common import accuracy_bound, ld_dense, norm_rel, rel_inf, require_gpu
+from tests.gpu_common import accuracy_bound, kappa_of, ld_dense, norm_rel, oracle_gap_bound, rel_inf, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -52,13 +52,15 @@ def test_weighted_H_r_and_invariant_solution(k, N, jit, rot):
         Hg = sp.csr_matrix((val, ci, rp), shape=Hw.shape).toarray()
         nH, nHo = norm_rel(Hl, Hg), norm_rel(Hl, Hw.toarray())
         nr, nro = norm_rel(rl, rg), norm_rel(rl, rw)
-        print(f"k={k}: weighted vs long double, GPU / oracle: H {nH:.1e} / {nHo:.1e}, r {nr:.1e} / {nro:.1e}",
-              flush=True)
-        assert nH <= accuracy_bound(nHo) and nr <= accuracy_bound(nro)
+        kap = kappa_of(k, mesh, a, b, hy.topo)
+        print(f"k={k}: weighted vs long double, GPU / oracle: H {nH:.1e} / {nHo:.1e}, r {nr:.1e} / {nro:.1e}; "
+              f"kappa_s {kap:.1e}", flush=True)
+        assert nH <= accuracy_bound(nHo, kap) and nr <= accuracy_bound(nro, kap)
     else:
+        kap = kappa_of(k, mesh, a, b, hy.topo)
         e = norm_rel(Hw.data, val)
-        print(f"k={k}: weighted H, GPU vs oracle {e:.1e}", flush=True)
-        assert e <= 1e-10
+        print(f"k={k}: weighted H, GPU vs oracle {e:.1e}; kappa_s {kap:.1e}", flush=True)
+        assert e <= oracle_gap_bound(kap)
     lw, iw = pw.solve(1e-13, 5000)
     uw = pw.recover(lw).cpu().numpy()
     p0 = _plan(torch, mesh, k, a, b, f, False)

@@ -21,7 +21,7 @@ import synth
 from oracle import element as oelem
 from oracle import extended as oext
 from oracle import hybrid as ohyb
-from tests.gpu_common import accuracy_bound, gpu_setup, ld_dense, norm_rel, rel_inf, require_gpu
+from tests.gpu_common import accuracy_bound, gpu_setup, kappa_of, ld_dense, norm_rel, rel_inf, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -67,11 +67,15 @@ def test_workload_matches_oracle(kind, k, p, dims):
         nH, nHo = norm_rel(Hl, Hg), norm_rel(Hl, ref.H.toarray())
         nr, nro = norm_rel(rl, rg), norm_rel(rl, ref.r)
         kap = _kappa_max(prob, ref)
+        kap_s = kappa_of(k, mesh, prob.alpha, prob.beta, ref.topo)
         nb = 6 * (k + 1) ** 2
+        # the long-double reference itself is only ~kappa 2^-64 accurate: where
+        # kappa(M_T) is near 2^53 (contrast 1e16) no FP64 path can do better
+        # than the element conditioning floor
         floor = 10 * nb * kap * 2.0**-53
         print(f"  vs long double, GPU / FP64 oracle: H {nH:.1e} / {nHo:.1e}, r {nr:.1e} / {nro:.1e}; "
-              f"kappa_max(M_T) {kap:.1e}, bound {floor:.1e}", flush=True)
-        assert nH <= max(accuracy_bound(nHo), floor) and nr <= max(accuracy_bound(nro), floor)
+              f"kappa_max(M_T) {kap:.1e}, kappa_s {kap_s:.1e}, bound {floor:.1e}", flush=True)
+        assert nH <= max(accuracy_bound(nHo, kap_s), floor) and nr <= max(accuracy_bound(nro, kap_s), floor)
     else:
         floor = 0.0
         e = norm_rel(ref.H.data, val)
@@ -84,13 +88,14 @@ def test_workload_matches_oracle(kind, k, p, dims):
     uref = ohyb.recover(ref, mesh.xyz, mesh.e2v, prob.alpha, prob.beta, prob.f, lref)
     eu = norm_rel(uref, u)
     # perturbation bound: H and r of the two FP64 paths differ by dH, dr
-    # (relative), so their solutions by up to kappa(H) (dH + dr); the
-    # recovery adds the element conditioning floor
+    # (relative), the PCG stops at a residual reduction of 1e-12, so the
+    # solutions differ by up to kappa(H) (dH + dr + 1e-12); the recovery adds
+    # the element conditioning floor
     Hd = ref.H.toarray()
     kH = np.linalg.cond(Hd)
     dH = norm_rel(Hd, sp.csr_matrix((val, ci, rp), shape=ref.H.shape).toarray())
     dr = norm_rel(ref.r, rg)
-    bound = max(1e-6, 4.0 * kH * (dH + dr) + 2.0 * floor)
+    bound = 4.0 * kH * (dH + dr + 1e-12) + 2.0 * floor
     print(f"  solve: {info['iters']} Jacobi-PCG iterations, u vs oracle direct {eu:.1e} (normwise); "
           f"kappa(H) {kH:.1e}, bound {bound:.1e}", flush=True)
     assert eu <= bound

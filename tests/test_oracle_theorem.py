@@ -1,7 +1,5 @@
 """Pins for the oracle's hybridization against Theorem 2.1 and the structure
 of P, C and H (no GPU)."""
-from fractions import Fraction
-
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -80,63 +78,15 @@ def test_local_equilibrium_and_constraint(k, N, jit):
     assert np.abs(C @ xhat).max() <= 1e-11 * np.abs(xhat).max()
 
 
-def _exact_solve(A, B):
-    """Fraction Gauss-Jordan: A^{-1} B."""
-    n = len(A)
-    M = [list(A[i]) + list(B[i]) for i in range(n)]
-    for c in range(n):
-        p = next(r for r in range(c, n) if M[r][c] != 0)
-        M[c], M[p] = M[p], M[c]
-        inv = 1 / M[c][c]
-        M[c] = [x * inv for x in M[c]]
-        for r in range(n):
-            if r != c and M[r][c] != 0:
-                fac = M[r][c]
-                M[r] = [x - fac * y for x, y in zip(M[r], M[c])]
-    return [row[n:] for row in M]
-
-
 def test_c1_exact_rational():
-    """The whole RT0 4^3 reduced system in exact rational arithmetic.
-
-    Closed-form M_T and f_T of the unit-side-h cube (h = 1/4, alpha = beta = 1),
-    the structured-grid face numbering written out independently (the face
-    between e and its +d neighbour is owned by e as its local face 2d+1),
-    exact elimination of boundary faces and exact local inverses."""
+    """The whole RT0 4^3 reduced system in exact rational arithmetic
+    (``tests/exact_rt.c1_exact``: closed-form M_T and f_T of the cube of side
+    h = 1/4, alpha = beta = 1, the structured-grid face numbering written out
+    independently, exact elimination of boundary faces and exact local
+    inverses) against the FP64 oracle."""
+    from tests.exact_rt import c1_exact
     prob = synth.config_c1()
-    N, h = 4, Fraction(1, 4)
-    blk = [[Fraction(1, 3), Fraction(1, 6)], [Fraction(1, 6), Fraction(1, 3)]]
-    d = [-1, 1, -1, 1, -1, 1]
-    M = [[(blk[i % 2][j % 2] / h if i // 2 == j // 2 else Fraction(0)) + d[i] * d[j] / h ** 3
-          for j in range(6)] for i in range(6)]
-    strides = [1, N, N * N]
-    owned = []
-    for e in range(N ** 3):
-        ijk = [e % N, (e // N) % N, e // (N * N)]
-        for dd in range(3):
-            if ijk[dd] + 1 < N:
-                owned.append((e, 2 * dd + 1))
-    owned.sort()
-    fid = {}
-    for i, (e, lf) in enumerate(owned):
-        dd = lf // 2
-        fid[(e, lf)] = i
-        fid[(e + strides[dd], lf - 1)] = i
-    m = len(owned)
-    Hx = {}
-    rx = [Fraction(0)] * m
-    for e in range(N ** 3):
-        fe = [Fraction(float(x)) for x in prob.f[e]]
-        fhat = [h / 2 * fe[i // 2] for i in range(6)]
-        kept = [lf for lf in range(6) if (e, lf) in fid]
-        Mrr = [[M[i][j] for j in kept] for i in kept]
-        rhs = [[Fraction(int(i == j)) * d[i] for j in kept] + [fhat[i]] for i in kept]
-        X = _exact_solve(Mrr, rhs)
-        for a, la in enumerate(kept):
-            for b, lb in enumerate(kept):
-                key = (fid[(e, la)], fid[(e, lb)])
-                Hx[key] = Hx.get(key, Fraction(0)) + d[la] * X[a][b]
-            rx[fid[(e, la)]] += d[la] * X[a][len(kept)]
+    Hx, rx, m = c1_exact(prob)
     hyb = hybrid.hybridize(0, prob.mesh.xyz, prob.mesh.e2v, prob.alpha, prob.beta, prob.f)
     H = hyb.H.toarray()
     assert hyb.H.nnz == len(Hx) == 1200 and m == 144
