@@ -5,7 +5,8 @@ M_T and f_T, Cholesky, H_T and its scatter into CSR H, r (setup), then the
 element-by-element recovery of u from lambda.  The Jacobi-PCG that produces
 lambda runs once before the timed region and is reported separately.
 
-Prints one JSON line (see the design doc for the roofline accounting).
+Prints one JSON line: the value, a roofline object for the dominant kernel
+and the oracle timed on the host cores as a reported baseline.
 """
 from __future__ import annotations
 
@@ -49,16 +50,47 @@ def per_element_counts(k: int, ne: int, nnz: int, m: int, nv: int):
     return dict(setup_bytes=setup_bytes, setup_flops=setup_flops, recover_bytes=rec_bytes, recover_flops=rec_flops)
 
 
+def algo_counts(k: int):
+    """Algorithmic count per element of order k, the work the method itself
+    must do (the dense weighted Gram assembly 2 n^2 Q, the Cholesky n^3/3,
+    the inverse of the face block 2 nb^3/3) and the bytes of the recovery
+    (the generic factor record read, y, the element's multipliers, u
+    written)."""
+    K2 = (k + 1) ** 2
+    n, nb, Q = 3 * K2 * (k + 2), 6 * K2, (k + 2) ** 3
+    flops = 2 * n * n * Q + n ** 3 / 3 + 2 * nb ** 3 / 3
+    rec_bytes = 8 * (n * (n + 1) // 2 + 2 * n + nb) + 6 * 4 + 8
+    return dict(setup_flops=flops, recover_bytes=rec_bytes)
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host (for cpu_baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
 def _sum_or_none(*xs):
     return None if any(x is None for x in xs) else float(sum(xs))
 
 
-def traffic_from_profile(kernel: str, ne: int):
+def traffic_from_profile(kernel: str, ne: int, fname: str = "hbm_traffic_rt1_32cubed.json"):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain device copy), or None
     when the summary is missing or the kernel sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_rt1_32cubed.json")
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -101,6 +133,93 @@ def cpu_baseline(prob, target_s: float = 12.0):
     return {"value": S / t, "unit": "elements/s", "cores": 1, "kind": "oracle",
             "sample": f"first {S} of {prob.mesh.ne} elements of the same workload, setup incl. rhs + recovery, "
                       f"{t:.1f} s, 1 thread (BLAS limited to 1)"}
+
+
+_MIX = []   # (problem, topology, multiplier ids) of the CPU baseline, inherited by forked workers
+
+
+def _oracle_chunk(args):
+    """Worker: _oracle_task on problem i of _MIX, elements [e0, e1)."""
+    i, e0, e1 = args
+    p, topo, mid = _MIX[i]
+    return _oracle_task((p.k, p.mesh.xyz, p.mesh.e2v, p.alpha, p.beta, p.f, topo, mid, e0, e1, i))
+
+
+def _oracle_task(args):
+    """One oracle run: setup with rhs + recovery of the elements [e0, e1) of
+    one problem; returns (elements, seconds)."""
+    k, xyz, e2v, alpha, beta, f, topo, mid, e0, e1, seed = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hybrid as ohyb
+    with threadpool_limits(1):
+        lam = np.random.default_rng(seed).standard_normal(topo.nfaces * (k + 1) ** 2)
+        els = np.arange(e0, e1)
+        t0 = time.perf_counter()
+        hyb = ohyb.hybridize(k, xyz, e2v, alpha, beta, f, topo=topo, elements=els, mult_id=mid)
+        ohyb.recover(hyb, xyz, e2v, alpha, beta, f, lam, elements=els)
+        return e1 - e0, time.perf_counter() - t0
+
+
+def cpu_baseline_mix(probs, target_s: float = 12.0, label: str = "the same workload"):
+    """The oracle as it stands on a bounded sample of a multi-problem
+    workload: the same fraction of every problem's elements (so the order
+    mix is the workload's), setup with rhs + recovery, single-threaded BLAS
+    per process; once in one process and once over min(usable CPUs, 16)
+    processes.  Run before the GPU is initialised: the workers are forked
+    and inherit the inputs."""
+    import multiprocessing as mp
+
+    from oracle import topology as otopo
+    model, ncpu, usable = host_cpu()
+    # topology and multiplier numbering once per problem (host planning, not timed)
+    topos = []
+    for p in probs:
+        topo = otopo.build_topology(p.mesh.e2v)
+        topos.append((topo, otopo.multiplier_map(topo, p.k)[0]))
+    # per-order oracle cost from a small probe in this process
+    per_k = {}
+    for p, (topo, mid) in zip(probs, topos):
+        if p.k not in per_k:
+            s = min(4, p.mesh.ne)
+            _, t = _oracle_task((p.k, p.mesh.xyz, p.mesh.e2v, p.alpha, p.beta, p.f, topo, mid, 0, s, 0))
+            per_k[p.k] = t / s
+    est = sum(per_k[p.k] * p.mesh.ne for p in probs)
+    frac = min(1.0, target_s / max(est, 1e-9))
+    tasks = []
+    for i, (p, (topo, mid)) in enumerate(zip(probs, topos)):
+        s = max(1, int(round(frac * p.mesh.ne)))
+        tasks.append((p.k, p.mesh.xyz, p.mesh.e2v, p.alpha, p.beta, p.f, topo, mid, 0, s, i))
+    out = {"unit": "elements/s", "kind": "oracle", "cpu_model": model, "logical_cpus": ncpu,
+           "usable_cpus": usable}
+    res = [_oracle_task(t) for t in tasks]
+    nel, t1 = sum(r[0] for r in res), sum(r[1] for r in res)
+    out["value"] = nel / t1
+    out["cores"] = 1
+    out["sample"] = (f"{frac:.3%} of every problem's elements ({nel} of {sum(p.mesh.ne for p in probs)}) of "
+                     f"{label}, setup incl. rhs + recovery (topology not timed), {t1:.1f} s, 1 process, "
+                     f"BLAS limited to 1 thread")
+    procs = max(1, min(usable, 16))
+    # every problem's sample in chunks of about equal cost, largest first
+    chunks = []
+    for i, t in enumerate(tasks):
+        k, e0, e1 = t[0], t[8], t[9]
+        step = 1 if k == 3 else max(1, (e1 - e0 + 3) // 4)
+        for c0 in range(e0, e1, step):
+            chunks.append((per_k[k] * (min(e1, c0 + step) - c0), (i, c0, min(e1, c0 + step))))
+    chunks = [c for _, c in sorted(chunks, key=lambda x: -x[0])]
+    _MIX[:] = [(p, topo, mid) for p, (topo, mid) in zip(probs, topos)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(processes=procs) as pool:
+        pool.map(_oracle_chunk, [(0, 0, 1)] * procs)    # warm the workers
+        t0 = time.perf_counter()
+        resp = pool.map(_oracle_chunk, chunks, chunksize=1)
+        tp = time.perf_counter() - t0
+    _MIX.clear()
+    out["multi_process"] = {"value": sum(r[0] for r in resp) / tp, "cores": procs, "seconds": tp,
+                            "sample": "the same sample in chunks over a process pool (forked workers, "
+                                      "1 BLAS thread each); wall time of the pool"}
+    return out
 
 
 def parity_sample(prob, plan, lam_np, nface=48, nel=48, seed=0):
@@ -202,7 +321,7 @@ def static_leg(args, prob, plain_value, u_hyb):
     plan = Plan(prob.mesh.xyz, prob.mesh.e2v, prob.k, system="static").bind("cuda:0")
     plan.setup(alpha, beta, f)
     t0 = time.perf_counter()
-    x, info = plan.solve(1e-12, 20000)
+    x, info = plan.pcg(1e-12, 20000)
     torch.cuda.synchronize()
     pcg_ms = (time.perf_counter() - t0) * 1e3
     u = torch.empty((prob.mesh.ne, plan.n), dtype=torch.float64, device=dev)
@@ -218,92 +337,149 @@ def static_leg(args, prob, plain_value, u_hyb):
     return out
 
 
-def run_c4(args):
-    """The uneven batch (64 jittered problems, n in 8..24, k in 0..3): setup +
-    recovery of every problem in one persistent launch each, tiles from the
-    library's autotuner, replayed as hipGraphs.  Recovery uses a seeded random
-    lambda (its cost does not depend on the values)."""
+def _batch_run_timed(b, steps, warmup):
+    """Warm-up, then `steps` timed setup + recovery passes of a batch (graph
+    replays), with HIP-event times of the two phases."""
     import torch
-
-    import synth
-    from paper_1801_08914_amd import Batch, Plan
-    probs = synth.config_c4()
-    t0 = time.perf_counter()
-    plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True).bind("cuda:0") for p in probs]
-    plan_s = time.perf_counter() - t0
-    b = Batch(plans)
-    rng = np.random.default_rng(0)
-    for i, (p, pl) in enumerate(zip(probs, plans)):
-        b.set(i, p.alpha, p.beta, p.f, lam=rng.standard_normal(max(pl.m, 1)))
-    ne = sum(p.mesh.ne for p in probs)
-    tiles = b.autotune(reps=1)
-    b.graph(True)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         b.setup()
         b.recover()
     torch.cuda.synchronize()
+    b.timing(True)
     ts = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         t1 = time.perf_counter()
         b.setup()
         b.recover()
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t1)
+    kt = b.timing_read()
+    b.timing(False)
+    return np.array(ts), kt["setup_ms"] / max(kt["setup_n"], 1), kt["recover_ms"] / max(kt["recover_n"], 1)
+
+
+def _c4_parity(probs, plans, lams, picks):
+    """Worst sampled error of the batch's H rows, r and u against the oracle
+    over the picked problems (one of each order)."""
+    worst = {"H_row_rel": 0.0, "r_rel_to_max": 0.0, "u_rel": 0.0}
+    per = {}
+    for i in picks:
+        e = parity_sample(probs[i], plans[i], lams[i], nface=16, nel=16)
+        per[probs[i].name] = {key: e[key] for key in worst}
+        for key in worst:
+            worst[key] = max(worst[key], e[key])
+    worst["problems"] = per
+    return worst
+
+
+def run_c4(args):
+    """The uneven batch (64 jittered problems, n in 8..24, k in 0..3): setup +
+    recovery of every problem in one persistent launch per phase, tiles from
+    the library's autotuner, replayed as hipGraphs; the FP64 plain form is
+    the line's value, the mixed-precision form a leg beside it.  Recovery
+    uses a seeded random lambda (its cost does not depend on the values)."""
+    import synth
+    probs = synth.config_c4()
+    ne = sum(p.mesh.ne for p in probs)
+    by_k = {k: sum(p.mesh.ne for p in probs if p.k == k) for k in range(4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_mix(probs, label="the uneven 64-problem batch")
+        print(f"cpu baseline: {cpu['value']:.0f} el/s (1 process), "
+              f"{cpu['multi_process']['value']:.0f} el/s ({cpu['multi_process']['cores']} processes)",
+              file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_1801_08914_amd import Batch, Plan
+    t0 = time.perf_counter()
+    plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True).bind("cuda:0") for p in probs]
+    plan_s = time.perf_counter() - t0
+    b = Batch(plans)
+    rng = np.random.default_rng(0)
+    lams = [rng.standard_normal(max(pl.m, 1)) for pl in plans]
+    for i, p in enumerate(probs):
+        b.set(i, p.alpha, p.beta, p.f, lam=lams[i])
+    tiles = b.autotune(reps=1)
+    b.graph(True)
+    ts, setup_ms, rec_ms = _batch_run_timed(b, args.steps, args.warmup)
     for i, pl in enumerate(plans):
         rc, det = pl.status()
         assert rc == 0, (i, rc, det)
-    ts = np.array(ts)
-    by_k = {k: sum(p.mesh.ne for p in probs if p.k == k) for k in range(4)}
-    mixed = None if args.no_mixed else c4_mixed_leg(args, probs, tiles, ne, ne * len(ts) / ts.sum())
-    out = {"metric": METRIC, "value": ne * len(ts) / ts.sum(), "unit": "elements/s", "n_gpus": 1,
+    value = ne * len(ts) / ts.sum()
+    print(f"c4 fp64: {value:.0f} el/s, setup phase {setup_ms:.2f} ms, recovery phase {rec_ms:.2f} ms",
+          file=sys.stderr, flush=True)
+    flops = sum(algo_counts(p.k)["setup_flops"] * p.mesh.ne for p in probs)
+    rbytes = sum(algo_counts(p.k)["recover_bytes"] * p.mesh.ne for p in probs)
+    roof = {"bound": "mfma", "kernel": "k_setup_batch (setup phase: k_batch_zero + k_setup_batch)",
+            "achieved": flops / (setup_ms * 1e-3) / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": flops / (setup_ms * 1e-3) / FP64_PEAK,
+            "traffic": traffic_from_profile("k_setup_batch", ne, "hbm_traffic_uneven_batch_64.json"),
+            "phase_ms": setup_ms, "algorithmic_flops": flops,
+            "flops_per_element_by_order": {k: algo_counts(k)["setup_flops"] for k in range(4)},
+            "recover_phase_ms": rec_ms, "recover_hbm_gbs": rbytes / (rec_ms * 1e-3) / 1e9,
+            "recover_hbm_frac": rbytes / (rec_ms * 1e-3) / HBM_PEAK,
+            "recover_traffic": traffic_from_profile("k_recover_batch", ne, "hbm_traffic_uneven_batch_64.json")}
+    picks = [next(i for i, p in enumerate(probs) if p.k == k) for k in range(4) if any(p.k == k for p in probs)]
+    parity = None if args.no_parity else _c4_parity(probs, plans, lams, picks)
+    del b, plans
+    torch.cuda.empty_cache()
+    mixed = None if args.no_mixed else c4_mixed_leg(args, probs, tiles, ne, value, lams, picks)
+    out = {"metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * ts.mean(), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "uneven batch: 64 jittered n^3 problems, n~U{8..24}, k~U{0..3}, seed 4",
+           "config": {"workload": "uneven batch: 64 jittered n^3 problems, n~U{8..24}, k~U{0..3}, alpha and beta "
+                                  "lognormal per problem, seed 4",
                       "elements": ne, "elements_by_order": by_k, "problems": len(probs),
                       "precision": "fp64-plain", "launch": "one persistent launch per phase, hipGraph replay",
                       "autotuned_tiles": {"blocks_per_cu": tiles[0], "items_per_block": tiles[1]}},
            "step_ms_p50": 1e3 * float(np.median(ts)), "step_ms_p90": 1e3 * float(np.percentile(ts, 90)),
-           "host_planning_s": plan_s, "mixed": mixed}
-    print(json.dumps(out), flush=True)
+           "host_planning_s": plan_s, "roofline": roof}
+    if parity is not None:
+        out["error_vs_oracle"] = parity
+    out["mixed"] = mixed
+    if cpu is not None:
+        cpu["gpu_over_cpu"] = value / cpu["value"]
+        out["cpu_baseline"] = cpu
+    return out
 
 
-def c4_mixed_leg(args, probs, tiles, ne, plain_value):
+def c4_mixed_leg(args, probs, tiles, ne, plain_value, lams, picks):
     """The same uneven batch with every problem in the mixed-precision form
-    (FP32 element factors, adaptive FP64 refinement): one persistent launch
-    per phase over the mixed problems' work items, the FP64 form's tiles
-    (the mixed setup is too slow to sweep tiles for), hipGraph replay; one
-    untimed pass and min(steps, 2) timed ones.  Problems whose refinement
-    failed its backward-error test are counted, not hidden."""
+    (FP32 element factors and solves, FP64 refinement), refined (adaptive
+    sweeps with the backward-error test) and unrefined: one persistent
+    launch per phase over the mixed problems' items, the FP64 form's tiles,
+    hipGraph replay.  Problems with an element that needed the FP64 fallback
+    are counted (the result is still within the bound), failures too."""
     import torch
 
     from paper_1801_08914_amd import Batch, Plan
-    plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True, precision="mixed").bind("cuda:0") for p in probs]
-    b = Batch(plans)
-    rng = np.random.default_rng(0)
-    for i, (p, pl) in enumerate(zip(probs, plans)):
-        b.set(i, p.alpha, p.beta, p.f, lam=rng.standard_normal(max(pl.m, 1)))
-    b.tiles(*tiles)
-    b.graph(True)
-    steps = max(1, min(args.steps, 2))
-    ts = []
-    for it in range(steps + 1):
-        t1 = time.perf_counter()
-        b.setup()
-        b.recover()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        print(f"c4 mixed pass {it}: {dt:.2f} s", file=sys.stderr, flush=True)
-        if it:
-            ts.append(dt)
-    refine_failed = [i for i, pl in enumerate(plans) if pl.status()[0] != 0]
-    ts = np.array(ts)
-    out = {"value": ne * len(ts) / ts.sum(), "unit": "elements/s", "ms_per_step": 1e3 * ts.mean(), "steps": len(ts),
-           "vs_fp64_plain": ne * len(ts) / ts.sum() / plain_value,
-           "sweeps": "adaptive (backward-error test, at most 30)",
-           "problems_refinement_failed": len(refine_failed),
-           "tiles": {"blocks_per_cu": tiles[0], "items_per_block": tiles[1]}}
-    del b, plans
-    torch.cuda.empty_cache()
+    out = {}
+    for name, sweeps in (("refined", None), ("unrefined", 0)):
+        plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True, precision="mixed", sweeps=sweeps).bind("cuda:0")
+                 for p in probs]
+        b = Batch(plans)
+        for i, p in enumerate(probs):
+            b.set(i, p.alpha, p.beta, p.f, lam=lams[i])
+        b.tiles(*tiles)
+        b.graph(True)
+        steps = max(1, min(args.steps, 5))
+        ts, setup_ms, rec_ms = _batch_run_timed(b, steps, 1)
+        failed = [i for i, pl in enumerate(plans) if pl.status()[0] != 0]
+        val = ne * len(ts) / ts.sum()
+        leg = {"value": val, "unit": "elements/s", "ms_per_step": 1e3 * ts.mean(), "steps": len(ts),
+               "vs_fp64_plain": val / plain_value, "setup_phase_ms": setup_ms, "recover_phase_ms": rec_ms,
+               "sweeps": "adaptive (backward-error test, at most 30)" if sweeps is None else sweeps,
+               "problems_failed": len(failed), "tiles": {"blocks_per_cu": tiles[0], "items_per_block": tiles[1]}}
+        if hasattr(plans[0], "fallback_count"):
+            leg["elements_fp64_fallback"] = int(sum(pl.fallback_count() for pl in plans))
+        if not args.no_parity and not failed:
+            leg["error_vs_oracle"] = _c4_parity(probs, plans, lams, picks)
+        print(f"c4 mixed {name}: {val:.0f} el/s, setup phase {setup_ms:.1f} ms, failed problems {len(failed)}",
+              file=sys.stderr, flush=True)
+        out[name] = leg
+        del b, plans
+        torch.cuda.empty_cache()
     return out
 
 
@@ -320,7 +496,7 @@ def run_single(args, prob, label):
     alpha, beta, f = (torch.as_tensor(x, device=dev) for x in (prob.alpha, prob.beta, prob.f))
     u = torch.empty((ne, plan.n), dtype=torch.float64, device=dev)
     plan.setup(alpha, beta, f)
-    lam, info = plan.solve(1e-12, 20000)
+    lam, info = plan.pcg(1e-12, 20000)
     for _ in range(args.warmup):
         plan.setup(alpha, beta, f)
         plan.recover(lam, u)
@@ -358,7 +534,13 @@ def run_single(args, prob, label):
         out["mixed"] = mixed
     if stat is not None:
         out["static_condensation"] = stat
-    print(json.dumps(out), flush=True)
+    t_set = out["setup_kernel_ms"] * 1e-3
+    if t_set > 0:
+        fl = algo_counts(prob.k)["setup_flops"] * ne
+        out["roofline"] = {"bound": "mfma", "kernel": f"k_setup_generic<{prob.k}> (+ zeroing of the same-face blocks)",
+                           "achieved": fl / t_set / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                           "frac": fl / t_set / FP64_PEAK, "traffic": None}
+    return out
 
 
 def solve_phases(prob, steps=3):
@@ -375,7 +557,7 @@ def solve_phases(prob, steps=3):
     plan.setup(alpha, beta, f)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lam, info = plan.solve(1e-12, 200000)
+    lam, info = plan.pcg(1e-12, 200000)
     torch.cuda.synchronize()
     pcg_s = time.perf_counter() - t0
     u = torch.empty((prob.mesh.ne, plan.n), dtype=torch.float64, device=dev)
@@ -480,10 +662,11 @@ def main():
                     help="recover from a seeded random lambda instead of the PCG solution (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "softhard", "spe10"],
-                    help="c2: the RT1 32^3 workload (default line); c1: RT0 4^3 latency; c3: RT2 48^3 jittered; "
-                         "c4: the uneven 64-problem batch; c5: the serving stream; softhard: the soft-hard "
-                         "materials study; spe10: the SPE10-shaped stand-in")
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "softhard", "spe10"],
+                    help="c4: the uneven 64-problem batch (default line, with C2 and C3 legs); c1: RT0 4^3 "
+                         "latency; c2: RT1 32^3; c3: RT2 48^3 jittered; c5: the serving stream; softhard: the "
+                         "soft-hard materials study; spe10: the SPE10-shaped stand-in")
+    ap.add_argument("--no-legs", action="store_true", help="c4: skip the C2 and C3 legs")
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the stream")
     ap.add_argument("--nmin", type=int, default=8, help="c5: smallest mesh edge")
     ap.add_argument("--nmax", type=int, default=16, help="c5: largest mesh edge")
@@ -492,11 +675,30 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design in DESIGN.md)"}))
+                                   "(the sharding of the path across GPUs is a design only)"}))
         sys.exit(2)
 
     if args.config == "c4":
-        run_c4(args)
+        out = run_c4(args)
+        if not args.no_legs:
+            import copy
+
+            import synth
+            leg_args = copy.copy(args)
+            leg_args.steps, leg_args.warmup, leg_args.no_static = min(args.steps, 10), 2, True
+            leg_args.no_cpu_baseline = True
+            legs = {}
+            for name, fn in (("c2", lambda: run_c2(leg_args)),
+                             ("c3", lambda: run_single(leg_args, synth.config_c3(), C3_LABEL))):
+                t0 = time.perf_counter()
+                r = fn()
+                for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data", "unit"):
+                    r.pop(key, None)
+                r["wall_s"] = time.perf_counter() - t0
+                legs[name] = r
+                print(f"leg {name}: {r['value']:.0f} el/s", file=sys.stderr, flush=True)
+            out["legs"] = legs
+        print(json.dumps(out), flush=True)
         return
     if args.config == "softhard":
         run_softhard(args)
@@ -510,12 +712,19 @@ def main():
     if args.config in ("c1", "c3"):
         import synth
         if args.config == "c1":
-            run_single(args, synth.config_c1(), "rt0_4x4x4 RT0 unit cube 4^3, alpha = beta = 1, seed 1")
+            out = run_single(args, synth.config_c1(), "rt0_4x4x4 RT0 unit cube 4^3, alpha = beta = 1, seed 1")
         else:
-            run_single(args, synth.config_c3(), "rt2_48x48x48 RT2 jittered 0.2h, alpha lognormal clipped "
-                                                "[1e-2,1e2], beta = 1e-2, seed 3")
+            out = run_single(args, synth.config_c3(), C3_LABEL)
+        print(json.dumps(out), flush=True)
         return
+    print(json.dumps(run_c2(args)), flush=True)
 
+
+C3_LABEL = "rt2_48x48x48 RT2 jittered 0.2h, alpha lognormal clipped [1e-2,1e2], beta = 1e-2, seed 3"
+
+
+def run_c2(args):
+    """RT1 on the structured 32^3 mesh (affine: the RT1-specific kernels)."""
     import torch
 
     import synth
@@ -523,6 +732,9 @@ def main():
 
     prob = synth.config_c2()
     k, ne = prob.k, prob.mesh.ne
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_mix([prob], label="the RT1 32^3 workload")
     plan = Plan(prob.mesh.xyz, prob.mesh.e2v, k).bind("cuda:0")
     dev = torch.device("cuda:0")
     alpha = torch.as_tensor(prob.alpha, device=dev)
@@ -538,7 +750,7 @@ def main():
         lam = torch.as_tensor(np.random.default_rng(0).standard_normal(plan.m), device=dev)
         info = {"iters": 0, "rel_res": None}
     else:
-        lam, info = plan.solve(1e-12, 20000)
+        lam, info = plan.pcg(1e-12, 20000)
     torch.cuda.synchronize()
     pcg_ms = (time.perf_counter() - t0) * 1e3
     if args.copy_calib:
@@ -598,14 +810,16 @@ def main():
            "roofline": roof}
     if not args.no_parity:
         out["error_vs_oracle"] = parity_sample(prob, plan, lam.cpu().numpy())
+    del plan
+    torch.cuda.empty_cache()
     if not args.no_mixed:
         out["mixed"] = mixed_leg(args, prob, lam, value)
     if not args.no_static:
         out["static_condensation"] = static_leg(args, prob, value, u)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob)
-        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
-    print(json.dumps(out), flush=True)
+    if cpu is not None:
+        cpu["gpu_over_cpu"] = value / cpu["value"]
+        out["cpu_baseline"] = cpu
+    return out
 
 
 if __name__ == "__main__":

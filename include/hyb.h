@@ -18,14 +18,16 @@
  * its face dofs with signs (Sec. 3.1 and Sec. 5).
  *
  * Call order: hyb_plan_create (host only, no GPU needed) -> hyb_bind ->
- * hyb_setup -> [hyb_rhs] -> hyb_solve -> hyb_recover -> hyb_destroy.
+ * hyb_setup -> [hyb_rhs] -> hyb_pcg -> hyb_recover -> hyb_destroy, or
+ * hyb_setup -> hyb_solve (rhs + PCG + recovery) for each new load.
  *
  * Conventions (fixed by this library; the paper leaves them to its FE code):
  *   - element vertex v = a + 2b + 4c sits at reference corner (a,b,c) of
  *     [0,1]^3; the geometry is the trilinear map of the 8 vertices and every
  *     element must have det J > 0;
  *   - face f = 2d + s is the face xi_d = s, outward sign eps_f = 2s - 1;
- *     faces on the domain boundary are essential (prescribed normal flux g);
+ *     faces on the domain boundary are essential (prescribed normal flux g)
+ *     unless hyb_mesh.ess marks them natural;
  *   - local dof order is interior dofs first (3 k (k+1)^2 of them), then the
  *     (k+1)^2 dofs of face 0, ..., face 5; a face dof (j0, j1) has index
  *     n_i + f (k+1)^2 + j0 + (k+1) j1; dofs are nodal normal components at
@@ -65,24 +67,27 @@ enum hyb_status_code {
   HYB_E_NOCONV = -7,    /* PCG did not reach rtol within maxit */
   HYB_E_HIP = -8,       /* HIP runtime error; detail holds the hipError_t */
   HYB_E_INTERNAL = -9,  /* the plan broke one of its own invariants (a bug) */
-  HYB_E_REFINE = -10    /* HYB_MIXED: an element's FP32 factor broke down
-                           or its refined solution fails the backward-error
-                           test (the scaled element matrix is too
-                           ill-conditioned for an FP32 factor, or not SPD);
-                           detail = element */
+  HYB_E_REFINE = -10    /* reserved (HYB_MIXED elements whose FP32 factor
+                           breaks down or whose refinement fails are solved
+                           in FP64 instead, see hyb_fallback_count) */
 };
 
 enum hyb_precision {
   HYB_FP64 = 0,         /* every step in double precision */
   HYB_MIXED = 1         /* element Cholesky and triangular solves in FP32
-                           (after an exact power-of-two diagonal scaling),
-                           refined against the FP64 element matrix for
-                           refine_sweeps sweeps; the element matrix, the
-                           refinement residuals, H, r, the solve and u are
-                           FP64.  The factor record then holds X = M_T^{-1}
-                           C_T^T, M_T, the FP32 factor and the scaling, and
+                           on the matrix cores (after an exact power-of-two
+                           diagonal scaling), refined against the FP64
+                           element matrix (residuals on the FP64 matrix
+                           cores); the element matrix, the residuals, H, r,
+                           the solve and u are FP64.  An element whose FP32
+                           factor breaks down or whose refinement fails the
+                           backward-error test is solved in FP64 (counted by
+                           hyb_fallback_count).  The factor record holds
+                           X = M_T^{-1} C_T^T (n x nb, column-major) and
                            recovery is u_T = y_T - X lambda_T (y_T = M_T^{-1}
-                           f_hat_T in the y buffer) */
+                           f_hat_T in the y buffer); hyb_rhs re-assembles M_T
+                           and re-derives the FP32 factor from the
+                           coefficients of the last setup */
 };
 
 /* Reduced system a plan assembles (Sec. 3.1 of the paper: hybridization
@@ -99,6 +104,14 @@ typedef struct hyb_mesh {
   int64_t ne;             /* number of hexahedra */
   const double* xyz;      /* host, nv x 3, row-major */
   const int32_t* e2v;     /* host, ne x 8, vertex v = a + 2b + 4c */
+  const uint8_t* ess;     /* host, ne x 6 (element, local face), or NULL:
+                             every boundary face is essential.  For a
+                             boundary face, nonzero = essential (normal flux
+                             prescribed by g; its dofs are eliminated, Sec. 5)
+                             and 0 = natural (its dofs stay unknowns of the
+                             element and carry no multiplier).  Entries of
+                             interior faces are not read.  Copied by
+                             hyb_plan_create. */
 } hyb_mesh;
 
 typedef struct hyb_opts {
@@ -111,9 +124,10 @@ typedef struct hyb_opts {
                              < 0: per element while the correction keeps
                              shrinking (stop at ||dx|| <= 2^-53 ||x|| or
                              ||dx|| > ||dx_prev|| / 2; at most 30 sweeps),
-                             then HYB_E_REFINE unless ||b - M x|| <= sqrt(n)
-                             2^-53 ||M|| ||x|| (inf-norms) */
-  int pcg_reduce;         /* where hyb_solve sums its per-block partials:
+                             then the element is solved in FP64 unless
+                             ||b - M x|| <= sqrt(n) 2^-53 ||M|| ||x||
+                             (inf-norms) */
+  int pcg_reduce;         /* where hyb_pcg sums its per-block partials:
                              0 automatic (by size), 1 inside the consuming
                              kernels, 2 in separate one-block kernels; the
                              results are the same bits either way */
@@ -127,6 +141,10 @@ typedef struct hyb_opts {
                              M_s the face mass matrix of the multiplier
                              space: H' = M_s H M_s, r' = M_s r, lambda' =
                              M_s^{-1} lambda, u unchanged (HYB_HYBRID) */
+  int quad_q;             /* Gauss-Legendre points per direction of the
+                             element quadrature: 0 or k + 2 (the rule the
+                             kernels are built for); any other value is
+                             HYB_E_ARG */
 } hyb_opts;
 
 /* Sizes of the caller-owned device buffers, filled by hyb_plan_create. */
@@ -158,7 +176,8 @@ typedef struct hyb_buffers {
   double* val;            /* nnz */
   double* r;              /* m: the reduced right-hand side */
   double* work;           /* bytes_work */
-  int32_t* status;        /* 4 ints: code, first failing element, spare */
+  int32_t* status;        /* 4 ints: code, first failing element, mixed-form
+                             FP64 fallback count, spare */
 } hyb_buffers;
 
 typedef struct hyb_solve_info {
@@ -224,13 +243,45 @@ int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta,
 int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g);
 
 /*
- * Jacobi-preconditioned CG on H lambda = r (device, deterministic
- * reductions); stops when ||r_k||_2 <= rtol ||r_0||_2 or after maxit
- * iterations.  lambda: device, m doubles (input: initial guess is zero;
- * output: solution).  Returns HYB_E_NOCONV if not converged.
+ * Jacobi-preconditioned CG on the reduced system H lambda = r (Sec. 6.1 of
+ * the paper solves it with PCG and stops on the relative l2 residual; the
+ * preconditioner here is the diagonal of H).  Deterministic reductions; stops
+ * when ||r_k||_2 <= rtol ||r_0||_2 (tested every 8 iterations) or after maxit
+ * iterations.  lambda: device, m doubles (the initial guess is zero; output:
+ * the solution).  Needs hyb_setup with f or hyb_rhs.  Returns HYB_E_NOCONV if
+ * not converged (lambda then holds the last iterate), HYB_E_STATE before a
+ * right-hand side, HYB_E_ARG for a null lambda or maxit < 0.
  */
-int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda,
-              hyb_solve_info* info);
+int hyb_pcg(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solve_info* info);
+
+/*
+ * The whole solve for a load on the current factors (Theorem 2.1): the
+ * right-hand side as hyb_rhs (f: device ne x 3, g: device boundary data or
+ * NULL), H lambda = r by hyb_pcg (rtol, maxit), then the recovery of u as
+ * hyb_recover.  lambda: device, m doubles; u: device, ne x n_local doubles.
+ * Errors: those of the three calls; on HYB_E_NOCONV u is still recovered
+ * from the last iterate and info says so.  HYB_E_STATE before hyb_setup.
+ */
+int hyb_solve(hyb_plan_t* plan, const double* f, const double* g, double rtol, int maxit, double* lambda,
+              double* u, hyb_solve_info* info);
+
+/*
+ * HYB_MIXED: the number of elements that the last hyb_setup or hyb_rhs (or
+ * batch setup) solved in FP64 because their FP32 factor broke down or their
+ * refinement failed the backward-error test (0 for HYB_FP64 plans).
+ * Synchronises the plan's stream.  Errors: HYB_E_ARG, HYB_E_STATE (not
+ * bound), HYB_E_HIP.
+ */
+int hyb_fallback_count(hyb_plan_t* plan, int64_t* count);
+
+/*
+ * Device pointers of the reduced matrix H in the bound buffers (borrowed,
+ * valid while the buffers are): row_ptr (m + 1, int64), col (nnz, int32),
+ * val (nnz, double; holds H after hyb_setup), and m, nnz.  Any output may be
+ * NULL.  Errors: HYB_E_ARG (null plan), HYB_E_STATE (not bound).
+ */
+int hyb_get_csr(const hyb_plan_t* plan, const int64_t** row_ptr, const int32_t** col, const double** val,
+                int64_t* m, int64_t* nnz);
 
 /*
  * Recovery of the broken flux (Theorem 2.1 back substitution):
@@ -329,6 +380,20 @@ int hyb_batch_graph(hyb_batch_t* b, int enable);
  * (may be NULL).  Needs every input of hyb_batch_set; overwrites the
  * outputs. */
 int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best);
+
+/*
+ * Timing of the batch phases with HIP events recorded on the stream each
+ * phase runs on (the batch's own stream on graph replays): one pair around
+ * every setup phase (the clearing of the same-face blocks, then the
+ * persistent setup launches) and one around every recovery phase.
+ * hyb_batch_timing_enable(b, 1) starts collecting (and drops earlier pairs;
+ * the autotuner's passes are not timed); hyb_batch_timing_read synchronises
+ * and returns the summed milliseconds and counts of each phase since
+ * enabling (outputs may be NULL), then clears them.  Errors: HYB_E_ARG,
+ * HYB_E_HIP.
+ */
+int hyb_batch_timing_enable(hyb_batch_t* b, int on);
+int hyb_batch_timing_read(hyb_batch_t* b, double* ms_setup, int* n_setup, double* ms_recover, int* n_recover);
 
 void hyb_batch_destroy(hyb_batch_t* b);
 

@@ -10,8 +10,9 @@ Usage::
     plan = Plan(xyz, e2v, k)            # host topology (no GPU needed)
     plan.bind()                          # device buffers on cuda:0
     plan.setup(alpha, beta, f)           # M_T, Cholesky, H_T -> H, r
-    lam, info = plan.solve(1e-12, 2000)  # Jacobi-PCG on H
+    lam, info = plan.pcg(1e-12, 2000)    # Jacobi-PCG on H
     u = plan.recover(lam)                # broken flux, ne x n
+    lam, u, info = plan.solve(f2)        # rhs + PCG + recovery for a new load
 """
 from __future__ import annotations
 
@@ -38,15 +39,20 @@ class Plan:
 
     def __init__(self, xyz: np.ndarray, e2v: np.ndarray, k: int, stream=None, generic: bool = False,
                  pcg_reduce: int = 0, precision: str = "fp64", sweeps: int | None = None,
-                 system: str = "hybrid", weighted_c: bool = False):
+                 system: str = "hybrid", weighted_c: bool = False, ess=None, quad_q: int = 0):
         lib = load_library()
         self._lib = lib
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.e2v = np.ascontiguousarray(e2v, dtype=np.int32)
         self.k = int(k)
+        # ess (ne, 6): 0 marks a natural boundary face (None: all essential)
+        self.ess = None if ess is None else np.ascontiguousarray(ess, dtype=np.uint8).reshape(-1, 6)
+        if self.ess is not None and self.ess.shape[0] != self.e2v.shape[0]:
+            raise ValueError("ess must have one row of 6 flags per element")
         mesh = _abi.HybMesh(self.xyz.shape[0], self.e2v.shape[0],
                             self.xyz.ctypes.data_as(ctypes.c_void_p),
-                            self.e2v.ctypes.data_as(ctypes.c_void_p))
+                            self.e2v.ctypes.data_as(ctypes.c_void_p),
+                            None if self.ess is None else self.ess.ctypes.data_as(ctypes.c_void_p))
         self._stream_obj = stream
         if precision not in ("fp64", "mixed"):
             raise ValueError(f"precision must be 'fp64' or 'mixed', not {precision!r}")
@@ -56,7 +62,8 @@ class Plan:
         opts = _abi.HybOpts(_abi.HYB_MIXED if precision == "mixed" else _abi.HYB_FP64,
                             ctypes.c_void_p(self._stream_handle()), 1 if generic else 0,
                             -1 if sweeps is None else int(sweeps), int(pcg_reduce),
-                            _abi.HYB_STATIC if system == "static" else _abi.HYB_HYBRID, 1 if weighted_c else 0)
+                            _abi.HYB_STATIC if system == "static" else _abi.HYB_HYBRID, 1 if weighted_c else 0,
+                            int(quad_q))
         self._plan = ctypes.c_void_p()
         sz = _abi.HybSizes()
         rc = lib.hyb_plan_create(ctypes.byref(mesh), self.k, ctypes.byref(opts), ctypes.byref(self._plan),
@@ -147,15 +154,34 @@ class Plan:
         self._g = self._dev(g, (ne, 6 * (self.k + 1) ** 2))
         _abi.check(self._lib, self._lib.hyb_rhs(self._plan, _dptr(self._f), _dptr(self._g)))
 
-    def solve(self, rtol=1e-12, maxit=10000, lam=None):
+    def pcg(self, rtol=1e-12, maxit=10000, lam=None):
+        """Jacobi-PCG on H lambda = r (hyb_pcg): (lambda, info)."""
         import torch
         if lam is None:
             lam = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.device)
         info = _abi.HybSolveInfo()
-        rc = self._lib.hyb_solve(self._plan, ctypes.c_double(rtol), int(maxit), _dptr(lam), ctypes.byref(info))
+        rc = self._lib.hyb_pcg(self._plan, ctypes.c_double(rtol), int(maxit), _dptr(lam), ctypes.byref(info))
         if rc not in (0, _abi.HYB_E_NOCONV):
             _abi.check(self._lib, rc)
         return lam[: self.m], dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res)
+
+    def solve(self, f, g=None, rtol=1e-12, maxit=10000, lam=None, u=None):
+        """The whole solve for a load on the current factors (hyb_solve: rhs,
+        PCG, recovery): (lambda, u, info)."""
+        import torch
+        ne = self.ne
+        self._f = self._dev(f, (ne, 3))
+        self._g = self._dev(g, (ne, 6 * (self.k + 1) ** 2))
+        if lam is None:
+            lam = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.device)
+        if u is None:
+            u = torch.empty((ne, self.n), dtype=torch.float64, device=self.device)
+        info = _abi.HybSolveInfo()
+        rc = self._lib.hyb_solve(self._plan, _dptr(self._f), _dptr(self._g), ctypes.c_double(rtol), int(maxit),
+                                 _dptr(lam), _dptr(u), ctypes.byref(info))
+        if rc not in (0, _abi.HYB_E_NOCONV):
+            _abi.check(self._lib, rc)
+        return lam[: self.m], u, dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res)
 
     def recover(self, lam, u=None):
         import torch
@@ -164,6 +190,12 @@ class Plan:
             u = torch.empty((self.ne, self.n), dtype=torch.float64, device=self.device)
         _abi.check(self._lib, self._lib.hyb_recover(self._plan, _dptr(lam), _dptr(u)))
         return u
+
+    def fallback_count(self) -> int:
+        """Elements the last setup or rhs of a mixed plan solved in FP64."""
+        c = ctypes.c_int64()
+        _abi.check(self._lib, self._lib.hyb_fallback_count(self._plan, ctypes.byref(c)))
+        return c.value
 
     def status(self):
         """Synchronise and return (code, element) of the first device error."""
@@ -184,8 +216,17 @@ class Plan:
                                                          ctypes.byref(ms_r), ctypes.byref(n_r)))
         return dict(setup_ms=ms_s.value, setup_n=n_s.value, recover_ms=ms_r.value, recover_n=n_r.value)
 
+    def csr_pointers(self):
+        """hyb_get_csr: device addresses of row_ptr, col, val and m, nnz."""
+        rp, ci, va = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        m, nnz = ctypes.c_int64(), ctypes.c_int64()
+        _abi.check(self._lib, self._lib.hyb_get_csr(self._plan, ctypes.byref(rp), ctypes.byref(ci), ctypes.byref(va),
+                                                     ctypes.byref(m), ctypes.byref(nnz)))
+        return dict(row_ptr=rp.value or 0, col=ci.value or 0, val=va.value or 0, m=m.value, nnz=nnz.value)
+
     def csr(self):
-        """Device CSR arrays (row_ptr, col, val) of H."""
+        """Device CSR arrays (row_ptr, col, val) of H: the bound buffers that
+        hyb_get_csr points into."""
         b = self.bufs
         return b["row_ptr"], b["col"][: self.nnz], b["val"][: self.nnz]
 
@@ -261,6 +302,19 @@ class Batch:
             _abi.check(self._lib, self._lib.hyb_batch_set_tiles(self._b, ctypes.byref(t)))
         _abi.check(self._lib, self._lib.hyb_batch_get_tiles(self._b, ctypes.byref(t)))
         return (t.blocks_per_cu, t.items_per_block)
+
+    def timing(self, on: bool = True):
+        """Start (or stop) HIP-event timing of the setup and recovery phases."""
+        _abi.check(self._lib, self._lib.hyb_batch_timing_enable(self._b, 1 if on else 0))
+
+    def timing_read(self):
+        """Summed phase milliseconds since timing(True): dict with setup_ms,
+        setup_n, recover_ms, recover_n (then cleared)."""
+        ms_s, ms_r = ctypes.c_double(), ctypes.c_double()
+        n_s, n_r = ctypes.c_int(), ctypes.c_int()
+        _abi.check(self._lib, self._lib.hyb_batch_timing_read(self._b, ctypes.byref(ms_s), ctypes.byref(n_s),
+                                                               ctypes.byref(ms_r), ctypes.byref(n_r)))
+        return dict(setup_ms=ms_s.value, setup_n=n_s.value, recover_ms=ms_r.value, recover_n=n_r.value)
 
     def autotune(self, reps: int = 3):
         t = _abi.HybBatchTiles()

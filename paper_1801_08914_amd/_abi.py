@@ -25,10 +25,11 @@ HYB_STATIC = 1
 # Every extern "C" symbol declared in include/hyb.h.
 EXPORTS = [
     "hyb_plan_create", "hyb_plan_topology", "hyb_last_detail", "hyb_bind", "hyb_setup", "hyb_rhs",
-    "hyb_solve", "hyb_recover", "hyb_status", "hyb_strerror", "hyb_destroy",
+    "hyb_pcg", "hyb_solve", "hyb_get_csr", "hyb_fallback_count", "hyb_recover", "hyb_status", "hyb_strerror", "hyb_destroy",
     "hyb_timing_enable", "hyb_timing_read", "hyb_set_stream",
     "hyb_batch_create", "hyb_batch_set", "hyb_batch_setup", "hyb_batch_recover", "hyb_batch_set_tiles",
-    "hyb_batch_get_tiles", "hyb_batch_graph", "hyb_batch_autotune", "hyb_batch_destroy",
+    "hyb_batch_get_tiles", "hyb_batch_graph", "hyb_batch_autotune", "hyb_batch_timing_enable",
+    "hyb_batch_timing_read", "hyb_batch_destroy",
 ]
 
 
@@ -45,13 +46,13 @@ class HybError(RuntimeError):
 
 class HybMesh(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("xyz", ctypes.c_void_p),
-                ("e2v", ctypes.c_void_p)]
+                ("e2v", ctypes.c_void_p), ("ess", ctypes.c_void_p)]
 
 
 class HybOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("stream", ctypes.c_void_p), ("kernel_variant", ctypes.c_int),
                 ("refine_sweeps", ctypes.c_int), ("pcg_reduce", ctypes.c_int), ("system", ctypes.c_int),
-                ("weighted_c", ctypes.c_int)]
+                ("weighted_c", ctypes.c_int), ("quad_q", ctypes.c_int)]
 
 
 class HybSizes(ctypes.Structure):
@@ -93,7 +94,10 @@ def load_library():
     lib.hyb_bind.argtypes = [vp, vp]
     lib.hyb_setup.argtypes = [vp, vp, vp, vp, vp]
     lib.hyb_rhs.argtypes = [vp, vp, vp]
-    lib.hyb_solve.argtypes = [vp, ctypes.c_double, ci, vp, vp]
+    lib.hyb_pcg.argtypes = [vp, ctypes.c_double, ci, vp, vp]
+    lib.hyb_solve.argtypes = [vp, vp, vp, ctypes.c_double, ci, vp, vp, vp]
+    lib.hyb_get_csr.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.hyb_fallback_count.argtypes = [vp, vp]
     lib.hyb_recover.argtypes = [vp, vp, vp]
     lib.hyb_status.argtypes = [vp, vp]
     lib.hyb_strerror.restype = ctypes.c_char_p
@@ -111,6 +115,8 @@ def load_library():
     lib.hyb_batch_get_tiles.argtypes = [vp, vp]
     lib.hyb_batch_graph.argtypes = [vp, ci]
     lib.hyb_batch_autotune.argtypes = [vp, ci, vp]
+    lib.hyb_batch_timing_enable.argtypes = [vp, ci]
+    lib.hyb_batch_timing_read.argtypes = [vp, vp, vp, vp, vp]
     lib.hyb_batch_destroy.argtypes = [vp]
     lib.hyb_batch_destroy.restype = None
     for name in EXPORTS:

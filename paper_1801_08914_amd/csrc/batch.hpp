@@ -6,6 +6,7 @@
 #include "kernels_common.hpp"
 #include "mixed.hpp"
 #include "setup_generic.hpp"
+#include "setup_k3.hpp"
 
 namespace hyb {
 
@@ -27,16 +28,16 @@ struct BatchItem {
 };
 
 // Element blocks per order (teams x lanes = 512 threads for every order:
-// 32 x 16, 8 x 64, one element on 512 lanes for k = 2, two elements on 256
-// lanes each for k = 3, the team of the single-plan RT3 kernels).  The
-// per-element arithmetic does not depend on the team size (every entry is
-// summed in a fixed order), so a batch gives the single plans' bits.
-__host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 32 : (k == 1 ? 8 : (k == 2 ? 1 : 2)); }
-// Mixed-precision problems: 32 x 16, 4 x 128 (eight RT1 mixed layouts
-// would exceed the LDS), then one element per block (the RT3 mixed record
-// holds M_T and X in HBM: one element per block).
-__host__ __device__ constexpr int batch_epb_mixed(int k) { return k == 0 ? 32 : (k == 1 ? 4 : 1); }
+// 32 x 16, 8 x 64, then one element on 512 lanes for k = 2 and k = 3, the
+// teams of the single-plan kernels).  The per-element arithmetic does not
+// depend on the team size (every entry is summed in a fixed order), so a
+// batch gives the single plans' bits.
+__host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 32 : (k == 1 ? 8 : 1); }
+// Mixed-precision problems: 8 x 64, 4 x 128, then one element per block
+// (RT3: its FP64 element matrix in the workgroup's scratch slot).
+__host__ __device__ constexpr int batch_epb_mixed(int k) { return k == 0 ? 8 : (k == 1 ? 4 : 1); }
 constexpr int kBatchThreads = 512;
+constexpr int kBatchThreadsK3 = 512;
 
 // The order-specific element routines as separate functions: inlined into
 // one persistent kernel, the four bodies share one register allocation (and
@@ -45,13 +46,17 @@ template <int K, int TEAM, int EPB>
 __device__ __attribute__((noinline)) void batch_setup_fp64(const SetupArgs& a, double* smem, int64_t blk) {
   setup_generic_body<K, TEAM, EPB>(a, smem, blk);
 }
+__device__ __attribute__((noinline)) void batch_setup_k3(const SetupArgs& a, double* smem, int64_t blk) {
+  setup_k3_body<kBatchThreadsK3>(a, smem, blk);
+}
 template <int K, int TEAM, int EPB>
 __device__ __attribute__((noinline)) void batch_recover_fp64(const RecoverArgs& a, double* smem, int64_t blk) {
   recover_generic_body<K, TEAM, EPB>(a, smem, blk);
 }
 template <int K, int TEAM, int EPB>
-__device__ __attribute__((noinline)) void batch_setup_mx(const SetupArgs& a, double* smem, int64_t blk, int sweeps) {
-  setup_mixed_body<K, TEAM, EPB>(a, smem, blk, sweeps);
+__device__ __attribute__((noinline)) void batch_setup_mx(const SetupArgs& a, double* smem, int64_t blk, int sweeps,
+                                                         double* scratch) {
+  setup_mixed_body<K, TEAM, EPB>(a, smem, blk, sweeps, scratch);
 }
 
 // Zero the same-face blocks of H (and r) of every problem: blockIdx.y is the
@@ -71,6 +76,8 @@ __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
       P.s.r[i - nd] = 0.0;
     }
   }
+  // the mixed form's count of elements solved in FP64 restarts with the setup
+  if (P.mixed && blockIdx.x == 0 && threadIdx.x == 0) P.s.status[2] = 0;
 }
 
 __global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* probs, const BatchItem* items,
@@ -85,7 +92,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* 
         case 0: batch_setup_fp64<0, 16, 32>(P.s, smem, blk); break;
         case 1: batch_setup_fp64<1, 64, 8>(P.s, smem, blk); break;
         case 2: batch_setup_fp64<2, 512, 1>(P.s, smem, blk); break;
-        default: batch_setup_fp64<3, 256, 2>(P.s, smem, blk); break;
+        default: batch_setup_k3(P.s, smem, blk); break;
       }
       __syncthreads();   // the next block reuses the LDS
     }
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
         case 0: batch_recover_fp64<0, 16, 32>(P.r, smem, blk); break;
         case 1: batch_recover_fp64<1, 64, 8>(P.r, smem, blk); break;
         case 2: batch_recover_fp64<2, 512, 1>(P.r, smem, blk); break;
-        default: batch_recover_fp64<3, 256, 2>(P.r, smem, blk); break;
+        default: batch_recover_fp64<3, 512, 1>(P.r, smem, blk); break;
       }
       __syncthreads();
     }
@@ -115,18 +122,20 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
 // items follow the FP64 ones in the list; a separate launch, so the FP64
 // kernels keep their own LDS size).
 __global__ __launch_bounds__(kBatchThreads) void k_setup_batch_mixed(const BatchProb* probs, const BatchItem* items,
-                                                                     int64_t nitems) {
+                                                                     int64_t nitems, double* scratch) {
   extern __shared__ double smem[];
+  // workgroup b owns scratch slot b (k = 3; the grid has at most kMixedSlots workgroups)
+  double* slot = scratch ? scratch + int64_t(blockIdx.x) * MixedLayout<3, 512, 1>::slot : nullptr;
   for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
     const BatchItem it = items[w];
     const BatchProb& P = probs[it.prob];
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
       switch (P.k) {
-        case 0: batch_setup_mx<0, 16, 32>(P.s, smem, blk, P.sweeps); break;
-        case 1: batch_setup_mx<1, 128, 4>(P.s, smem, blk, P.sweeps); break;
-        case 2: batch_setup_mx<2, 512, 1>(P.s, smem, blk, P.sweeps); break;
-        default: batch_setup_mx<3, 512, 1>(P.s, smem, blk, P.sweeps); break;
+        case 0: batch_setup_mx<0, 64, 8>(P.s, smem, blk, P.sweeps, nullptr); break;
+        case 1: batch_setup_mx<1, 128, 4>(P.s, smem, blk, P.sweeps, nullptr); break;
+        case 2: batch_setup_mx<2, 512, 1>(P.s, smem, blk, P.sweeps, nullptr); break;
+        default: batch_setup_mx<3, 512, 1>(P.s, smem, blk, P.sweeps, slot); break;
       }
       __syncthreads();
     }
@@ -142,7 +151,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch_mixed(const Bat
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
       switch (P.k) {
-        case 0: recover_mixed_body<0, 16, 32>(P.r, smem, blk); break;
+        case 0: recover_mixed_body<0, 64, 8>(P.r, smem, blk); break;
         case 1: recover_mixed_body<1, 128, 4>(P.r, smem, blk); break;
         case 2: recover_mixed_body<2, 512, 1>(P.r, smem, blk); break;
         default: recover_mixed_body<3, 512, 1>(P.r, smem, blk); break;
@@ -158,7 +167,7 @@ inline size_t batch_setup_lds(int k) {
     case 0: return 8 * 32 * size_t(GenericLayout<0, 16, 32>::per);
     case 1: return 8 * 8 * size_t(GenericLayout<1, 64, 8>::per);
     case 2: return 8 * size_t(GenericLayout<2, 512, 1>::per);
-    default: return 8 * 2 * size_t(GenericLayout<3, 256, 2>::per);
+    default: return 8 * size_t(K3Layout::per);
   }
 }
 inline size_t batch_recover_lds(int k) {
@@ -166,13 +175,13 @@ inline size_t batch_recover_lds(int k) {
     case 0: return 8 * 32 * size_t(recover_per<0>());
     case 1: return 8 * 8 * size_t(recover_per<1>());
     case 2: return 8 * size_t(recover_per<2>());
-    default: return 8 * 2 * size_t(recover_per<3>());
+    default: return 8 * size_t(recover_per<3>());
   }
 }
 
 inline size_t batch_setup_lds_mixed(int k) {
   switch (k) {
-    case 0: return 8 * 32 * size_t(MixedLayout<0, 16, 32>::per);
+    case 0: return 8 * 8 * size_t(MixedLayout<0, 64, 8>::per);
     case 1: return 8 * 4 * size_t(MixedLayout<1, 128, 4>::per);
     case 2: return 8 * size_t(MixedLayout<2, 512, 1>::per);
     default: return 8 * size_t(MixedLayout<3, 512, 1>::per);
@@ -180,7 +189,7 @@ inline size_t batch_setup_lds_mixed(int k) {
 }
 inline size_t batch_recover_lds_mixed(int k) {
   switch (k) {
-    case 0: return 8 * 32 * size_t(RT<0>::nb);
+    case 0: return 8 * 8 * size_t(RT<0>::nb);
     case 1: return 8 * 4 * size_t(RT<1>::nb);
     case 2: return 8 * size_t(RT<2>::nb);
     default: return 8 * size_t(RT<3>::nb);

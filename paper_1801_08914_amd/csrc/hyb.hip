@@ -13,6 +13,7 @@
 #include "k1_fast.hpp"
 #include "setup_generic.hpp"
 #include "mixed.hpp"
+#include "setup_k3.hpp"
 #include "batch.hpp"
 
 #include <algorithm>
@@ -43,6 +44,7 @@ hyb::DeviceMaps device_maps(const hyb::Plan& P) {
   m.tab_w = reinterpret_cast<const double*>(base + L.tab_w);
   m.tab_ref = reinterpret_cast<const double*>(base + L.tab_ref);
   m.gauss_x = reinterpret_cast<const double*>(base + L.tab_x);
+  m.tab1d = reinterpret_cast<const double*>(base + L.tab_1d);
   m.face_selfslot = reinterpret_cast<const int32_t*>(base + L.face_selfslot);
   m.face_owner = reinterpret_cast<const int32_t*>(base + L.face_owner);
   m.k1_geo = reinterpret_cast<const double*>(base + L.k1_geo);
@@ -94,7 +96,12 @@ int dispatch_setup(int k, const hyb::SetupArgs& a, hipStream_t s) {
     case 0: return launch_setup<0, 16, 16>(a, s);
     case 1: return launch_setup<1, 64, 4>(a, s);
     case 2: return launch_setup<2, 512, 1>(a, s);
-    case 3: return launch_setup<3, 256, 1>(a, s);
+    case 3:
+      if (a.ne > 0) {
+        hipLaunchKernelGGL(hyb::k_setup_k3<512>, dim3(unsigned(a.ne)), dim3(512), 0, s, a);
+        HYB_HIP(hipGetLastError());
+      }
+      return HYB_OK;
     default: return HYB_E_ARG;
   }
 }
@@ -127,6 +134,21 @@ int launch_setup_mixed(const hyb::SetupArgs& a, int sweeps, hipStream_t s) {
   return HYB_OK;
 }
 
+// k = 3: a persistent grid of at most kMixedSlots workgroups, each with its
+// scratch slot (FP64 element matrix, FP32 work columns) in the work buffer.
+int launch_setup_mixed3(const hyb::SetupArgs& a, int sweeps, double* scratch, hipStream_t s) {
+  if (a.ne == 0) return HYB_OK;
+  const int64_t grid = std::min<int64_t>(a.ne, hyb::kMixedSlots);
+  hipLaunchKernelGGL((hyb::k_setup_mixed_slots<3, 512>), dim3(unsigned(grid)), dim3(512), 0, s, a, sweeps, scratch);
+  HYB_HIP(hipGetLastError());
+  return HYB_OK;
+}
+
+// Bytes of the k = 3 mixed scratch slots.
+int64_t mixed_scratch_bytes(int k) {
+  return k == 3 ? int64_t(8) * hyb::kMixedSlots * hyb::MixedLayout<3, 512, 1>::slot : 0;
+}
+
 template <int K, int TEAM, int EPB>
 int launch_recover_mixed(const hyb::RecoverArgs& a, hipStream_t s) {
   if (a.ne == 0) return HYB_OK;
@@ -136,12 +158,15 @@ int launch_recover_mixed(const hyb::RecoverArgs& a, hipStream_t s) {
   return HYB_OK;
 }
 
-int dispatch_setup_mixed(int k, const hyb::SetupArgs& a, int sweeps, hipStream_t s) {
+int dispatch_setup_mixed(int k, const hyb::SetupArgs& a, int sweeps, double* scratch, hipStream_t s) {
+  // the count of elements solved in FP64 restarts with every call
+  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, s, a.status + 2, int64_t(1), 0);
+  HYB_HIP(hipGetLastError());
   switch (k) {
-    case 0: return launch_setup_mixed<0, 16, 16>(a, sweeps, s);
-    case 1: return launch_setup_mixed<1, 64, 4>(a, sweeps, s);
+    case 0: return launch_setup_mixed<0, 64, 4>(a, sweeps, s);
+    case 1: return launch_setup_mixed<1, 128, 2>(a, sweeps, s);
     case 2: return launch_setup_mixed<2, 512, 1>(a, sweeps, s);
-    case 3: return launch_setup_mixed<3, 512, 1>(a, sweeps, s);
+    case 3: return launch_setup_mixed3(a, sweeps, scratch, s);
     default: return HYB_E_ARG;
   }
 }
@@ -263,7 +288,8 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
               opt->pcg_reduce > 2 || opt->refine_sweeps > 16 ||
               (opt->system != HYB_HYBRID && opt->system != HYB_STATIC) ||
               (opt->system == HYB_STATIC && opt->precision != HYB_FP64) ||
-              (opt->weighted_c && opt->system == HYB_STATIC)))
+              (opt->weighted_c && opt->system == HYB_STATIC) ||
+              (opt->quad_q != 0 && opt->quad_q != k + 2)))
     return HYB_E_ARG;
   hyb_plan* p = new (std::nothrow) hyb_plan;
   if (!p) return HYB_E_NOMEM;
@@ -279,7 +305,14 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
   P.mixed = P.opts.precision == HYB_MIXED;
   P.stat = P.opts.system == HYB_STATIC;
   P.sweeps = P.opts.refine_sweeps < 0 ? -1 : P.opts.refine_sweeps;
-  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0 && !P.mixed && !P.stat && !P.opts.weighted_c;
+  if (P.stat && P.has_natural) {
+    // static condensation keeps one global dof per face dof and numbers them
+    // like the multipliers, which natural boundary faces do not have
+    delete p;
+    return HYB_E_ARG;
+  }
+  P.fast_k1 = k == 1 && P.all_affine && P.opts.kernel_variant == 0 && !P.mixed && !P.stat && !P.opts.weighted_c &&
+              !P.has_natural;
   if (P.opts.weighted_c) {
     // M_s of the weighted constraint: the face dofs' tangential nodes are the
     // k+1 Gauss-Legendre points, so the face mass matrix of their Lagrange
@@ -332,7 +365,8 @@ int hyb_plan_create(const hyb_mesh* mesh, int k, const hyb_opts* opt, hyb_plan_t
     sizes->bytes_maps = int64_t(P.lay.total);
     sizes->bytes_factor = 8 * P.ne * P.factor_len;
     sizes->bytes_y = 8 * P.ne * P.ord.n;
-    sizes->bytes_work = work_bytes(P.m, P.work_blocks, P.spmv_blocks, P.nfaces);
+    sizes->bytes_work = std::max(work_bytes(P.m, P.work_blocks, P.spmv_blocks, P.nfaces),
+                                 P.mixed ? mixed_scratch_bytes(k) : int64_t(0));
   }
   *out = p;
   return HYB_OK;
@@ -378,6 +412,7 @@ int hyb_bind(hyb_plan_t* plan, const hyb_buffers* buf) {
   put(L.tab_w, P.tab_w.data(), 8 * P.tab_w.size());
   put(L.tab_ref, P.tab_ref.data(), 8 * P.tab_ref.size());
   put(L.tab_x, P.tab_x.data(), 8 * P.tab_x.size());
+  put(L.tab_1d, P.tab_1d.data(), 8 * P.tab_1d.size());
   put(L.face_selfslot, P.face_selfslot.data(), 4 * P.face_selfslot.size());
   {
     std::vector<int32_t> owner_elem(size_t(P.nfaces));
@@ -433,7 +468,7 @@ int hyb_setup(hyb_plan_t* plan, const double* alpha, const double* beta, const d
   } else {
     rc = zero_diag(P, s);
     if (!rc && f) rc = fill(s, P.buf.r, P.m, 0.0);
-    if (!rc) rc = P.mixed ? dispatch_setup_mixed(P.ord.k, a, P.sweeps, s) : dispatch_setup(P.ord.k, a, s);
+    if (!rc) rc = P.mixed ? dispatch_setup_mixed(P.ord.k, a, P.sweeps, P.buf.work, s) : dispatch_setup(P.ord.k, a, s);
   }
   mark(P, P.ev_setup);
   if (rc) return rc;
@@ -478,21 +513,28 @@ int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g) {
     a.status = P.buf.status;
     a.mode = hyb::MODE_RHS;
     a.stat = P.stat ? 1 : 0;
-    rc = P.mixed ? dispatch_setup_mixed(P.ord.k, a, P.sweeps, s) : dispatch_setup(P.ord.k, a, s);
+    rc = P.mixed ? dispatch_setup_mixed(P.ord.k, a, P.sweeps, P.buf.work, s) : dispatch_setup(P.ord.k, a, s);
   }
   if (rc) return rc;
   P.have_rhs = true;
   return HYB_OK;
 }
 
-int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solve_info* info) {
-  if (!plan || !lambda || maxit < 0) return HYB_E_ARG;
-  hyb::Plan& P = plan->P;
-  if (!P.have_rhs) return HYB_E_STATE;
+}  // extern "C"
+
+namespace {
+
+// Bytes of PCG work (vectors, partial sums, the scalars) of a plan.
+size_t pcg_work_bytes(const hyb::Plan& P) {
+  return ((8 * (6 * size_t(P.m) + P.spmv_blocks + 4 * size_t(P.work_blocks)) + 63) & ~size_t(63)) +
+         sizeof(hyb::PcgScalars);
+}
+
+// The Jacobi-PCG of hyb_pcg with its work vectors at w.
+int pcg_run(hyb::Plan& P, double rtol, int maxit, double* lambda, hyb_solve_info* info, double* w) {
   hipStream_t s = stream_of(P);
   const int64_t m = P.m;
   const int nblk = P.work_blocks, nspmv = P.spmv_blocks;
-  double* w = P.buf.work;
   double* r = w;
   double* z = r + m;
   double* pb[2] = {z + m, z + 2 * m};
@@ -567,6 +609,18 @@ int hyb_solve(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solv
   return conv ? HYB_OK : HYB_E_NOCONV;
 }
 
+}  // namespace
+
+extern "C" {
+
+int hyb_pcg(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solve_info* info) {
+  if (!plan || !lambda || maxit < 0) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  if (!P.have_rhs) return HYB_E_STATE;
+  return pcg_run(P, rtol, maxit, lambda, info, P.buf.work);
+}
+
+
 int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u) {
   if (!plan || !lambda || !u) return HYB_E_ARG;
   hyb::Plan& P = plan->P;
@@ -594,6 +648,43 @@ int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u) {
   }
   mark(P, P.ev_recover);
   return rc;
+}
+
+int hyb_solve(hyb_plan_t* plan, const double* f, const double* g, double rtol, int maxit, double* lambda,
+              double* u, hyb_solve_info* info) {
+  if (!plan || !f || !lambda || !u || maxit < 0) return HYB_E_ARG;
+  if (!plan->P.have_setup) return HYB_E_STATE;
+  int rc = hyb_rhs(plan, f, g);
+  if (rc) return rc;
+  const int rc_pcg = hyb_pcg(plan, rtol, maxit, lambda, info);
+  if (rc_pcg != HYB_OK && rc_pcg != HYB_E_NOCONV) return rc_pcg;
+  rc = hyb_recover(plan, lambda, u);
+  return rc ? rc : rc_pcg;
+}
+
+int hyb_fallback_count(hyb_plan_t* plan, int64_t* count) {
+  if (!plan || !count) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  if (!P.bound) return HYB_E_STATE;
+  hipStream_t s = stream_of(P);
+  int32_t st[4] = {0, 0, 0, 0};
+  HYB_HIP(hipMemcpyAsync(st, P.buf.status, sizeof(st), hipMemcpyDeviceToHost, s));
+  HYB_HIP(hipStreamSynchronize(s));
+  *count = P.mixed ? int64_t(st[2]) : 0;
+  return HYB_OK;
+}
+
+int hyb_get_csr(const hyb_plan_t* plan, const int64_t** row_ptr, const int32_t** col, const double** val,
+                int64_t* m, int64_t* nnz) {
+  if (!plan) return HYB_E_ARG;
+  const hyb::Plan& P = plan->P;
+  if (!P.bound) return HYB_E_STATE;
+  if (row_ptr) *row_ptr = P.buf.row_ptr;
+  if (col) *col = P.buf.col;
+  if (val) *val = P.buf.val;
+  if (m) *m = P.m;
+  if (nnz) *nnz = P.nnz;
+  return HYB_OK;
 }
 
 int hyb_timing_enable(hyb_plan_t* plan, int on) {
@@ -680,6 +771,10 @@ struct hyb_batch {
   hipGraphExec_t g_setup = nullptr, g_recover = nullptr;
   hipStream_t gstream = nullptr;           // capture/replay stream (graphs need a non-null stream)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  double* scratch = nullptr;               // k = 3 mixed: a slot per workgroup of the mixed launch
+  // optional HIP-event timing of each phase (start/stop pairs, launch order)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_setup, ev_recover, ev_pool;
 };
 
 namespace {
@@ -771,8 +866,9 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {
-    hipLaunchKernelGGL(hyb::k_setup_batch_mixed, dim3(batch_grid(b, nmx)), dim3(hyb::kBatchThreads),
-                       b->lds_setup_mx, st, b->d_probs, b->d_items + b->n64, int64_t(nmx));
+    const unsigned gm = std::min<unsigned>(batch_grid(b, nmx), unsigned(hyb::kMixedSlots));
+    hipLaunchKernelGGL(hyb::k_setup_batch_mixed, dim3(gm), dim3(hyb::kBatchThreads), b->lds_setup_mx, st,
+                       b->d_probs, b->d_items + b->n64, int64_t(nmx), b->scratch);
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
@@ -793,12 +889,32 @@ int batch_launch_recover(hyb_batch* b, hipStream_t st) {
   return HYB_OK;
 }
 
-// Run fn on the stream, or replay its captured graph.
+// A timing event recorded on st (from the batch's pool), appended to list.
+int batch_mark(hyb_batch* b, std::vector<hipEvent_t>& list, hipStream_t st) {
+  if (!b->timing) return HYB_OK;
+  hipEvent_t e = nullptr;
+  if (!b->ev_pool.empty()) {
+    e = b->ev_pool.back();
+    b->ev_pool.pop_back();
+  } else {
+    HYB_HIP(hipEventCreate(&e));
+  }
+  list.push_back(e);
+  HYB_HIP(hipEventRecord(e, st));
+  return HYB_OK;
+}
+
+// Run fn on the stream, or replay its captured graph; with timing on, the
+// phase is bracketed by events on the stream it runs on.
 template <class Fn>
-int batch_run(hyb_batch* b, hipGraphExec_t& g, Fn&& fn) {
+int batch_run(hyb_batch* b, hipGraphExec_t& g, std::vector<hipEvent_t>& evs, Fn&& fn) {
   int rc = batch_upload(b);
   if (rc) return rc;
-  if (!b->use_graph) return fn(b, b->stream);
+  if (!b->use_graph) {
+    if ((rc = batch_mark(b, evs, b->stream))) return rc;
+    if ((rc = fn(b, b->stream))) return rc;
+    return batch_mark(b, evs, b->stream);
+  }
   // graphs are captured and replayed on the batch's own stream, ordered
   // after and before the plans' stream by events
   if (!g) {
@@ -817,7 +933,9 @@ int batch_run(hyb_batch* b, hipGraphExec_t& g, Fn&& fn) {
   }
   HYB_HIP(hipEventRecord(b->ev_in, b->stream));
   HYB_HIP(hipStreamWaitEvent(b->gstream, b->ev_in, 0));
+  if ((rc = batch_mark(b, evs, b->gstream))) return rc;
   HYB_HIP(hipGraphLaunch(g, b->gstream));
+  if ((rc = batch_mark(b, evs, b->gstream))) return rc;
   HYB_HIP(hipEventRecord(b->ev_out, b->gstream));
   HYB_HIP(hipStreamWaitEvent(b->stream, b->ev_out, 0));
   return HYB_OK;
@@ -881,7 +999,10 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
       b->lds_recover = std::max(b->lds_recover, hyb::batch_recover_lds(P.ord.k));
     }
   }
+  bool mixed3 = false;
+  for (int32_t i = 0; i < count; ++i) mixed3 |= plans[i]->P.mixed && plans[i]->P.ord.k == 3;
   hipError_t e1 = hipMalloc(&b->d_probs, sizeof(hyb::BatchProb) * b->probs.size());
+  if (e1 == hipSuccess && mixed3) e1 = hipMalloc(&b->scratch, size_t(mixed_scratch_bytes(3)));
   if (e1 == hipSuccess) e1 = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
   if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
@@ -949,7 +1070,7 @@ int hyb_batch_setup(hyb_batch_t* b) {
   if (!b) return HYB_E_ARG;
   for (const auto& pr : b->probs)
     if (!pr.s.alpha || !pr.s.beta) return HYB_E_STATE;
-  int rc = batch_run(b, b->g_setup, batch_launch_setup);
+  int rc = batch_run(b, b->g_setup, b->ev_setup, batch_launch_setup);
   if (rc) return rc;
   for (size_t i = 0; i < b->plans.size(); ++i) {
     hyb::Plan& P = b->plans[i]->P;
@@ -965,15 +1086,16 @@ int hyb_batch_recover(hyb_batch_t* b) {
   if (!b) return HYB_E_ARG;
   for (size_t i = 0; i < b->plans.size(); ++i)
     if (!b->plans[i]->P.have_rhs || !b->probs[i].r.lambda || !b->probs[i].r.u) return HYB_E_STATE;
-  return batch_run(b, b->g_recover, batch_launch_recover);
+  return batch_run(b, b->g_recover, b->ev_recover, batch_launch_recover);
 }
 
 int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best) {
   if (!b || reps <= 0) return HYB_E_ARG;
   for (const auto& pr : b->probs)
     if (!pr.s.alpha || !pr.s.beta || !pr.r.lambda || !pr.r.u) return HYB_E_STATE;
-  const bool graph = b->use_graph;
+  const bool graph = b->use_graph, timing = b->timing;
   b->use_graph = false;
+  b->timing = false;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   HYB_HIP(hipEventCreate(&t0));
   HYB_HIP(hipEventCreate(&t1));
@@ -1010,6 +1132,7 @@ int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best) {
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   b->use_graph = graph;
+  b->timing = timing;
   if (rc) return rc;
   rc = hyb_batch_set_tiles(b, &win);
   if (rc) return rc;
@@ -1017,13 +1140,51 @@ int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best) {
   return HYB_OK;
 }
 
+int hyb_batch_timing_enable(hyb_batch_t* b, int on) {
+  if (!b) return HYB_E_ARG;
+  for (auto* L : {&b->ev_setup, &b->ev_recover}) {
+    for (hipEvent_t e : *L) b->ev_pool.push_back(e);
+    L->clear();
+  }
+  b->timing = on != 0;
+  return HYB_OK;
+}
+
+int hyb_batch_timing_read(hyb_batch_t* b, double* ms_setup, int* n_setup, double* ms_recover, int* n_recover) {
+  if (!b) return HYB_E_ARG;
+  HYB_HIP(hipStreamSynchronize(b->stream));
+  if (b->gstream) HYB_HIP(hipStreamSynchronize(b->gstream));
+  auto sum = [&](std::vector<hipEvent_t>& L, double* ms, int* cnt) -> int {
+    double tot = 0.0;
+    int c = 0;
+    for (size_t i = 0; i + 1 < L.size(); i += 2) {
+      float t = 0.0f;
+      hipError_t err = hipEventElapsedTime(&t, L[i], L[i + 1]);
+      if (err != hipSuccess) return hip_fail(err);
+      tot += t;
+      ++c;
+    }
+    for (hipEvent_t e : L) b->ev_pool.push_back(e);
+    L.clear();
+    if (ms) *ms = tot;
+    if (cnt) *cnt = c;
+    return HYB_OK;
+  };
+  int rc = sum(b->ev_setup, ms_setup, n_setup);
+  if (rc) return rc;
+  return sum(b->ev_recover, ms_recover, n_recover);
+}
+
 void hyb_batch_destroy(hyb_batch_t* b) {
   if (!b) return;
   if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+  for (auto* L : {&b->ev_setup, &b->ev_recover, &b->ev_pool})
+    for (hipEvent_t e : *L) (void)hipEventDestroy(e);
   for (hipGraphExec_t g : {b->g_setup, b->g_recover})
     if (g) (void)hipGraphExecDestroy(g);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_probs) (void)hipFree(b->d_probs);
+  if (b->scratch) (void)hipFree(b->scratch);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->gstream) (void)hipStreamDestroy(b->gstream);

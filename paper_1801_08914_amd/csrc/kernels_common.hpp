@@ -59,7 +59,7 @@ struct DeviceMaps {
   const int32_t* e2v;
   const double* xyz;
   const int32_t* elem_face;
-  const uint8_t* elem_pi;      // 8 bytes per element (6 used)
+  const uint8_t* elem_pi;      // 8 bytes per element: frame code per face, byte 6 natural-face bits
   const uint8_t* elem_slot;    // 36 bytes per element
   const int64_t* face_rowbase;
   const int32_t* face_nslots;
@@ -73,6 +73,7 @@ struct DeviceMaps {
   const double* k1_geo;        // RT_1 affine: per-element edge vectors (9)
   const uint8_t* k1_meta;      // RT_1 affine: per-element face data (144 B)
   const double* face_w;        // multiplier weight per face-dof position (K2)
+  const double* tab1d;         // 1D tables [basis][point]: closed values, derivatives, open values
 };
 
 // Sticky device error: the first (code, element) pair wins.

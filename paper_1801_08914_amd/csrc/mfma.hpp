@@ -96,4 +96,119 @@ __device__ __forceinline__ void assemble_mfma(const DeviceMaps& mp, const double
   }
 }
 
+// Local index (interior dofs first, then faces) of the component-d basis
+// function whose 1D factors along axes 0, 1, 2 have indices a0, a1, a2 (the
+// closed index along axis d, the open ones along the two other axes in
+// increasing order).
+template <int K>
+__device__ __forceinline__ int dof_index(int d, int a0, int a1, int a2) {
+  using R = RT<K>;
+  const int ic = d == 0 ? a0 : (d == 1 ? a1 : a2);
+  const int j0 = d == 0 ? a1 : a0, j1 = d == 2 ? a1 : a2;
+  if (ic >= 1 && ic <= K) return d * K * R::K2 + (j1 * R::K1 + j0) * K + (ic - 1);
+  return R::ni + (2 * d + (ic == 0 ? 0 : 1)) * R::K2 + j0 + R::K1 * j1;
+}
+
+// LDS doubles used by assemble_sumfact: the axis-0 and axis-1 partial sums of
+// both terms.
+template <int K>
+constexpr int sumfact_stage() {
+  constexpr int KC = K + 2, K1 = K + 1, q1 = K + 2;
+  return 2 * (KC * KC * q1 * q1 + KC * KC * K1 * K1 * q1);
+}
+
+// Element matrix M_T by sum factorization (k >= 1, any trilinear element).
+// The basis is a tensor product (per component d: the closed Lagrange factor
+// along axis d, open ones along the other two) and the Gauss rule is a
+// tensor rule, so block (d, e) of M_T,
+//   sum_q G_de(q) prod_x A_x[a_x][q_x] B_x[b_x][q_x]
+//     + w_div(q) prod_x A'_x[a_x][q_x] B'_x[b_x][q_x],
+// (A, B: the 1D factors of components d and e, A', B' those of the
+// divergences: derivatives of the closed factor on the own axis) is summed
+// one axis at a time: over the points along axis 0 into S1[a0][b0][q1][q2],
+// along axis 1 into S2[a0][b0][a1][b1][q2], along axis 2 into the entries.
+// The per-point weights come from element_qd (qd: 6 metric weights
+// w alpha (J^T J)_de / det J, the div-div weight w beta / det J).  Team-wide,
+// three barriers per block of components; store(i, j, v) receives every
+// entry with j <= i < n once.  stage: sumfact_stage<K>() doubles of LDS.
+template <int K, int TEAM, class Store>
+__device__ __forceinline__ void assemble_sumfact(const DeviceMaps& mp, const double* qd, double* stage, int lane,
+                                                 Store store) {
+  constexpr int KC = K + 2, K1 = K + 1, q1 = K + 2, QD = 10;
+  static_assert(K >= 1, "sum factorization for k >= 1");
+  const double* Lc = mp.tab1d;          // [KC][q1]
+  const double* Dc = Lc + KC * q1;      // [KC][q1]
+  const double* Lo = Dc + KC * q1;      // [K1][q1]
+  double* S1 = stage;                                  // [2][a0][b0][q1][q2]
+  double* S2 = stage + 2 * KC * KC * q1 * q1;          // [2][a0][b0][a1][b1][q2]
+  constexpr int S1P = KC * KC * q1 * q1, S2P = KC * KC * K1 * K1 * q1;
+  for (int d = 0; d < 3; ++d) {
+    for (int e = d; e < 3; ++e) {
+      const int gi = gidx(d, e);
+      // 1D factor of the own (x == c) or another axis; part 1: divergence
+      auto fac = [&](int c, int part, int x, int a, int q) {
+        return x == c ? (part ? Dc[a * q1 + q] : Lc[a * q1 + q]) : Lo[a * q1 + q];
+      };
+      const int pa0 = d == 0 ? KC : K1, pb0 = e == 0 ? KC : K1;
+      const int pa1 = d == 1 ? KC : K1, pb1 = e == 1 ? KC : K1;
+      const int pa2 = d == 2 ? KC : K1, pb2 = e == 2 ? KC : K1;
+      // axis 0: task (part, q1 q2, a0)
+      const int n1 = 2 * q1 * q1 * pa0;
+      for (int t = lane; t < n1; t += TEAM) {
+        const int part = t / (q1 * q1 * pa0), r = t % (q1 * q1 * pa0), a0 = r % pa0, qq = r / pa0;
+        double aw[q1];
+#pragma unroll
+        for (int q0 = 0; q0 < q1; ++q0)
+          aw[q0] = fac(d, part, 0, a0, q0) * qd[(q0 + q1 * qq) * QD + (part ? 6 : gi)];
+        for (int b0 = 0; b0 < pb0; ++b0) {
+          double s = 0.0;
+#pragma unroll
+          for (int q0 = 0; q0 < q1; ++q0) s += aw[q0] * fac(e, part, 0, b0, q0);
+          S1[part * S1P + (a0 * pb0 + b0) * q1 * q1 + qq] = s;
+        }
+      }
+      __syncthreads();
+      // axis 1: task (part, a0 b0, q2, a1)
+      const int n2 = 2 * pa0 * pb0 * q1 * pa1;
+      for (int t = lane; t < n2; t += TEAM) {
+        const int part = t / (pa0 * pb0 * q1 * pa1), r = t % (pa0 * pb0 * q1 * pa1);
+        const int a1 = r % pa1, q2 = (r / pa1) % q1, ab0 = r / (pa1 * q1);
+        double aw[q1];
+#pragma unroll
+        for (int qy = 0; qy < q1; ++qy)
+          aw[qy] = fac(d, part, 1, a1, qy) * S1[part * S1P + ab0 * q1 * q1 + qy + q1 * q2];
+        for (int b1 = 0; b1 < pb1; ++b1) {
+          double s = 0.0;
+#pragma unroll
+          for (int qy = 0; qy < q1; ++qy) s += aw[qy] * fac(e, part, 1, b1, qy);
+          S2[part * S2P + ((ab0 * pa1 + a1) * pb1 + b1) * q1 + q2] = s;
+        }
+      }
+      __syncthreads();
+      // axis 2: task (a0 b0 a1 b1, a2), both terms into the entries
+      const int n3 = pa0 * pb0 * pa1 * pb1 * pa2;
+      for (int t = lane; t < n3; t += TEAM) {
+        const int a2 = t % pa2, r = t / pa2;
+        const int b1 = r % pb1, a1 = (r / pb1) % pa1, b0 = (r / (pb1 * pa1)) % pb0, a0 = r / (pb1 * pa1 * pb0);
+        double am[q1], ad[q1];
+#pragma unroll
+        for (int qz = 0; qz < q1; ++qz) {
+          am[qz] = fac(d, 0, 2, a2, qz) * S2[r * q1 + qz];
+          ad[qz] = fac(d, 1, 2, a2, qz) * S2[S2P + r * q1 + qz];
+        }
+        const int ia = dof_index<K>(d, a0, a1, a2);
+        for (int b2 = 0; b2 < pb2; ++b2) {
+          const int ib = dof_index<K>(e, b0, b1, b2);
+          if (d == e && ib > ia) continue;
+          double s = 0.0;
+#pragma unroll
+          for (int qz = 0; qz < q1; ++qz) s += am[qz] * fac(e, 0, 2, b2, qz) + ad[qz] * fac(e, 1, 2, b2, qz);
+          if (ia >= ib) store(ia, ib, s); else store(ib, ia, s);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace hyb

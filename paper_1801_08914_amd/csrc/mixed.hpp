@@ -1,92 +1,252 @@
-// Mixed-precision form of the element kernels.  The element matrix M_T is
-// assembled in FP64 (as in the plain form); its Cholesky factor is computed
-// in FP32 after an exact power-of-two diagonal scaling S (S M_T S has its
-// diagonal in [0.5, 2)).  X = M_T^{-1} C_T^T (the columns that give H_T) and
-// y = M_T^{-1} f_hat are solved with the FP32 factor and refined: each sweep
-// forms the residual against the FP64 M_T in FP64, solves for the correction
-// in FP32 and adds it in FP64 (a fixed number of sweeps, or while the
-// correction keeps shrinking).  H_T = C_T X (symmetrized), its scatter into
-// H, r_T = C_T y and the recovery u_T = y - X lambda_T are FP64.
+// Mixed-precision form of the element kernels (precision = HYB_MIXED).
 //
-// Element record (offsets in doubles): X (n x nb, column-major, FP64), M_T
-// (packed lower, FP64, essential rows and columns replaced by the identity),
-// the FP32 factor of S M_T S (packed lower, two per double) and S (n).
+// The element matrix M_T is assembled in FP64 (as in the plain form) and
+// kept for the refinement residuals.  Its Cholesky factor is computed in FP32
+// on the matrix cores after an exact power-of-two diagonal scaling S (S M_T S
+// has its diagonal in [0.5, 2)): panels of 16 columns, the trailing lower
+// tiles by v_mfma_f32_16x16x4f32.  X = M_T^{-1} C_T^T (the columns that give
+// H_T, Sec. 3.1) and y = M_T^{-1} f_hat are then solved with the FP32 factor
+// and refined: every sweep forms the residual B - M_T X on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64), solves for the correction in FP32 and adds
+// it in FP64.  The triangular solves run by column tiles of 16, one wave per
+// tile and no block barrier: each block of 16 rows is updated by the solved
+// blocks on the matrix cores and multiplied by the inverse of its diagonal
+// block (inverted once per factorization).  An element whose FP32 factor
+// breaks down, or whose refinement fails the backward-error test, is solved
+// in FP64 instead (its FP64 Cholesky and the same tile solves on the FP64
+// matrix cores) and counted.  H_T = C_T X (symmetrized), its scatter into H,
+// r_T = C_T y and the recovery u_T = y - X lambda_T are FP64.
+//
+// Element record: X only (n x nb, column-major, FP64): a right-hand side
+// alone re-assembles M_T from the coefficients and re-derives the FP32
+// factor, so the record is no larger than the FP64 form's (smaller for
+// k = 3).  For k = 3 the FP64 element matrix (231 KB) and the FP32 work
+// columns stay in a per-workgroup scratch slot in HBM (L2-resident while the
+// element is processed); the FP32 factor is in LDS for every order.
 #pragma once
 
 #include "setup_generic.hpp"
 
 namespace hyb {
 
-template <int K>
-struct MixedRec {
-  using R = RT<K>;
-  static constexpr int64_t x = 0;
-  static constexpr int64_t m64 = int64_t(R::n) * R::nb;
-  static constexpr int64_t l32 = m64 + R::npk;
-  static constexpr int64_t sc = l32 + (R::npk + 1) / 2;
-  static constexpr int64_t len = sc + R::n;
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+// 16 x 16 x 4 matrix-core step D = A B + C on one wave for FP32 and FP64:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element r of
+// lane l's result is D[row(l, r)][l % 16] (both layouts measured on the
+// device: FP32 rows 4 (l / 16) + r, FP64 rows l / 16 + 4 r).
+template <class T>
+struct MfmaT;
+template <>
+struct MfmaT<float> {
+  using v4 = fx4;
+  __device__ static v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct MfmaT<double> {
+  using v4 = dx4;
+  __device__ static v4 op(double a, double b, v4 c) { return mfma16x16x4(a, b, c); }
+  __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
-// Per-element LDS (doubles).  From k = 3 on, M_T and X stay in the element's
-// HBM record (L2-resident while the element is processed) and the FP32 solves
-// run over chunks of CH columns.  X's column stride in LDS is odd, so that
-// lanes on consecutive columns hit different banks.
-template <int K, int TEAM, int EPB>
-struct MixedLayout {
-  using R = RT<K>;
-  static constexpr bool kGlobal = K >= 3;
-  static constexpr int CH = K >= 3 ? 16 : R::nb;
-  static constexpr int XS = kGlobal ? R::n : (R::n | 1);
-  static constexpr int l32 = (R::npk + 1) / 2;
-  static constexpr int w32 = (R::n * CH + 1) / 2;
-  static constexpr int d32 = (R::n + 1) / 2;
-  // the assembly stages its tables in W (free until the solves): QC points
-  static constexpr int QC = (2 * w32) / (4 * R::n) >= 1 ? (2 * w32) / (4 * R::n) : 1;
-  static constexpr int per = l32 + w32 + d32 + (kGlobal ? 0 : R::npk + XS * R::nb) + R::Q * 10 + 3 * R::n + 24 + 10;
-  static_assert(2 * R::n * QC <= w32, "assembly staging fits in W");
-  static_assert(!kGlobal || EPB == 1, "an HBM-resident element matrix needs one element per block");
-  static_assert(R::nb % CH == 0, "whole column chunks");
-};
-
-// Inverse of pk in FP32 arithmetic (exact after the correction steps for the
-// packed sizes here, t < 2^24).
-__device__ __forceinline__ void unpk_f(int t, int& i, int& j) {
-  int r = int((sqrtf(8.0f * float(t) + 1.0f) - 1.0f) * 0.5f);
-  while (r * (r + 1) / 2 > t) --r;
-  while ((r + 1) * (r + 2) / 2 <= t) ++r;
-  i = r;
-  j = t - r * (r + 1) / 2;
+// Makes the wave's earlier LDS and global stores visible to its later loads
+// (other lanes of the same wave) without a block barrier: work that one wave
+// owns.  Workgroup-scope fences wait for the stores to complete.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// W (N x NC, row-major, FP32) := (L L^T)^{-1} W with the packed FP32 factor
-// L and the reciprocals dinv of its diagonal; one barrier per column in each
-// direction.  Expects W complete on entry, ends with a barrier.  A team with
-// active false only takes part in the barriers.
-template <int N, int TEAM, int NC>
-__device__ __forceinline__ void chol_solve32(const float* L, const float* dinv, float* W, int lane,
-                                             bool active = true) {
-  const int l0 = active ? lane : (1 << 30);
-  for (int c = 0; c < N; ++c) {
-    const float rc = dinv[c];
-    for (int t = l0; t < (N - c - 1) * NC; t += TEAM) {
-      const int i = c + 1 + t / NC, col = t % NC;
-      W[i * NC + col] -= L[pk(i, c)] * (W[c * NC + col] * rc);
+// Packed lower Cholesky factorization in place in LDS (teams of whole waves)
+// by panels of 16 columns: the diagonal block on one wave (registers and wave
+// broadcasts), the rows below it one per lane, the trailing lower 16 x 16
+// tiles on the matrix cores of T.  With active false the team only takes
+// part in the barriers.  Returns true in every lane of the team when a pivot
+// was not positive (replaced by 1); flag: one int of team LDS.
+template <class T, int N, int TEAM>
+__device__ __forceinline__ bool chol_mfma_t(T* A, int lane, bool active, int* flag) {
+  using M = MfmaT<T>;
+  constexpr int NB = 16, NT = (N + 15) / 16, NW = TEAM / 64;
+  static_assert(TEAM % 64 == 0, "whole waves per team");
+  const int w_id = lane / 64, l = lane % 64, li = l % 16, lc = l / 16;
+  __syncthreads();
+  if (lane == 0) *flag = 0;
+  bool bad = false;
+  for (int c0 = 0; c0 < N; c0 += NB) {
+    const int w = N - c0 < NB ? N - c0 : NB;
+    if (active && w_id == 0) bad |= chol_diag16(A, c0, w, l);
+    __syncthreads();
+    if (active) chol_panel_rows<T, N, TEAM>(A, c0, w, lane);
+    __syncthreads();
+    const int T0 = (c0 + w + 15) / 16, m = NT - T0;
+    for (int t = active ? w_id : (1 << 30); t < m * (m + 1) / 2; t += NW) {
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      const int J = T0 + (t - I * (I + 1) / 2);
+      I += T0;
+      typename M::v4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + M::row(l, r), j = 16 * J + li;
+        acc[r] = (i < N && j <= i) ? A[pk(i, j)] : T(0);
+      }
+      const int ia = 16 * I + li, jb = 16 * J + li;
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk) {
+        const int q = 4 * kk + lc;
+        const T av = (ia < N && q < w) ? -A[pk(ia, c0 + q)] : T(0);
+        const T bv = (jb < N && q < w) ? A[pk(jb, c0 + q)] : T(0);
+        acc = M::op(av, bv, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + M::row(l, r), j = 16 * J + li;
+        if (i < N && j <= i) A[pk(i, j)] = acc[r];
+      }
     }
     __syncthreads();
-    // row c is not touched by later forward steps
-    for (int col = l0; col < NC; col += TEAM) W[c * NC + col] *= rc;
   }
+  if (active && lane == 0 && bad) *flag = 1;
   __syncthreads();
-  for (int c = N - 1; c >= 0; --c) {
-    const float rc = dinv[c];
-    for (int t = l0; t < c * NC; t += TEAM) {
-      const int i = t / NC, col = t % NC;
-      W[i * NC + col] -= L[pk(c, i)] * (W[c * NC + col] * rc);
+  const bool out = *flag != 0;
+  __syncthreads();
+  return out;
+}
+
+// Inverses of the 16 x 16 diagonal blocks of a lower factor L (lower
+// triangular, the identity past N), one block per wave in turn and a lane
+// per column (forward substitution, x_i = (delta_ij - sum_k L_ik x_k) / L_ii):
+// Linv[256 I + 16 i + j].  L(i, j) reads the factor for j <= i < N.
+template <class T, int N, int TEAM, class LAcc>
+__device__ __forceinline__ void diag_inverses(LAcc L, T* Linv, int lane, bool active) {
+  constexpr int NT = (N + 15) / 16, NW = TEAM / 64;
+  const int w_id = lane / 64, j = lane % 64;
+  if (!active || j >= 16) return;
+  for (int I = w_id; I < NT; I += NW) {
+    const int c0 = 16 * I;
+    T x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      T s = i == j ? T(1) : T(0);
+      if (c0 + i < N) {
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+          if (k >= j) s -= L(c0 + i, c0 + k) * x[k];
+        x[i] = i >= j ? s / L(c0 + i, c0 + i) : T(0);
+      } else {
+        x[i] = s;
+      }
     }
-    __syncthreads();
-    for (int col = l0; col < NC; col += TEAM) W[c * NC + col] *= rc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Linv[256 * I + 16 * i + j] = x[i];
   }
-  __syncthreads();
+}
+
+// W := (L L^T)^{-1} W (BACK) or L^{-1} W on one column tile (columns c0 ..
+// c0 + ncol - 1 of W, ncol <= 16) by one wave: forward, then backward
+// substitution by blocks of 16 rows; every block is first updated by the
+// blocks already solved (on the matrix cores of T) and then multiplied by
+// the inverse of its diagonal block.  Only this wave touches these columns of
+// W (LDS or global), so wave-level ordering suffices.  L(i, j): the factor,
+// j <= i < N.
+template <class T, int N, bool BACK = true, class LAcc, class WAcc>
+__device__ __forceinline__ void tile_solve(LAcc L, const T* Linv, WAcc W, int c0, int ncol, int l) {
+  using M = MfmaT<T>;
+  using v4 = typename M::v4;
+  constexpr int NT = (N + 15) / 16;
+  const int li = l & 15, lk = l >> 4;
+  const int c = c0 + li;
+  const bool cok = li < ncol;
+  auto ld = [&](int i) -> T { return (cok && i < N) ? static_cast<T>(W(i, c)) : T(0); };
+  auto st = [&](int I, v4 v) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + M::row(l, r);
+      if (cok && i < N) W(i, c) = v[r];
+    }
+  };
+  for (int I = 0; I < NT; ++I) {
+    v4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = ld(16 * I + M::row(l, r));
+    const int i = 16 * I + li;
+    for (int J = 0; J < I; ++J) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int q = 16 * J + 4 * s + lk;
+        acc = M::op(i < N ? -L(i, q) : T(0), ld(q), acc);
+      }
+    }
+    st(I, acc);
+    wave_sync();
+    v4 x = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x = M::op(Linv[256 * I + 16 * li + 4 * s + lk], ld(16 * I + 4 * s + lk), x);
+    wave_sync();
+    st(I, x);
+    wave_sync();
+  }
+  if constexpr (!BACK) return;
+  for (int I = NT - 1; I >= 0; --I) {
+    v4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = ld(16 * I + M::row(l, r));
+    const int j = 16 * I + li;
+    for (int K = I + 1; K < NT; ++K) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int q = 16 * K + 4 * s + lk;
+        acc = M::op(q < N ? -L(q, j) : T(0), ld(q), acc);
+      }
+    }
+    st(I, acc);
+    wave_sync();
+    v4 x = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x = M::op(Linv[256 * I + 16 * (4 * s + lk) + li], ld(16 * I + 4 * s + lk), x);
+    wave_sync();
+    st(I, x);
+    wave_sync();
+  }
+}
+
+// R = B - M X (FP64) on the output tiles (16 rows x 16 columns) dealt to the
+// team's waves; out(i, c, R) receives every entry i < N, c < ncol.  Returns
+// the lane's largest |R|.  Mf(i, j): the symmetric FP64 matrix, any i, j < N.
+template <int N, int TEAM, class MAcc, class XAcc, class BFn, class Out>
+__device__ __forceinline__ double residual_tiles(MAcc Mf, XAcc X, BFn B, Out out, int ncol, int lane) {
+  using M = MfmaT<double>;
+  constexpr int NT = (N + 15) / 16, NW = TEAM / 64;
+  const int w_id = lane / 64, l = lane % 64, li = l & 15, lk = l >> 4;
+  const int CT = (ncol + 15) / 16;
+  double rm = 0.0;
+  for (int t = w_id; t < NT * CT; t += NW) {
+    const int I = t / CT, c = 16 * (t % CT) + li;
+    const bool cok = c < ncol;
+    const int ia = 16 * I + li;
+    dx4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int J = 0; J < NT; ++J) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int q = 16 * J + 4 * s + lk;
+        const double a = (ia < N && q < N) ? Mf(ia, q) : 0.0;
+        const double b = (cok && q < N) ? static_cast<double>(X(q, c)) : 0.0;
+        acc = M::op(a, b, acc);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + M::row(l, r);
+      if (cok && i < N) {
+        const double R = B(i, c) - acc[r];
+        rm = fmax(rm, fabs(R));
+        out(i, c, R);
+      }
+    }
+  }
+  return rm;
 }
 
 // Sweep control of the refinement.  sweeps >= 0: exactly that many sweeps
@@ -97,7 +257,7 @@ __device__ __forceinline__ void chol_solve32(const float* L, const float* dinv, 
 // sweeps; the result is accepted if the FP64 residual then passes the
 // backward-error test ||b - M x||_inf <= sqrt(n) 2^-53 ||M||_inf ||x||_inf
 // (the test of LAPACK's mixed-precision Cholesky solver), otherwise the
-// element is reported (kappa(S M_T S) 2^-24 near 1), not hidden.
+// element is solved in FP64.
 constexpr int kRefineMax = 30;
 
 // Team-wide maximum of non-negative doubles through their bit patterns
@@ -126,55 +286,54 @@ __device__ __forceinline__ double norm_inf(MRow mrow, double* red, int lane) {
   return out;
 }
 
-// Solve M X = B for NC columns with the FP32 factor and FP64 refinement:
-// sweep 0 solves for B, every later sweep for the residual B - M X (FP64,
-// from mrow), the correction added in FP64.  bcol(i, c) and xel(i, c) give
-// B and X for local column c; anrm = ||M||_inf; red holds 8 doubles of team
-// scratch (two slots of max |residual|, max |x|, max |correction|).  Returns
-// false when an adaptive refinement did not pass the backward-error test.
-template <int N, int TEAM, int NC, class MRow, class BCol, class XEl>
-__device__ __forceinline__ bool refine_solve(const float* L, const float* dinv, float* W, const double* Sv,
-                                             MRow mrow, BCol bcol, XEl xel, int sweeps, double anrm, double* red,
-                                             int lane) {
+// M X = B for ncol columns with the FP32 factor (L, diagonal-block inverses
+// Li) and FP64 refinement: the first solve for S B, every later sweep for
+// the residual B - M X (FP64 matrix cores), its correction added in FP64.
+// W: FP32 work columns (same shape as X).  red: 8 doubles of team scratch.
+// Returns false when an adaptive refinement fails the backward-error test.
+// A team with active false takes part in the barriers only; the block leaves
+// the sweep loop together (barriers stay paired across the teams of a block).
+template <int N, int TEAM, class LAcc, class WAcc, class XAcc, class BFn, class MAcc>
+__device__ __forceinline__ bool refine_cols(LAcc L, const float* Li, WAcc W, XAcc X, BFn B, MAcc Mf,
+                                            const double* Sv, int ncol, int sweeps, double anrm, double* red,
+                                            int lane, bool active) {
+  constexpr int NW = TEAM / 64;
+  const int w_id = lane / 64, l = lane % 64;
+  const int CT = (ncol + 15) / 16;
   const bool adaptive = sweeps < 0;
   const int cap = adaptive ? kRefineMax : sweeps;
   const double tol = sqrt(double(N)) * 0x1p-53 * anrm;
+  const int tot = active ? N * ncol : 0;
   __syncthreads();  // the team is done with red and W
   if (lane < 8) red[lane] = 0.0;
-  for (int t = lane; t < N * NC; t += TEAM) {
-    const int i = t / NC, c = t % NC;
-    W[i * NC + c] = float(Sv[i] * bcol(i, c));
+  for (int t = lane; t < tot; t += TEAM) {
+    const int i = t / ncol, c = t % ncol;
+    W(i, c) = float(Sv[i] * B(i, c));
   }
   __syncthreads();
-  chol_solve32<N, TEAM, NC>(L, dinv, W, lane);
+  for (int ct = active ? w_id : CT; ct < CT; ct += NW)
+    tile_solve<float, N>(L, Li, W, 16 * ct, ncol - 16 * ct < 16 ? ncol - 16 * ct : 16, l);
+  __syncthreads();
   double xm = 0.0, zm = 0.0, zprev = 0.0;
-  for (int t = lane; t < N * NC; t += TEAM) {
-    const int i = t / NC, c = t % NC;
-    const double x = Sv[i] * double(W[i * NC + c]);
-    xel(i, c) = x;
+  for (int t = lane; t < tot; t += TEAM) {
+    const int i = t / ncol, c = t % ncol;
+    const double x = Sv[i] * double(W(i, c));
+    X(i, c) = x;
     xm = fmax(xm, fabs(x));
   }
-  // A team whose refinement has ended keeps taking part in the block's
-  // barriers (its work masked off) until every team of the block is done:
-  // the block leaves the loop together, so barriers stay paired across teams
-  // (in a persistent batch block the teams go on to other work items, whose
-  // LDS layout may differ).
-  bool done = false, result = true;
+  bool done = !active || (!adaptive && cap == 0), result = true;
   for (int sw = 1;; ++sw) {
+    if (!__syncthreads_or(done ? 0 : 1)) return result;
     double* slot = red + 4 * (sw & 1);
     if (adaptive && !done) {
       team_max(slot + 1, xm);
       team_max(slot + 2, zm);
     }
-    __syncthreads();  // x complete
+    __syncthreads();  // X complete
     double rm = 0.0;
-    for (int t = done ? N * NC : lane; t < N * NC; t += TEAM) {
-      const int i = t / NC, c = t % NC;
-      double res = bcol(i, c);
-      for (int j = 0; j < N; ++j) res -= mrow(i, j) * xel(j, c);
-      rm = fmax(rm, fabs(res));
-      W[i * NC + c] = float(Sv[i] * res);
-    }
+    if (!done)
+      rm = residual_tiles<N, TEAM>(Mf, X, B, [&](int i, int c, double R) { W(i, c) = float(Sv[i] * R); }, ncol,
+                                   lane);
     if (adaptive && !done) team_max(slot, rm);
     __syncthreads();
     // every lane has read the other slot in the previous sweep
@@ -188,56 +347,115 @@ __device__ __forceinline__ bool refine_solve(const float* L, const float* dinv, 
           result = backward_ok;
         }
         zprev = slot[2];
-      } else if (sw > cap) {
-        done = true;
+      } else if (sw >= cap) {
+        done = true;   // the last correction below is still applied
       }
     }
-    if (!__syncthreads_or(done ? 0 : 1)) return result;
-    chol_solve32<N, TEAM, NC>(L, dinv, W, lane, !done);
+    const bool solve_now = !done || (!adaptive && sw == cap);
+    if (!__syncthreads_or(solve_now ? 1 : 0)) return result;
+    for (int ct = solve_now ? w_id : CT; ct < CT; ct += NW)
+      tile_solve<float, N>(L, Li, W, 16 * ct, ncol - 16 * ct < 16 ? ncol - 16 * ct : 16, l);
+    __syncthreads();
     xm = zm = 0.0;
-    for (int t = done ? N * NC : lane; t < N * NC; t += TEAM) {
-      const int i = t / NC, c = t % NC;
-      const double z = Sv[i] * double(W[i * NC + c]);
-      const double x = xel(i, c) + z;
-      xel(i, c) = x;
+    for (int t = solve_now ? lane : tot; t < tot; t += TEAM) {
+      const int i = t / ncol, c = t % ncol;
+      const double z = Sv[i] * double(W(i, c));
+      const double x = X(i, c) + z;
+      X(i, c) = x;
       xm = fmax(xm, fabs(x));
       zm = fmax(zm, fabs(z));
     }
   }
 }
 
+template <int K>
+struct MixedRec {
+  using R = RT<K>;
+  static constexpr int64_t x = 0;                        // X, n x nb column-major
+  static constexpr int64_t len = int64_t(R::n) * R::nb;
+};
+
+// Per-element LDS (doubles) and, for k = 3, the per-workgroup HBM scratch
+// slot.  Regions: M64 (packed FP64 element matrix; k = 3: in the slot), X64
+// (n x nb row-major FP64; k = 3: the record), FW (the packed FP32 factor,
+// then the FP32 work columns; the FP64 fallback factor over both; the
+// assembly's staging tables before the factor), Li (inverses of the FP32
+// factor's diagonal blocks; the FP64 ones where M64 cannot hold them),
+// per-point terms, f_hat, S, y, corners, reduction slots.
 template <int K, int TEAM, int EPB>
-__device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* smem, int64_t blk, int sweeps) {
+struct MixedLayout {
+  using R = RT<K>;
+  static constexpr int n = R::n, nb = R::nb, NT = (n + 15) / 16;
+  static constexpr bool kGlobal = K >= 3;
+  static constexpr int l32 = (R::npk + 1) / 2;            // packed FP32 factor
+  static constexpr int w32 = (n * nb + 1) / 2;            // FP32 work columns
+  static constexpr int fw_min = kGlobal ? l32 : (l32 + w32 > R::npk ? l32 + w32 : R::npk);
+  static constexpr int QC = kGlobal ? kAsmQC : (fw_min / (2 * n) < kAsmQC ? fw_min / (2 * n) : kAsmQC);
+  static constexpr int fw = fw_min > 2 * n * QC ? fw_min : 2 * n * QC;
+  // FP64 inverses of the diagonal blocks: in M64 (k <= 2, when they fit), in
+  // FW after the HBM Cholesky's panel (k = 3), else in Li
+  static constexpr int li64 = NT * 256;
+  static constexpr bool li64_in_m = !kGlobal && li64 <= R::npk;
+  static constexpr int hbm_panel = 32 * (n | 1);
+  static constexpr int li = (kGlobal || li64_in_m) ? NT * 128 : li64;
+  static constexpr int m64 = kGlobal ? 0 : R::npk;
+  static constexpr int x64 = kGlobal ? 0 : n * nb;
+  static constexpr int per = m64 + x64 + fw + li + R::Q * 10 + 3 * n + 24 + 16;
+  // HBM scratch per workgroup (k = 3): M64 and the FP32 work columns
+  static constexpr int64_t slot = kGlobal ? int64_t(R::npk) + w32 : 0;
+  static_assert(!kGlobal || fw >= hbm_panel + li64, "the HBM Cholesky's panel and FP64 block inverses fit in FW");
+  static_assert(kGlobal || fw >= R::npk, "the FP64 fallback factor fits in FW");
+  static_assert(!kGlobal || EPB == 1, "a scratch slot per element in flight: one element per block");
+  static_assert(QC >= 1, "assembly staging");
+};
+
+// Workgroups of the k = 3 persistent launch (one scratch slot each).
+constexpr int kMixedSlots = 512;
+
+// The mixed element routine: setup (MODE_MATRIX: M_T, the FP32 factor, X,
+// H_T into H) and/or right-hand side (MODE_RHS: f_hat, y, r_T into r; alone,
+// M_T and the FP32 factor are derived again from the coefficients).  scratch:
+// the workgroup's HBM slot (k = 3), fallbacks: counter of elements solved in
+// FP64.
+template <int K, int TEAM, int EPB>
+__device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* smem, int64_t blk, int sweeps,
+                                                 double* scratch) {
   using R = RT<K>;
   using Lay = MixedLayout<K, TEAM, EPB>;
   using Rec = MixedRec<K>;
-  constexpr int n = R::n, ni = R::ni, nb = R::nb, K1 = R::K1, K2 = R::K2, Q = R::Q, QD = 10;
-  constexpr int CH = Lay::CH, XS = Lay::XS;
+  constexpr int n = R::n, ni = R::ni, nb = R::nb, K1 = R::K1, K2 = R::K2, Q = R::Q, QD = 10, NT = Lay::NT;
   const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  const int w_id = lane / 64, l = lane % 64;
+  constexpr int NW = TEAM / 64;
   const int64_t e = blk * EPB + team;
   const bool live = e < a.ne;
   const int64_t es = live ? e : 0;  // safe index for loads of padding teams
   const bool matrix = (a.mode & MODE_MATRIX) != 0, rhs = (a.mode & MODE_RHS) != 0;
   double* rec = a.factor + es * Rec::len;
   double* base = smem + team * Lay::per;
-  float* L = reinterpret_cast<float*>(base);
-  float* W = reinterpret_cast<float*>(base + Lay::l32);
-  float* dinv = reinterpret_cast<float*>(base + Lay::l32 + Lay::w32);
-  double* rest = base + Lay::l32 + Lay::w32 + Lay::d32;
-  double* Ml = rest;
-  double* Xl = rest + (Lay::kGlobal ? 0 : R::npk);
-  double* qd = Xl + (Lay::kGlobal ? 0 : XS * nb);
+  double* M64 = Lay::kGlobal ? scratch : base;
+  double* X64 = Lay::kGlobal ? nullptr : base + Lay::m64;
+  double* FW = base + Lay::m64 + Lay::x64;
+  float* L32 = reinterpret_cast<float*>(FW);
+  float* W32 = Lay::kGlobal ? reinterpret_cast<float*>(scratch + R::npk) : L32 + 2 * Lay::l32;
+  double* Li = FW + Lay::fw;
+  float* Li32 = reinterpret_cast<float*>(Li);
+  double* qd = Li + Lay::li;
   double* fh = qd + Q * QD;
-  double* yv = fh + n;
-  double* Sv = yv + n;
-  double* xe = Sv + n;
+  double* Sv = fh + n;
+  double* yv = Sv + n;
+  double* xe = yv + n;
   double* red = xe + 24;
-  // the FP64 matrix: in LDS while a setup assembles it (k <= 2), else the record's
-  double* M = (matrix && !Lay::kGlobal) ? Ml : rec + Rec::m64;
-  double* X = Lay::kGlobal ? rec + Rec::x : Xl;
-  auto Mrow = [&](int i, int j) { return i >= j ? M[pk(i, j)] : M[pk(j, i)]; };
-  auto Xe = [&](int i, int b) -> double& { return X[b * XS + i]; };
+  int* flag = reinterpret_cast<int*>(red + 12);
   const DeviceMaps& mp = a.mp;
+
+  auto Mrow = [&](int i, int j) { return i >= j ? M64[pk(i, j)] : M64[pk(j, i)]; };
+  auto L32a = [&](int i, int j) -> float { return L32[pk(i, j)]; };
+  // X: n x nb, row-major in LDS (k <= 2) or the record's column-major array
+  auto Xe = [&](int i, int c) -> double& { return Lay::kGlobal ? rec[int64_t(c) * n + i] : X64[i * nb + c]; };
+  auto Wx = [&](int i, int c) -> float& { return W32[i * nb + c]; };
+  auto Wy = [&](int i, int) -> float& { return W32[i]; };
+  auto Y = [&](int i, int) -> double& { return yv[i]; };
 
   int fid[6], pic[6];
 #pragma unroll
@@ -245,151 +463,161 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
     fid[f] = mp.elem_face[es * 6 + f];
     pic[f] = mp.elem_pi[es * 8 + f];
   }
-  auto is_ess = [&](int i) { return i >= ni && fid[(i - ni) / K2] < 0; };
+  // essential dofs: those of boundary faces not marked natural
+  const int nat = mp.elem_pi[es * 8 + 6];
+  auto is_ess = [&](int i) {
+    const int f = (i - ni) / K2;
+    return i >= ni && fid[f] < 0 && !((nat >> f) & 1);
+  };
   // sign of face dof b in C_T: +1 on the max side of an axis, -1 on the min side
   auto eps = [&](int b) { return ((b / K2) & 1) ? 1.0 : -1.0; };
-  double anrm = 0.0;  // ||M_T||_inf (masked), for the refinement's stopping test
+  auto Bx = [&](int i, int c) { return i == ni + c ? eps(c) : 0.0; };
+  auto By = [&](int i, int) { return fh[i]; };
 
   const double al = a.alpha ? a.alpha[es] : 0.0, be = a.beta ? a.beta[es] : 0.0;
   double fv[3] = {0.0, 0.0, 0.0};
   if (rhs) {
     fv[0] = a.f[es * 3 + 0]; fv[1] = a.f[es * 3 + 1]; fv[2] = a.f[es * 3 + 2];
   }
-  const bool need_matrix = matrix || (rhs && a.g);
-  element_qd<K, TEAM>(mp, es, al, be, fv, need_matrix, rhs, xe, qd, lane, live, a.status, e);
+  element_qd<K, TEAM>(mp, es, al, be, fv, true, rhs, xe, qd, lane, live, a.status, e);
 
-  if (matrix) {
-    if constexpr (TEAM % 64 == 0) {
-      assemble_mfma<K, TEAM, Lay::QC>(mp, qd, reinterpret_cast<double*>(W), lane,
-                                      [&](int i, int j, double v) { M[pk(i, j)] = v; });
-    } else {
-      for (int p = lane; p < R::npk; p += TEAM) {
-        int i, j;
-        unpk_f(p, i, j);
-        M[p] = m_entry<K>(mp, qd, i, j);
-      }
-    }
-    __syncthreads();
+  // M_T (FP64, packed lower): by sum factorization (k >= 1), on the matrix
+  // cores for k = 0; the partial sums or tables staged in FW
+  if constexpr (K >= 1) {
+    static_assert(Lay::fw >= sumfact_stage<K>(), "the sum factorization's partial sums fit in FW");
+    assemble_sumfact<K, TEAM>(mp, qd, FW, lane, [&](int i, int j, double v) { M64[pk(i, j)] = v; });
   } else {
-    // right-hand side only: the stored factor and scaling
-    const float* Lr = reinterpret_cast<const float*>(rec + Rec::l32);
-    for (int p = lane; p < R::npk; p += TEAM) L[p] = Lr[p];
-    for (int i = lane; i < n; i += TEAM) Sv[i] = rec[Rec::sc + i];
-    __syncthreads();
-    for (int c = lane; c < n; c += TEAM) dinv[c] = 1.0f / L[pk(c, c)];
-    __syncthreads();
+    assemble_mfma<K, TEAM, Lay::QC>(mp, qd, FW, lane, [&](int i, int j, double v) { M64[pk(i, j)] = v; });
   }
+  __syncthreads();
   if (rhs) {
     // f_hat, with f_r -= M_re g_e from the unmasked matrix
     for (int i = lane; i < n; i += TEAM) {
       const int d = R::comp(i);
       double s = 0.0;
+#pragma unroll 8
       for (int q = 0; q < Q; ++q) s += mp.tab_s[q * n + i] * qd[q * QD + 7 + d];
       if (is_ess(i)) {
         s = a.g ? a.g[es * nb + (i - ni)] : 0.0;
       } else if (a.g) {
         for (int j = ni; j < n; ++j)
-          if (is_ess(j)) s -= (matrix ? Mrow(i, j) : (i > j ? m_entry<K>(mp, qd, i, j) : m_entry<K>(mp, qd, j, i))) *
-                              a.g[es * nb + (j - ni)];
+          if (is_ess(j)) s -= Mrow(i, j) * a.g[es * nb + (j - ni)];
       }
       fh[i] = s;
     }
     __syncthreads();
   }
+  // essential rows/columns -> identity; power-of-two scaling; FP32 copy
+  for (int p = lane; p < R::npk; p += TEAM) {
+    int i, j;
+    unpk(p, i, j);
+    if (is_ess(i) || is_ess(j)) M64[p] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int i = lane; i < n; i += TEAM) {
+    int ex;
+    (void)frexp(M64[pk(i, i)], &ex);
+    Sv[i] = ldexp(1.0, -(ex >> 1));
+  }
+  __syncthreads();
+  for (int p = lane; p < R::npk; p += TEAM) {
+    int i, j;
+    unpk(p, i, j);
+    L32[p] = float(Sv[i] * M64[p] * Sv[j]);
+  }
+  const double anrm = norm_inf<n, TEAM>(Mrow, red + 10, lane);
+  // FP32 Cholesky of S M_T S; a breakdown means kappa(S M_T S) 2^-24 >= 1
+  // (or M_T is not SPD): such an element is solved in FP64
+  const bool broke = chol_mfma_t<float, n, TEAM>(L32, lane, true, flag);
+  diag_inverses<float, n, TEAM>(L32a, Li32, lane, !broke);
+  __syncthreads();
 
+  // (every team of the block runs the calls: they hold block barriers)
+  bool ok_y = true, ok_x = true;
+  if (rhs) {
+    const bool r = refine_cols<n, TEAM>(L32a, Li32, Wy, Y, By, Mrow, Sv, 1, sweeps, anrm, red, lane, !broke);
+    ok_y = !broke && r;
+  }
   if (matrix) {
-    // essential rows/columns -> identity; power-of-two scaling; FP32 copy
-    for (int p = lane; p < R::npk; p += TEAM) {
-      int i, j;
-      unpk_f(p, i, j);
-      if (is_ess(i) || is_ess(j)) M[p] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int i = lane; i < n; i += TEAM) {
-      int ex;
-      (void)frexp(M[pk(i, i)], &ex);
-      Sv[i] = ldexp(1.0, -(ex >> 1));
-    }
-    __syncthreads();
-    for (int p = lane; p < R::npk; p += TEAM) {
-      int i, j;
-      unpk_f(p, i, j);
-      L[p] = float(Sv[i] * M[p] * Sv[j]);
-    }
-    __syncthreads();
-    // FP32 Cholesky; a breakdown means kappa(S M_T S) 2^-24 >= 1 (or M_T is
-    // not SPD): the plain FP64 form is the one to use for this element
-    if (chol_packed<float, n, TEAM>(L, lane) && live && lane == 0) report_error(a.status, HYB_E_REFINE, e);
-    for (int c = lane; c < n; c += TEAM) dinv[c] = 1.0f / L[pk(c, c)];
-    __syncthreads();
-
-    // X = M^{-1} C_T^T by chunks of CH columns
-    anrm = norm_inf<n, TEAM>(Mrow, red + 8, lane);
-    bool ok = true;
-    for (int c0 = 0; c0 < nb; c0 += CH) {
-      ok &= refine_solve<n, TEAM, CH>(
-          L, dinv, W, Sv, Mrow, [&](int i, int c) { return (i == ni + c0 + c) ? eps(c0 + c) : 0.0; },
-          [&](int i, int c) -> double& { return Xe(i, c0 + c); }, sweeps, anrm, red, lane);
-    }
-    if (!ok && live && lane == 0) report_error(a.status, HYB_E_REFINE, e);
-
-    // H_T = D (M^{-1})_bb D = D E_b^T X, symmetrized, scattered into H (same-
-    // face blocks receive two element terms by atomic add)
-    if (live) {
-      for (int t = lane; t < R::nbpk; t += TEAM) {
-        int aa, bb;
-        unpk_f(t, aa, bb);
-        const int fa = aa / K2, fb = bb / K2;
-        if (fid[fa] < 0 || fid[fb] < 0) continue;
-        const double v = 0.5 * (eps(aa) * Xe(ni + aa, bb) + eps(bb) * Xe(ni + bb, aa));
-        int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
-        frame_map(pic[fa], K, a0, a1);
-        frame_map(pic[fb], K, b0, b1);
-        const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
-        const int Fa = fid[fa], Fb = fid[fb];
-        const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
-        const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
-                            mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
-        const int64_t pba = mp.face_rowbase[Fb] + int64_t(jb) * mp.face_nslots[Fb] * K2 +
-                            mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
-        if (fa == fb) {
-          atomicAdd(&a.Hval[pab], vw);
-          if (aa != bb) atomicAdd(&a.Hval[pba], vw);
-        } else {
-          a.Hval[pab] = vw;
-          a.Hval[pba] = vw;
-        }
-      }
-    }
+    const bool r = refine_cols<n, TEAM>(L32a, Li32, Wx, Xe, Bx, Mrow, Sv, nb, sweeps, anrm, red, lane, !broke);
+    ok_x = !broke && r;
   }
 
-  if (rhs) {
-    // y = M^{-1} f_hat, refined the same way (one column)
-    if (!matrix) anrm = norm_inf<n, TEAM>(Mrow, red + 8, lane);
-    const bool oky = refine_solve<n, TEAM, 1>(
-        L, dinv, W, Sv, Mrow, [&](int i, int) { return fh[i]; }, [&](int i, int) -> double& { return yv[i]; },
-        sweeps, anrm, red, lane);
-    if (!oky && live && lane == 0) report_error(a.status, HYB_E_REFINE, e);
-    if (live) {
-      for (int i = lane; i < n; i += TEAM) a.y[e * n + i] = yv[i];
-      // r_T = D y_b
-      for (int b = lane; b < nb; b += TEAM) {
-        const int fb = b / K2;
-        if (fid[fb] < 0) continue;
-        int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
-        frame_map(pic[fb], K, b0, b1);
-        atomicAdd(&a.r[int64_t(fid[fb]) * K2 + b0 + K1 * b1], eps(b) * yv[ni + b] * mp.face_w[b0 + K1 * b1]);
-      }
+  // FP64 for what FP32 could not do: Cholesky of M_T (FP64 matrix cores), the
+  // same tile solves in FP64 (block-uniform branch; the other teams of the
+  // block take part in the barriers)
+  const bool fb = !(ok_x && ok_y);
+  if (__syncthreads_or(fb ? 1 : 0)) {
+    double* F = Lay::kGlobal ? M64 : FW;
+    double* Li64 = Lay::kGlobal ? FW + Lay::hbm_panel : (Lay::li64_in_m ? M64 : Li);
+    bool notspd;
+    if constexpr (Lay::kGlobal) {
+      notspd = chol_hbm32<n, TEAM>(F, FW, lane, fb);
+      __syncthreads();
+    } else {
+      for (int p = fb ? lane : R::npk; p < R::npk; p += TEAM) F[p] = M64[p];
+      notspd = chol_mfma_t<double, n, TEAM>(F, lane, fb, flag);
     }
+    if (fb && notspd && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
+    auto Fa = [&](int i, int j) -> double { return F[pk(i, j)]; };
+    diag_inverses<double, n, TEAM>(Fa, Li64, lane, fb);
+    __syncthreads();
+    if (fb && !ok_y) {
+      for (int i = lane; i < n; i += TEAM) yv[i] = fh[i];
+    }
+    if (fb && !ok_x) {
+      for (int t = lane; t < n * nb; t += TEAM) Xe(t / nb, t % nb) = Bx(t / nb, t % nb);
+    }
+    __syncthreads();
+    if (fb && !ok_y && w_id == 0) tile_solve<double, n>(Fa, Li64, Y, 0, 1, l);
+    if (fb && !ok_x) {
+      constexpr int CT = (nb + 15) / 16;
+      for (int ct = w_id; ct < CT; ct += NW) tile_solve<double, n>(Fa, Li64, Xe, 16 * ct, nb - 16 * ct < 16 ? nb - 16 * ct : 16, l);
+    }
+    __syncthreads();
+    if (fb && live && lane == 0) atomicAdd(reinterpret_cast<int*>(a.status) + 2, 1);
   }
 
   if (matrix && live) {
-    float* Lr = reinterpret_cast<float*>(rec + Rec::l32);
-    for (int p = lane; p < R::npk; p += TEAM) Lr[p] = L[p];
-    for (int i = lane; i < n; i += TEAM) rec[Rec::sc + i] = Sv[i];
+    // H_T = D (M^{-1})_bb D = D E_b^T X, symmetrized, scattered into H (same-
+    // face blocks receive two element terms by atomic add)
+    for (int t = lane; t < R::nbpk; t += TEAM) {
+      int aa, bb;
+      unpk(t, aa, bb);
+      const int fa = aa / K2, fb2 = bb / K2;
+      if (fid[fa] < 0 || fid[fb2] < 0) continue;
+      const double v = 0.5 * (eps(aa) * Xe(ni + aa, bb) + eps(bb) * Xe(ni + bb, aa));
+      int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
+      frame_map(pic[fa], K, a0, a1);
+      frame_map(pic[fb2], K, b0, b1);
+      const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
+      const int Fa = fid[fa], Fb = fid[fb2];
+      const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
+      const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
+                          mp.elem_slot[e * 36 + fa * 6 + fb2] * K2 + jb;
+      const int64_t pba = mp.face_rowbase[Fb] + int64_t(jb) * mp.face_nslots[Fb] * K2 +
+                          mp.elem_slot[e * 36 + fb2 * 6 + fa] * K2 + ja;
+      if (fa == fb2) {
+        atomicAdd(&a.Hval[pab], vw);
+        if (aa != bb) atomicAdd(&a.Hval[pba], vw);
+      } else {
+        a.Hval[pab] = vw;
+        a.Hval[pba] = vw;
+      }
+    }
     if constexpr (!Lay::kGlobal) {
-      for (int p = lane; p < R::npk; p += TEAM) rec[Rec::m64 + p] = Ml[p];
-      for (int t = lane; t < n * nb; t += TEAM) rec[Rec::x + t] = Xl[(t / n) * XS + t % n];
+      for (int t = lane; t < n * nb; t += TEAM) rec[t] = X64[(t % n) * nb + t / n];
+    }
+  }
+  if (rhs && live) {
+    for (int i = lane; i < n; i += TEAM) a.y[e * n + i] = yv[i];
+    // r_T = D y_b
+    for (int b = lane; b < nb; b += TEAM) {
+      const int fb2 = b / K2;
+      if (fid[fb2] < 0) continue;
+      int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
+      frame_map(pic[fb2], K, b0, b1);
+      atomicAdd(&a.r[int64_t(fid[fb2]) * K2 + b0 + K1 * b1], eps(b) * yv[ni + b] * mp.face_w[b0 + K1 * b1]);
     }
   }
 }
@@ -397,7 +625,18 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
 template <int K, int TEAM, int EPB>
 __global__ __launch_bounds__(TEAM* EPB) void k_setup_mixed(SetupArgs a, int sweeps) {
   __shared__ double smem[EPB * MixedLayout<K, TEAM, EPB>::per];
-  setup_mixed_body<K, TEAM, EPB>(a, smem, blockIdx.x, sweeps);
+  setup_mixed_body<K, TEAM, EPB>(a, smem, blockIdx.x, sweeps, nullptr);
+}
+
+// k = 3: a persistent grid, workgroup b owning scratch slot b.
+template <int K, int TEAM>
+__global__ __launch_bounds__(TEAM) void k_setup_mixed_slots(SetupArgs a, int sweeps, double* scratch) {
+  __shared__ double smem[MixedLayout<K, TEAM, 1>::per];
+  double* slot = scratch + int64_t(blockIdx.x) * MixedLayout<K, TEAM, 1>::slot;
+  for (int64_t e = blockIdx.x; e < a.ne; e += gridDim.x) {
+    setup_mixed_body<K, TEAM, 1>(a, smem, e, sweeps, slot);
+    __syncthreads();
+  }
 }
 
 // u_T = y - X lambda_T, lambda_T the element's face multipliers in its own

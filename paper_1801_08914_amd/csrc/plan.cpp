@@ -242,6 +242,17 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
       ++nf;
     }
   P.nfaces = nf;
+  // natural boundary faces (Sec. 5: only faces with prescribed normal flux
+  // are eliminated): bit f of byte 6 of the element's frame record
+  P.has_natural = false;
+  if (mesh->ess) {
+    for (int64_t e = 0; e < ne; ++e)
+      for (int f = 0; f < 6; ++f)
+        if (P.elem_face[size_t(6 * e + f)] < 0 && mesh->ess[6 * e + f] == 0) {
+          P.elem_pi[size_t(8 * e + 6)] |= uint8_t(1u << f);
+          P.has_natural = true;
+        }
+  }
   P.m = nf * o.K2;
   if (P.m > (int64_t(1) << 31) - 1) return HYB_E_ARG;
 
@@ -316,6 +327,16 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
     dLc[a] = lagrange_deriv_at(zc, xq[a]);
     Lo[a] = lagrange_at(zo, xq[a]);
   }
+  // 1D tables at the Gauss points, [basis][point]: closed Lagrange values,
+  // their derivatives, open Lagrange values (the factors of the tensor basis)
+  P.tab_1d.assign(size_t((2 * (k + 2) + (k + 1)) * o.q1), 0.0);
+  for (int a = 0; a < o.q1; ++a) {
+    for (int i = 0; i < k + 2; ++i) {
+      P.tab_1d[size_t(i * o.q1 + a)] = Lc[a][size_t(i)];
+      P.tab_1d[size_t(((k + 2) + i) * o.q1 + a)] = dLc[a][size_t(i)];
+    }
+    for (int j = 0; j < k + 1; ++j) P.tab_1d[size_t((2 * (k + 2) + j) * o.q1 + a)] = Lo[a][size_t(j)];
+  }
   // dof -> (d, ic, j0, j1) in local order
   std::vector<std::array<int, 4>> dof;
   for (int d = 0; d < 3; ++d)
@@ -379,6 +400,7 @@ int build_plan(const hyb_mesh* mesh, int k, Plan& P, int64_t& detail) {
   L.tab_w = off;        off = align256(off + sizeof(double) * P.tab_w.size());
   L.tab_ref = off;      off = align256(off + sizeof(double) * P.tab_ref.size());
   L.tab_x = off;        off = align256(off + sizeof(double) * P.tab_x.size());
+  L.tab_1d = off;       off = align256(off + sizeof(double) * P.tab_1d.size());
   L.face_selfslot = off; off = align256(off + sizeof(int32_t) * size_t(nf));
   L.face_owner = off;   off = align256(off + sizeof(int32_t) * size_t(nf));
   // per-element inputs of the RT_1 affine kernels (mesh data only)

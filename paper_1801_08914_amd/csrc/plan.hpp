@@ -44,7 +44,7 @@ static_assert(sizeof(K1Meta) == K1Meta::kBytes, "K1Meta layout");
 struct MapLayout {
   size_t e2v = 0, xyz = 0, elem_face = 0, elem_pi = 0, elem_slot = 0,
          face_rowbase = 0, face_nslots = 0, tab_s = 0, tab_d = 0, tab_w = 0,
-         tab_ref = 0, tab_x = 0, face_selfslot = 0, face_owner = 0, k1_geo = 0, k1_meta = 0, face_w = 0,
+         tab_ref = 0, tab_x = 0, tab_1d = 0, face_selfslot = 0, face_owner = 0, k1_geo = 0, k1_meta = 0, face_w = 0,
          total = 0;
 };
 
@@ -56,7 +56,9 @@ struct Plan {
   // topology
   int64_t nfaces = 0, nbfaces = 0;  // interior / boundary faces
   std::vector<int32_t> elem_face;   // ne x 6, interior face id or -1
-  std::vector<uint8_t> elem_pi;     // ne x 8 (6 used), neighbour frame code
+  std::vector<uint8_t> elem_pi;     // ne x 8: neighbour frame code per face (0..5),
+                                    // byte 6: bit f set = face f is a natural boundary face
+  bool has_natural = false;         // some boundary face is natural
   std::vector<int32_t> face_owner;  // nfaces x 2 (element, local face)
   std::vector<int32_t> face_nbr;    // nfaces x 2
   // CSR of H and scatter slots
@@ -78,6 +80,8 @@ struct Plan {
   std::vector<double> tab_w;        // Q: weights
   std::vector<double> tab_ref;      // affine reference integrals (see plan.cpp)
   std::vector<double> tab_x;        // q1 Gauss points on [0,1]
+  std::vector<double> tab_1d;       // 1D tables [basis][point]: closed values (k+2), their
+                                    // derivatives (k+2), open values (k+1)
   // RT_1 affine kernels: per-element edge vectors J (9 doubles, row-major,
   // J[r][c] = x_{v_c}[r] - x_0[r] for vertices v = 1, 2, 4) and the element's
   // face data for the scatter into H (K1Meta, 144 bytes)

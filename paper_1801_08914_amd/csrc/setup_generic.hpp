@@ -540,7 +540,12 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     fid[f] = mp.elem_face[es * 6 + f];
     pic[f] = mp.elem_pi[es * 8 + f];
   }
-  auto is_ess = [&](int i) { return i >= ni && fid[(i - ni) / K2] < 0; };
+  // essential dofs: those of boundary faces not marked natural
+  const int nat = mp.elem_pi[es * 8 + 6];
+  auto is_ess = [&](int i) {
+    const int f = (i - ni) / K2;
+    return i >= ni && fid[f] < 0 && !((nat >> f) & 1);
+  };
   // static condensation: sign of face dof b's copy of the owner's outward flux
   auto sigma = [&](int b) {
     const int f = b / K2;
@@ -569,7 +574,12 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   // must not overwrite it, and computes the entries it needs directly)
   const bool store_matrix = need_matrix && (!Lay::kGlobal || (a.mode & MODE_MATRIX));
   if (store_matrix) {
-    if constexpr (TEAM % 64 == 0) {
+    if constexpr (K >= 1) {
+      static_assert(Lay::stage >= sumfact_stage<K>(), "the sum factorization's partial sums fit in the staging area");
+      assemble_sumfact<K, TEAM>(mp, qd, stg, lane, [&](int i, int j, double v) {
+        if (own) A[pk(i, j)] = v;
+      });
+    } else if constexpr (TEAM % 64 == 0) {
       assemble_mfma<K, TEAM, kAsmQC>(mp, qd, stg, lane, [&](int i, int j, double v) {
         if (own) A[pk(i, j)] = v;
       });

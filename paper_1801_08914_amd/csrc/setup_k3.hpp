@@ -1,0 +1,347 @@
+// RT_3 element setup (n = 240 broken dofs, 144 interior, 96 on faces) by
+// the blocks of the interior-first order, M_T = [[A_ii, A_ib], [A_bi, A_bb]]:
+//   L_ii = chol(A_ii)                    in LDS (83.5 KB), FP64 matrix cores,
+//   L_bi = A_bi L_ii^{-T}                forward tile solves, in place in HBM,
+//   S    = A_bb - L_bi L_bi^T            the face Schur complement, FP64
+//                                        matrix-core SYRK into LDS,
+//   L_bb = chol(S), then L_bb^{-1}       in LDS,
+// so that H_T = D L_bb^{-T} L_bb^{-1} D (Sec. 3.1, Sec. 5) needs no pass
+// over the whole 231 KB matrix in HBM per panel.  The element matrix is
+// assembled by sum factorization: the interior block straight into LDS, the
+// rows of the face dofs into the element's record (the packed factor, where
+// L_bi stays and the face block is written back inverted, the layout of the
+// generic kernels, which recover from it).
+#pragma once
+
+#include "mixed.hpp"
+
+namespace hyb {
+
+struct K3Layout {
+  using R = RT<3>;
+  static constexpr int n = R::n, ni = R::ni, nb = R::nb;
+  static constexpr int npi = ni * (ni + 1) / 2;                 // packed interior block
+  // staging: the sum factorization's partial sums, then the inverses of the
+  // diagonal blocks of L_ii, then S (its factor, its inverse) and the
+  // diagonal part of the blocked inverse
+  static constexpr int stage0 = sumfact_stage<3>();
+  static constexpr int stage1 = ((ni + 15) / 16) * 256;
+  static constexpr int stage2 = R::nbpk + 136;
+  static constexpr int stage = stage0 > stage1 ? (stage0 > stage2 ? stage0 : stage2) : (stage1 > stage2 ? stage1 : stage2);
+  static constexpr int per = npi + stage + R::Q * 10 + n + 24 + nb + 8;
+};
+
+template <int TEAM>
+__device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, int64_t e) {
+  using R = RT<3>;
+  using Lay = K3Layout;
+  constexpr int K = 3, n = R::n, ni = R::ni, nb = R::nb, K1 = R::K1, K2 = R::K2, Q = R::Q, QD = 10;
+  constexpr int NW = TEAM / 64;
+  static_assert(TEAM % 64 == 0 && TEAM >= nb, "whole waves, a lane per face row");
+  const int lane = threadIdx.x % TEAM, w_id = lane / 64, l = lane % 64;
+  const bool live = e < a.ne;
+  const int64_t es = live ? e : 0;
+  const bool own = live;   // a padding team (none in the launches here) writes nothing to the record
+  double* A = smem;                  // L_ii (packed), LDS
+  double* stg = A + Lay::npi;        // staging (see K3Layout)
+  double* qd = stg + Lay::stage;
+  double* fh = qd + Q * QD;
+  double* xe = fh + n;
+  double* tb = xe + 24;
+  int* flag = reinterpret_cast<int*>(tb + nb);
+  double* rec = a.factor + es * R::npk;   // the packed factor of the element (HBM)
+  double* Sb = stg;                       // S, L_bb, L_bb^{-1} (packed nb x nb)
+  auto LI = [&](int i, int j) -> double& { return Sb[pk(i, j)]; };
+  const DeviceMaps& mp = a.mp;
+  const bool matrix = (a.mode & MODE_MATRIX) != 0, rhs = (a.mode & MODE_RHS) != 0;
+
+  int fid[6], pic[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    fid[f] = mp.elem_face[es * 6 + f];
+    pic[f] = mp.elem_pi[es * 8 + f];
+  }
+  const int nat = mp.elem_pi[es * 8 + 6];
+  auto is_ess = [&](int i) {
+    const int f = (i - ni) / K2;
+    return i >= ni && fid[f] < 0 && !((nat >> f) & 1);
+  };
+  auto sigma = [&](int b) {
+    const int f = b / K2;
+    const double eps = (f & 1) ? 1.0 : -1.0;
+    return mp.face_owner[fid[f]] == e ? eps : -eps;
+  };
+
+  const double al = a.alpha ? a.alpha[es] : 0.0, be = a.beta ? a.beta[es] : 0.0;
+  double fv[3] = {0.0, 0.0, 0.0};
+  if (rhs) {
+    fv[0] = a.f[es * 3 + 0]; fv[1] = a.f[es * 3 + 1]; fv[2] = a.f[es * 3 + 2];
+  }
+  const bool need_matrix = matrix || (rhs && a.g);
+  element_qd<K, TEAM>(mp, es, al, be, fv, need_matrix, rhs, xe, qd, lane, live, a.status, e);
+  // entry (i, j) of M_T by Gauss quadrature (the right-hand side alone, for
+  // the boundary correction)
+  auto mij = [&](int i, int j) {
+    const int gi = gidx(R::comp(i), R::comp(j));
+    double s = 0.0;
+    for (int q = 0; q < Q; ++q)
+      s += qd[q * QD + gi] * mp.tab_s[q * n + i] * mp.tab_s[q * n + j] +
+           qd[q * QD + 6] * mp.tab_d[q * n + i] * mp.tab_d[q * n + j];
+    return s;
+  };
+
+  if (matrix) {
+    assemble_sumfact<K, TEAM>(mp, qd, stg, lane, [&](int i, int j, double v) {
+      if (i < ni) A[pk(i, j)] = v;
+      else if (own) rec[pk(i, j)] = v;
+    });
+    __syncthreads();
+  }
+  if (rhs) {
+    for (int i = lane; i < n; i += TEAM) {
+      const int d = R::comp(i);
+      double s = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < Q; ++q) s += mp.tab_s[q * n + i] * qd[q * QD + 7 + d];
+      if (is_ess(i)) {
+        s = a.g ? a.g[es * nb + (i - ni)] : 0.0;
+      } else if (a.g) {
+        // f_r -= M_re g_e (unmasked matrix; the essential dofs are face dofs)
+        for (int j = ni; j < n; ++j)
+          if (is_ess(j)) s -= (matrix ? rec[i > j ? pk(i, j) : pk(j, i)] : (i > j ? mij(i, j) : mij(j, i))) *
+                              a.g[es * nb + (j - ni)];
+      }
+      fh[i] = s;
+    }
+    __syncthreads();
+  }
+
+  if (matrix) {
+    // essential face dofs: identity rows and columns (the interior block has none)
+    for (int t = pk(ni, 0) + lane; t < R::npk; t += TEAM) {
+      int i, j;
+      unpk(t, i, j);
+      if (own && (is_ess(i) || is_ess(j))) rec[t] = (i == j) ? 1.0 : 0.0;
+    }
+    // L_ii = chol(A_ii) in LDS; the inverses of its diagonal blocks
+    const bool bad_i = chol_mfma_t<double, ni, TEAM>(A, lane, true, flag);
+    auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
+    diag_inverses<double, ni, TEAM>(Lii, stg, lane, true);
+    __syncthreads();
+    // L_bi^T = L_ii^{-1} A_bi^T: forward tile solves on the record's face rows
+    // (column c of W is face row ni + c), six column tiles over the waves
+    auto Wbi = [&](int i, int c) -> double& { return rec[pk(ni + c, i)]; };
+    for (int ct = own ? w_id : nb / 16; ct < nb / 16; ct += NW) tile_solve<double, ni, false>(Lii, stg, Wbi, 16 * ct, 16, l);
+    __syncthreads();
+    // S = A_bb - L_bi L_bi^T (lower 16 x 16 tiles on the FP64 matrix cores)
+    {
+      using M = MfmaT<double>;
+      constexpr int NT = nb / 16;
+      const int li = l & 15, lk = l >> 4;
+      for (int t = w_id; t < NT * (NT + 1) / 2; t += NW) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        const int J = t - I * (I + 1) / 2;
+        dx4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + M::row(l, r), j = 16 * J + li;
+          acc[r] = j <= i ? rec[pk(ni + i, ni + j)] : 0.0;
+        }
+        const double* ra = rec + pk(ni + 16 * I + li, 0);
+        const double* rb = rec + pk(ni + 16 * J + li, 0);
+        for (int q0 = 0; q0 < ni; q0 += 4) acc = M::op(-ra[q0 + lk], rb[q0 + lk], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + M::row(l, r), j = 16 * J + li;
+          if (j <= i) Sb[pk(i, j)] = acc[r];
+        }
+      }
+    }
+    // L_bb = chol(S) in LDS
+    const bool bad_b = chol_mfma_t<double, nb, TEAM>(Sb, lane, true, flag);
+    if ((bad_i || bad_b) && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
+    // L_ii back to the record (its packed rows lead the record)
+    for (int t = lane; t < Lay::npi; t += TEAM)
+      if (own) rec[t] = A[t];
+    if (a.stat) {
+      // static condensation: S_hat_T = L_bb L_bb^T (lower triangle), sigma-signed, into S
+      if (live) {
+        for (int t = lane; t < R::nbpk; t += TEAM) {
+          int aa, bb;
+          unpk(t, aa, bb);
+          const int fa = aa / K2, fb = bb / K2;
+          if (fid[fa] < 0 || fid[fb] < 0) continue;
+          double h = 0.0;
+          for (int c = 0; c <= bb; ++c) h += LI(aa, c) * LI(bb, c);
+          const double v = sigma(aa) * sigma(bb) * h;
+          int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
+          frame_map(pic[fa], K, a0, a1);
+          frame_map(pic[fb], K, b0, b1);
+          const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
+          const int Fa = fid[fa], Fb = fid[fb];
+          const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
+                              mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
+          const int64_t pba = mp.face_rowbase[Fb] + int64_t(jb) * mp.face_nslots[Fb] * K2 +
+                              mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
+          if (fa == fb) {
+            atomicAdd(&a.Hval[pab], v);
+            if (aa != bb) atomicAdd(&a.Hval[pba], v);
+          } else {
+            a.Hval[pab] = v;
+            a.Hval[pba] = v;
+          }
+        }
+      }
+    } else {
+      // L_bb^{-1} in place, by blocks of 16 columns right to left (a lane per
+      // row sums the terms of the finished columns into registers, then
+      // finishes its row of the block from the block's diagonal part Dg)
+      double* Fb = Sb;
+      double* Dg = Fb + R::nbpk;
+      for (int j0 = ((nb - 1) / 16) * 16; j0 >= 0; j0 -= 16) {
+        const int w = nb - j0 < 16 ? nb - j0 : 16;
+        for (int t = lane; t < w * (w + 1) / 2; t += TEAM) {
+          int aa, bb;
+          unpk(t, aa, bb);
+          Dg[t] = Fb[pk(j0 + aa, j0 + bb)];
+        }
+        const int i = j0 + lane;
+        double pr[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) pr[jj] = 0.0;
+        if (i >= j0 + w && i < nb) {
+          for (int c = j0 + w; c <= i; ++c) {
+            const double xic = Fb[pk(i, c)];
+            const double* Lc = Fb + pk(c, j0);
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj)
+              if (jj < w) pr[jj] += xic * Lc[jj];
+          }
+        }
+        __syncthreads();   // the block's columns of L are read, Dg is complete
+        if (i < nb) {
+          double x[16];
+#pragma unroll
+          for (int jj = 15; jj >= 0; --jj) {
+            x[jj] = 0.0;
+            const int j = j0 + jj;
+            if (jj < w && j <= i) {
+              if (j == i) {
+                x[jj] = 1.0 / Dg[pk(jj, jj)];
+              } else {
+                double sacc = pr[jj];
+#pragma unroll
+                for (int cc = jj + 1; cc < 16; ++cc)
+                  if (cc < w && j0 + cc <= i) sacc += x[cc] * Dg[pk(cc, jj)];
+                x[jj] = -sacc / Dg[pk(jj, jj)];
+              }
+            }
+          }
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj)
+            if (jj < w && j0 + jj <= i) Fb[pk(i, j0 + jj)] = x[jj];
+        }
+        __syncthreads();
+      }
+      // H_T = D L_bb^{-T} L_bb^{-1} D, scattered into H (lower triangle
+      // computed, mirrored; same-face blocks receive two terms by atomic add)
+      if (live) {
+        for (int t = lane; t < R::nbpk; t += TEAM) {
+          int aa, bb;
+          unpk(t, aa, bb);
+          const int fa = aa / K2, fb = bb / K2;
+          if (fid[fa] < 0 || fid[fb] < 0) continue;
+          double h = 0.0;
+          for (int c = aa; c < nb; ++c) h += LI(c, aa) * LI(c, bb);
+          const double v = ((fa ^ fb) & 1) ? -h : h;
+          int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
+          frame_map(pic[fa], K, a0, a1);
+          frame_map(pic[fb], K, b0, b1);
+          const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
+          const int Fa = fid[fa], Fb2 = fid[fb];
+          const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
+                              mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
+          const int64_t pba = mp.face_rowbase[Fb2] + int64_t(jb) * mp.face_nslots[Fb2] * K2 +
+                              mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
+          const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
+          if (fa == fb) {
+            atomicAdd(&a.Hval[pab], vw);
+            if (aa != bb) atomicAdd(&a.Hval[pba], vw);
+          } else {
+            a.Hval[pab] = vw;
+            a.Hval[pba] = vw;
+          }
+        }
+      }
+    }
+    // the face block (inverted, or L_bb for static condensation) to the record
+    __syncthreads();
+    for (int t = lane; t < R::nbpk; t += TEAM) {
+      int i, j;
+      unpk(t, i, j);
+      if (own) rec[pk(ni + i, ni + j)] = Sb[t];
+    }
+    __syncthreads();
+  } else if (rhs) {
+    // a right-hand side alone: the stored L_ii and face block back into LDS
+    for (int t = lane; t < Lay::npi; t += TEAM) A[t] = rec[t];
+    for (int t = lane; t < R::nbpk; t += TEAM) {
+      int i, j;
+      unpk(t, i, j);
+      Sb[t] = rec[pk(ni + i, ni + j)];
+    }
+    __syncthreads();
+  }
+
+  if (rhs) {
+    // y_i = L_ii^{-1} f_i
+    wave_forward<ni>(A, fh, lane);
+    // y_b = L_bb^{-1} (f_b - L_bi y_i)
+    for (int b = lane; b < nb; b += TEAM) {
+      const double* rb = rec + pk(ni + b, 0);
+      double s = fh[ni + b];
+      for (int j = 0; j < ni; ++j) s -= rb[j] * fh[j];
+      tb[b] = s;
+    }
+    __syncthreads();
+    // static condensation keeps f_b - L_bi y_i (on boundary faces: their data g)
+    for (int b = lane; b < nb; b += TEAM) {
+      double s = tb[b];
+      if (!a.stat) {
+        s = 0.0;
+        for (int c = 0; c <= b; ++c) s += LI(b, c) * tb[c];
+      }
+      fh[ni + b] = s;
+    }
+    __syncthreads();
+    if (live) {
+      for (int i = lane; i < n; i += TEAM) a.y[e * n + i] = fh[i];
+      // r_T = D L_bb^{-T} y_b, or (static condensation) sigma (f_b - L_bi y_i)
+      for (int b = lane; b < nb; b += TEAM) {
+        const int fb = b / K2;
+        if (fid[fb] < 0) continue;
+        double s;
+        if (a.stat) {
+          s = sigma(b) * fh[ni + b];
+        } else {
+          s = 0.0;
+          for (int c = b; c < nb; ++c) s += LI(c, b) * fh[ni + c];
+          if (!(fb & 1)) s = -s;
+        }
+        int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
+        frame_map(pic[fb], K, b0, b1);
+        if (!a.stat) s *= mp.face_w[b0 + K1 * b1];   // M_s r_T (weighted C)
+        atomicAdd(&a.r[int64_t(fid[fb]) * K2 + b0 + K1 * b1], s);
+      }
+    }
+  }
+}
+
+template <int TEAM>
+__global__ __launch_bounds__(TEAM) void k_setup_k3(SetupArgs a) {
+  __shared__ double smem[K3Layout::per];
+  setup_k3_body<TEAM>(a, smem, blockIdx.x);
+}
+
+}  // namespace hyb

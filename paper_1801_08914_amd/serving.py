@@ -155,7 +155,7 @@ class Server:
                         plan.setup(req.alpha, req.beta, f)
                     else:
                         plan.rhs(f)
-                    lam, info = plan.solve(self.rtol, self.maxit)
+                    lam, info = plan.pcg(self.rtol, self.maxit)
                     u = plan.recover(lam)
                     us.append(u.cpu().numpy())
                     iters.append(info["iters"])

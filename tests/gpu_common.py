@@ -97,13 +97,15 @@ def kappa_of(k, mesh, alpha, beta, topo, elements=None, ess=None):
 
 def accuracy_bound(e_oracle: float, kappa: float) -> float:
     """The GPU must be at least as accurate as the FP64 oracle (factor 2 for
-    rounding-order luck) against the long-double reference, and never needs
-    to beat 1e-12.  The oracle's own error is capped first: more than
-    10 kappa_s 2^-53 from the long-double reference means that one of the two
-    references is wrong, and the bound is refused rather than loosened."""
+    rounding-order luck) against the long-double reference, or within the
+    FP64 floor kappa_s 2^-53 of a backward-stable method where the oracle
+    happens to be luckier, and never needs to beat 1e-12.  The oracle's own
+    error is capped first: more than 10 kappa_s 2^-53 from the long-double
+    reference means that one of the two references is wrong, and the bound
+    is refused rather than loosened."""
     cap = 10.0 * kappa * U64
     assert e_oracle <= cap, f"FP64 oracle {e_oracle:.2e} off the long-double reference, above 10 kappa_s u = {cap:.2e}"
-    return max(1e-12, 2.0 * e_oracle)
+    return max(1e-12, 2.0 * e_oracle, kappa * U64)
 
 
 def oracle_gap_bound(kappa: float) -> float:
@@ -114,8 +116,8 @@ def oracle_gap_bound(kappa: float) -> float:
 
 def mixed_bound(e_oracle: float, kappa: float) -> float:
     """The mixed-precision form refined: within max(1e-10, 2 x the FP64
-    oracle's own error) of the long-double reference (the oracle's error
-    capped as in ``accuracy_bound``)."""
+    oracle's own error, the FP64 floor kappa_s 2^-53) of the long-double
+    reference (the oracle's error capped as in ``accuracy_bound``)."""
     cap = 10.0 * kappa * U64
     assert e_oracle <= cap, f"FP64 oracle {e_oracle:.2e} off the long-double reference, above 10 kappa_s u = {cap:.2e}"
-    return max(1e-10, 2.0 * e_oracle)
+    return max(1e-10, 2.0 * e_oracle, kappa * U64)

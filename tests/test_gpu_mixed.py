@@ -24,7 +24,7 @@ import scipy.sparse as sp
 import synth
 from oracle import extended as oext
 from oracle import hybrid as ohyb
-from tests.gpu_common import ld_dense, ld_row_errors, norm_rel, rel_inf, require_gpu
+from tests.gpu_common import U64, kappa_of, ld_dense, ld_row_errors, mixed_bound, norm_rel, rel_inf, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -114,7 +114,7 @@ def test_mixed_end_to_end_solve(k):
     torch = require_gpu()
     mesh, a, b, f = _problem(k, 2 if k == 3 else 3, 0.2, True, 3200 + k)
     plan = _mixed(torch, mesh, k, a, b, f)
-    lam, info = plan.solve(1e-13, 5000)
+    lam, info = plan.pcg(1e-13, 5000)
     assert info["converged"]
     u = plan.recover(lam).cpu().numpy()
     ref = ohyb.hybridize(k, mesh.xyz, mesh.e2v, a, b, f)
@@ -125,22 +125,58 @@ def test_mixed_end_to_end_solve(k):
     assert err <= 1e-9
 
 
-def test_mixed_reports_what_fp32_cannot_factor():
-    """beta / alpha ~ 1e6 on RT_2: kappa(S M_T S) 2^-24 > 1, the FP32 factor
-    breaks down; the mixed form reports HYB_E_REFINE with the element, the
-    plain FP64 form handles the same input."""
+@pytest.mark.parametrize("k,N", [(2, 2), (3, 2), (1, 3)])
+def test_mixed_falls_back_to_fp64_where_fp32_cannot(k, N):
+    """beta / alpha ~ 1e6 on some elements: kappa(S M_T S) 2^-24 > 1, the FP32
+    factor breaks down (or its refinement stalls); those elements are solved
+    in FP64 and counted, the others stay mixed, and every result is as
+    accurate as the FP64 form's (the FP64 bound against the long-double
+    reference).  k = 1 puts fallback and mixed elements in the same block."""
     torch = require_gpu()
     from paper_1801_08914_amd import Plan
-    from paper_1801_08914_amd._abi import HYB_E_REFINE
-    mesh, a, b, f = _problem(2, 2, 0.2, False, 3300, 1e6)
-    pm = Plan(mesh.xyz, mesh.e2v, 2, precision="mixed").bind()
+    mesh, a, b, f = _problem(k, N, 0.2, True, 3300 + k)
+    hard = np.arange(mesh.ne) % 3 == 0
+    b = np.where(hard, 1e6 * b, b)
+    ref = ohyb.hybridize(k, mesh.xyz, mesh.e2v, a, b, f)
+    lam = np.random.default_rng(8).standard_normal(ref.r.size)
+    Hld, rld, U = oext.hybridize_ld(k, mesh.xyz, mesh.e2v, a, b, f, ref.topo, np.arange(mesh.ne), lam)
+    pm = Plan(mesh.xyz, mesh.e2v, k, precision="mixed").bind()
     pm.setup(a, b, f)
+    torch.cuda.synchronize()
     rc, det = pm.status()
-    print(f"mixed: status {rc}, element {det}", flush=True)
-    assert rc == HYB_E_REFINE and 0 <= det < mesh.ne
-    pp = Plan(mesh.xyz, mesh.e2v, 2).bind()
+    nfb = pm.fallback_count()
+    print(f"k={k}: status {rc}, elements solved in FP64 {nfb} of {mesh.ne} ({int(hard.sum())} with beta x 1e6)",
+          flush=True)
+    assert rc == 0 and int(hard.sum()) <= nfb < mesh.ne
+    rp, ci, val = [t.cpu().numpy() for t in pm.csr()]
+    Hg = sp.csr_matrix((val, ci, rp), shape=ref.H.shape)
+    rows = np.arange(ref.r.size)
+    eH, er = ld_row_errors(Hld, rld, rows, Hg, pm.r().cpu().numpy())
+    eHo, ero = ld_row_errors(Hld, rld, rows, ref.H, ref.r)
+    ul = np.array([U[e].astype(float) for e in range(mesh.ne)])
+    u = pm.recover(torch.as_tensor(lam, device="cuda")).cpu().numpy()
+    uo = ohyb.recover(ref, mesh.xyz, mesh.e2v, a, b, f, lam)
+    kap = kappa_of(k, mesh, a, b, ref.topo)
+    eu, euo = rel_inf(ul, u), rel_inf(ul, uo)
+    print(f"  vs long double, mixed+fallback / FP64 oracle: H {eH:.1e} / {eHo:.1e}, r {er:.1e} / {ero:.1e}, "
+          f"u {eu:.1e} / {euo:.1e}; kappa_s {kap:.1e}", flush=True)
+    # the fallback elements are FP64 solves of matrices with kappa_s ~ 1e10:
+    # an FP64 backward-stable method is held to the cap the FP64 oracle itself
+    # must meet, 10 kappa_s 2^-53 (U64)
+    cap = 10.0 * kap * U64
+    assert eH <= max(mixed_bound(eHo, kap), cap) and er <= max(mixed_bound(ero, kap), cap)
+    assert eu <= max(mixed_bound(euo, kap), cap)
+    # a right-hand side alone takes the same paths (same bits as the setup's)
+    f2 = np.random.default_rng(12).standard_normal(f.shape)
+    pm.rhs(f2)
+    p2 = Plan(mesh.xyz, mesh.e2v, k, precision="mixed").bind()
+    p2.setup(a, b, f2)
+    torch.cuda.synchronize()
+    assert torch.equal(pm.r(), p2.r()) and torch.equal(pm.y_raw(), p2.y_raw())
+    # the FP64 form on the same input
+    pp = Plan(mesh.xyz, mesh.e2v, k).bind()
     pp.setup(a, b, f)
-    assert pp.status()[0] == 0
+    assert pp.status()[0] == 0 and pp.fallback_count() == 0
 
 
 def test_mixed_argument_errors():

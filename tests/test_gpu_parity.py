@@ -105,7 +105,7 @@ def test_c1_end_to_end():
     require_gpu()
     prob = synth.config_c1()
     plan = gpu_setup(prob.mesh, 0, prob.alpha, prob.beta, prob.f)
-    lam, info = plan.solve(1e-14, 1000)
+    lam, info = plan.pcg(1e-14, 1000)
     assert info["converged"], info
     u = plan.recover(lam).cpu().numpy()
     ref = ohyb.hybridize(0, prob.mesh.xyz, prob.mesh.e2v, prob.alpha, prob.beta, prob.f)
@@ -149,12 +149,12 @@ def test_constant_flux_with_boundary_data(k):
     exact = _interp_constant(k, mesh.xyz, mesh.e2v, c)
     g = exact[:, rt_basis.n_interior(k):]
     plan = gpu_setup(mesh, k, alpha, beta, f, g)
-    lam, info = plan.solve(1e-14, 2000)
+    lam, info = plan.pcg(1e-14, 2000)
     u = plan.recover(lam).cpu().numpy()
     assert rel_inf(exact, u) <= 1e-10, info
     # the rhs-only path with boundary data
     plan.rhs(f, g)
-    lam, info = plan.solve(1e-14, 2000)
+    lam, info = plan.pcg(1e-14, 2000)
     u = plan.recover(lam).cpu().numpy()
     assert rel_inf(exact, u) <= 1e-10, info
 

@@ -58,7 +58,7 @@ def test_iterates_match_oracle_pcg(k, N, jit, rot):
     torch = require_gpu()
     plan, ref = _plan_with_oracle_system(torch, k, N, jit, rot, 700 + 10 * k + N)
     for n in (1, 2, 3, 8, 17):
-        lam, info = plan.solve(1e-30, n)
+        lam, info = plan.pcg(1e-30, n)
         assert info["iters"] == n and not info["converged"]
         lo, it, _, _ = jacobi_pcg(ref.H, ref.r, rtol=1e-30, maxit=n)
         assert it == n
@@ -71,7 +71,7 @@ def test_iterates_match_oracle_pcg(k, N, jit, rot):
 def test_full_solve_matches_direct_solution(k, N, jit, rot):
     torch = require_gpu()
     plan, ref = _plan_with_oracle_system(torch, k, N, jit, rot, 800 + 10 * k + N)
-    lam, info = plan.solve(1e-12, 20000)
+    lam, info = plan.pcg(1e-12, 20000)
     lam = lam.cpu().numpy()
     direct = ohyb.solve_reduced(ref.H, ref.r)
     lo, it8, conv8, _ = jacobi_pcg(ref.H, ref.r, rtol=1e-12, maxit=20000, check_every=8)
@@ -83,7 +83,7 @@ def test_full_solve_matches_direct_solution(k, N, jit, rot):
     assert np.abs(lam - direct).max() <= 1e-9 * np.abs(direct).max()
     assert np.abs(lo - direct).max() <= 1e-9 * np.abs(direct).max()
     # deterministic: the same iterate bitwise on a second solve
-    lam2, info2 = plan.solve(1e-12, 20000)
+    lam2, info2 = plan.pcg(1e-12, 20000)
     assert info2["iters"] == info["iters"] and np.array_equal(lam2.cpu().numpy(), lam)
 
 
@@ -98,7 +98,7 @@ def test_reduction_modes_agree_bitwise(k, N):
     for mode in (1, 2):
         plan = Plan(mesh.xyz, mesh.e2v, k, pcg_reduce=mode).bind()
         plan.setup(a, b, f)
-        lam, info = plan.solve(1e-12, 5000)
+        lam, info = plan.pcg(1e-12, 5000)
         assert info["converged"]
         out.append((lam.cpu().numpy(), info["iters"], info["rel_res"]))
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
@@ -108,15 +108,15 @@ def test_not_converged_zero_rhs_and_empty_system():
     torch = require_gpu()
     from paper_1801_08914_amd import Plan
     plan, _ = _plan_with_oracle_system(torch, 1, 4, 0.2, False, 900)
-    lam, info = plan.solve(1e-14, 3)
+    lam, info = plan.pcg(1e-14, 3)
     assert info["iters"] == 3 and not info["converged"] and info["rel_res"] > 1e-14
     plan.r().zero_()
-    lam, info = plan.solve(1e-12, 100)
+    lam, info = plan.pcg(1e-12, 100)
     assert info["iters"] == 0 and info["converged"] and not lam.any()
     # one element: every face on the boundary, no multipliers
     mesh = synth.structured_hex(1)
     p1 = Plan(mesh.xyz, mesh.e2v, 1).bind()
     p1.setup(np.ones(1), np.ones(1), np.ones((1, 3)))
     assert p1.m == 0
-    lam, info = p1.solve(1e-12, 100)
+    lam, info = p1.pcg(1e-12, 100)
     assert info["iters"] == 0 and info["converged"] and lam.numel() == 0

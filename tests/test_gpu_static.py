@@ -65,11 +65,11 @@ def test_solution_equals_conforming_and_hybridized(k, N, jit, rot, wg):
     torch = require_gpu()
     mesh, a, b, f, g = _problem(k, N, jit, rot, wg, 7100 + 10 * k + N)
     ps = _plan(torch, mesh, k, a, b, f, g)
-    x, info = ps.solve(1e-13, 5000)
+    x, info = ps.pcg(1e-13, 5000)
     assert info["converged"]
     u = ps.recover(x).cpu().numpy()
     ph = _plan(torch, mesh, k, a, b, f, g, system="hybrid")
-    lam, ih = ph.solve(1e-13, 5000)
+    lam, ih = ph.pcg(1e-13, 5000)
     uh = ph.recover(lam).cpu().numpy()
     uc = conforming.conforming_solve(k, mesh.xyz, mesh.e2v, a, b, f, g)
     e1, e2 = rel_inf(uc, u), rel_inf(uh, u)

@@ -61,10 +61,10 @@ def test_weighted_H_r_and_invariant_solution(k, N, jit, rot):
         e = norm_rel(Hw.data, val)
         print(f"k={k}: weighted H, GPU vs oracle {e:.1e}; kappa_s {kap:.1e}", flush=True)
         assert e <= oracle_gap_bound(kap)
-    lw, iw = pw.solve(1e-13, 5000)
+    lw, iw = pw.pcg(1e-13, 5000)
     uw = pw.recover(lw).cpu().numpy()
     p0 = _plan(torch, mesh, k, a, b, f, False)
-    l0, i0 = p0.solve(1e-13, 5000)
+    l0, i0 = p0.pcg(1e-13, 5000)
     u0 = p0.recover(l0).cpu().numpy()
     e_lam = rel_inf(l0.cpu().numpy(), ms * lw.cpu().numpy())
     e_u = rel_inf(u0, uw)

@@ -81,7 +81,7 @@ def test_workload_matches_oracle(kind, k, p, dims):
         e = norm_rel(ref.H.data, val)
         print(f"  GPU vs FP64 oracle: H {e:.1e}", flush=True)
         assert e <= 1e-10
-    lam, info = plan.solve(1e-12, 50000)
+    lam, info = plan.pcg(1e-12, 50000)
     assert info["converged"], info
     u = plan.recover(lam).cpu().numpy()
     lref = ohyb.solve_reduced(ref.H, ref.r)
