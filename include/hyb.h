@@ -255,6 +255,20 @@ int hyb_rhs(hyb_plan_t* plan, const double* f, const double* g);
 int hyb_pcg(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solve_info* info);
 
 /*
+ * hyb_pcg for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same iteration and the same bits as hyb_pcg, with its work vectors,
+ * partial sums and scalars in a 48 MiB array that the library holds on each
+ * GPU it runs on until the process ends (the plan's work buffer is not
+ * touched).  Calls nothing that allocates.  Plans whose PCG work exceeds the
+ * array (about 8 (6 m) bytes, m up to about 1.0e6 multipliers) get HYB_E_ARG
+ * with the bytes needed in hyb_last_detail.  Every call on one GPU shares
+ * that GPU's array and leaves its contents behind: calls that overlap on one
+ * GPU (other streams, other host threads) race.  Other errors as hyb_pcg.
+ */
+int hyb_pcg_noalloc(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solve_info* info);
+
+/*
  * The whole solve for a load on the current factors (Theorem 2.1): the
  * right-hand side as hyb_rhs (f: device ne x 3, g: device boundary data or
  * NULL), H lambda = r by hyb_pcg (rtol, maxit), then the recovery of u as

@@ -154,13 +154,15 @@ class Plan:
         self._g = self._dev(g, (ne, 6 * (self.k + 1) ** 2))
         _abi.check(self._lib, self._lib.hyb_rhs(self._plan, _dptr(self._f), _dptr(self._g)))
 
-    def pcg(self, rtol=1e-12, maxit=10000, lam=None):
-        """Jacobi-PCG on H lambda = r (hyb_pcg): (lambda, info)."""
+    def pcg(self, rtol=1e-12, maxit=10000, lam=None, noalloc=False):
+        """Jacobi-PCG on H lambda = r (hyb_pcg, or hyb_pcg_noalloc with its
+        work in the library's fixed device array): (lambda, info)."""
         import torch
         if lam is None:
             lam = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.device)
         info = _abi.HybSolveInfo()
-        rc = self._lib.hyb_pcg(self._plan, ctypes.c_double(rtol), int(maxit), _dptr(lam), ctypes.byref(info))
+        fn = self._lib.hyb_pcg_noalloc if noalloc else self._lib.hyb_pcg
+        rc = fn(self._plan, ctypes.c_double(rtol), int(maxit), _dptr(lam), ctypes.byref(info))
         if rc not in (0, _abi.HYB_E_NOCONV):
             _abi.check(self._lib, rc)
         return lam[: self.m], dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res)

@@ -25,7 +25,7 @@ HYB_STATIC = 1
 # Every extern "C" symbol declared in include/hyb.h.
 EXPORTS = [
     "hyb_plan_create", "hyb_plan_topology", "hyb_last_detail", "hyb_bind", "hyb_setup", "hyb_rhs",
-    "hyb_pcg", "hyb_solve", "hyb_get_csr", "hyb_fallback_count", "hyb_recover", "hyb_status", "hyb_strerror", "hyb_destroy",
+    "hyb_pcg", "hyb_pcg_noalloc", "hyb_solve", "hyb_get_csr", "hyb_fallback_count", "hyb_recover", "hyb_status", "hyb_strerror", "hyb_destroy",
     "hyb_timing_enable", "hyb_timing_read", "hyb_set_stream",
     "hyb_batch_create", "hyb_batch_set", "hyb_batch_setup", "hyb_batch_recover", "hyb_batch_set_tiles",
     "hyb_batch_get_tiles", "hyb_batch_graph", "hyb_batch_autotune", "hyb_batch_timing_enable",
@@ -95,6 +95,7 @@ def load_library():
     lib.hyb_setup.argtypes = [vp, vp, vp, vp, vp]
     lib.hyb_rhs.argtypes = [vp, vp, vp]
     lib.hyb_pcg.argtypes = [vp, ctypes.c_double, ci, vp, vp]
+    lib.hyb_pcg_noalloc.argtypes = [vp, ctypes.c_double, ci, vp, vp]
     lib.hyb_solve.argtypes = [vp, vp, vp, ctypes.c_double, ci, vp, vp, vp]
     lib.hyb_get_csr.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.hyb_fallback_count.argtypes = [vp, vp]

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -620,6 +621,57 @@ int hyb_pcg(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solve_
   return pcg_run(P, rtol, maxit, lambda, info, P.buf.work);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// hyb_pcg_noalloc: the same PCG with its work vectors, partial sums and
+// scalars in a file-scope device array instead of the bound work buffer.
+// Host code never passes the array's name to a kernel (that is a host-side
+// stand-in): each device's address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+namespace {
+constexpr size_t kNoAllocBytes = size_t(48) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(double** out) {
+  int dev = 0;
+  HYB_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return HYB_E_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HYB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return HYB_E_INTERNAL;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
+  return HYB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int hyb_pcg_noalloc(hyb_plan_t* plan, double rtol, int maxit, double* lambda, hyb_solve_info* info) {
+  if (!plan || !lambda || maxit < 0) return HYB_E_ARG;
+  hyb::Plan& P = plan->P;
+  const size_t need = pcg_work_bytes(P);
+  if (need > kNoAllocBytes) {
+    g_last_detail = int64_t(need);
+    return HYB_E_ARG;
+  }
+  if (!P.have_rhs) return HYB_E_STATE;
+  double* w = nullptr;
+  const int rc = scratch_of_current_device(&w);
+  if (rc) return rc;
+  return pcg_run(P, rtol, maxit, lambda, info, w);
+}
 
 int hyb_recover(hyb_plan_t* plan, const double* lambda, double* u) {
   if (!plan || !lambda || !u) return HYB_E_ARG;
