@@ -77,6 +77,8 @@ __device__ __forceinline__ void assemble_mfma(const DeviceMaps& mp, const double
         for (int g = 0; g < G; ++g) {
           if (!on[g]) continue;  // uniform across the wave
           const int i = 16 * ti[g] + li, j = 16 * tj[g] + li;
+          // one table load per operand (the LDS bandwidth bounds this loop;
+          // loading both tables at clamped indices measured 1.5x slower)
           double a = 0.0, b = 0.0;
           if (i < n) a = lc < 3 ? (R::comp(i) == lc ? ts[i] : 0.0) : td[i];
           if (j < n) b = lc < 3 ? wq[gidx(lc, R::comp(j))] * ts[j] : wq[6] * td[j];
@@ -109,12 +111,26 @@ __device__ __forceinline__ int dof_index(int d, int a0, int a1, int a2) {
   return R::ni + (2 * d + (ic == 0 ? 0 : 1)) * R::K2 + j0 + R::K1 * j1;
 }
 
-// LDS doubles used by assemble_sumfact: the axis-0 and axis-1 partial sums of
-// both terms.
+// Whether the element assembly of order k uses sum factorization.  It needs
+// about 1.1 Mflop per RT3 element against 14.4 for the dense Gram sum on the
+// matrix cores and is then much faster (measured 50 against about 370 us per
+// element in a workgroup); for k <= 2 the saving is small in absolute terms
+// (0.17 against 1.49 Mflop for RT2) and the dense sum's independent tiles hide
+// latency better than the sum factorization's 18 barrier-separated passes
+// (RT2 48^3 setup 37.5 ms dense against 49.9 ms factored).
+template <int K>
+constexpr bool use_sumfact() { return K >= 3; }
+
+// LDS doubles used by assemble_sumfact: the 1D tables, then the axis-0 and
+// axis-1 partial sums of both terms.
+template <int K>
+constexpr int sumfact_tables() {
+  return (2 * (K + 2) + (K + 1)) * (K + 2);
+}
 template <int K>
 constexpr int sumfact_stage() {
   constexpr int KC = K + 2, K1 = K + 1, q1 = K + 2;
-  return 2 * (KC * KC * q1 * q1 + KC * KC * K1 * K1 * q1);
+  return sumfact_tables<K>() + 2 * (KC * KC * q1 * q1 + KC * KC * K1 * K1 * q1);
 }
 
 // Element matrix M_T by sum factorization (k >= 1, any trilinear element).
@@ -136,12 +152,17 @@ __device__ __forceinline__ void assemble_sumfact(const DeviceMaps& mp, const dou
                                                  Store store) {
   constexpr int KC = K + 2, K1 = K + 1, q1 = K + 2, QD = 10;
   static_assert(K >= 1, "sum factorization for k >= 1");
-  const double* Lc = mp.tab1d;          // [KC][q1]
+  // the 1D tables into LDS (read in every inner loop below)
+  constexpr int TB = sumfact_tables<K>();
+  __syncthreads();   // the team is done with the staging area
+  for (int t = lane; t < TB; t += TEAM) stage[t] = mp.tab1d[t];
+  const double* Lc = stage;             // [KC][q1]
   const double* Dc = Lc + KC * q1;      // [KC][q1]
   const double* Lo = Dc + KC * q1;      // [K1][q1]
-  double* S1 = stage;                                  // [2][a0][b0][q1][q2]
-  double* S2 = stage + 2 * KC * KC * q1 * q1;          // [2][a0][b0][a1][b1][q2]
+  double* S1 = stage + TB;                             // [2][a0][b0][q1][q2]
+  double* S2 = S1 + 2 * KC * KC * q1 * q1;             // [2][a0][b0][a1][b1][q2]
   constexpr int S1P = KC * KC * q1 * q1, S2P = KC * KC * K1 * K1 * q1;
+  __syncthreads();
   for (int d = 0; d < 3; ++d) {
     for (int e = d; e < 3; ++e) {
       const int gi = gidx(d, e);

@@ -90,15 +90,19 @@ __device__ __forceinline__ bool chol_mfma_t(T* A, int lane, bool active, int* fl
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * I + M::row(l, r), j = 16 * J + li;
-        acc[r] = (i < N && j <= i) ? A[pk(i, j)] : T(0);
+        const bool in = i < N && j <= i;
+        const T v = A[in ? pk(i, j) : 0];
+        acc[r] = in ? v : T(0);
       }
       const int ia = 16 * I + li, jb = 16 * J + li;
+      // operand loads at clamped (valid) addresses, masked values: no
+      // lane-dependent branches around the loads
+      const int iac = ia < N ? ia : N - 1, jbc = jb < N ? jb : N - 1;
 #pragma unroll
       for (int kk = 0; kk < NB / 4; ++kk) {
-        const int q = 4 * kk + lc;
-        const T av = (ia < N && q < w) ? -A[pk(ia, c0 + q)] : T(0);
-        const T bv = (jb < N && q < w) ? A[pk(jb, c0 + q)] : T(0);
-        acc = M::op(av, bv, acc);
+        const int q = 4 * kk + lc, qc = q < w ? q : w - 1;
+        const T av = A[pk(iac, c0 + qc)], bv = A[pk(jbc, c0 + qc)];
+        acc = M::op((ia < N && q < w) ? -av : T(0), (jb < N && q < w) ? bv : T(0), acc);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -129,12 +133,14 @@ __device__ __forceinline__ void diag_inverses(LAcc L, T* Linv, int lane, bool ac
     T x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
+      // x_k = 0 for k < j, so the sum needs no lane-dependent bounds (no
+      // branch around the loads)
       T s = i == j ? T(1) : T(0);
-      if (c0 + i < N) {
+      if (c0 + i < N) {   // uniform
 #pragma unroll
-        for (int k = 0; k < i; ++k)
-          if (k >= j) s -= L(c0 + i, c0 + k) * x[k];
-        x[i] = i >= j ? s / L(c0 + i, c0 + i) : T(0);
+        for (int k = 0; k < i; ++k) s -= L(c0 + i, c0 + k) * x[k];
+        const T xi = s / L(c0 + i, c0 + i);
+        x[i] = i >= j ? xi : T(0);
       } else {
         x[i] = s;
       }
@@ -159,7 +165,13 @@ __device__ __forceinline__ void tile_solve(LAcc L, const T* Linv, WAcc W, int c0
   const int li = l & 15, lk = l >> 4;
   const int c = c0 + li;
   const bool cok = li < ncol;
-  auto ld = [&](int i) -> T { return (cok && i < N) ? static_cast<T>(W(i, c)) : T(0); };
+  // loads at clamped (valid) positions, masked values: no lane-dependent
+  // branch around the loads
+  const int cc = cok ? c : c0;
+  auto ld = [&](int i) -> T {
+    const T v = static_cast<T>(W(i < N ? i : N - 1, cc));
+    return (cok && i < N) ? v : T(0);
+  };
   auto st = [&](int I, v4 v) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -171,12 +183,15 @@ __device__ __forceinline__ void tile_solve(LAcc L, const T* Linv, WAcc W, int c0
     v4 acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = ld(16 * I + M::row(l, r));
-    const int i = 16 * I + li;
+    const int i = 16 * I + li, ic = i < N ? i : N - 1;
+    // (unrolled: the operand loads of several blocks are in flight together)
+#pragma unroll 4
     for (int J = 0; J < I; ++J) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int q = 16 * J + 4 * s + lk;
-        acc = M::op(i < N ? -L(i, q) : T(0), ld(q), acc);
+        const T lv = L(ic, q);
+        acc = M::op(i < N ? -lv : T(0), ld(q), acc);
       }
     }
     st(I, acc);
@@ -194,11 +209,13 @@ __device__ __forceinline__ void tile_solve(LAcc L, const T* Linv, WAcc W, int c0
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = ld(16 * I + M::row(l, r));
     const int j = 16 * I + li;
+#pragma unroll 4
     for (int K = I + 1; K < NT; ++K) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int q = 16 * K + 4 * s + lk;
-        acc = M::op(q < N ? -L(q, j) : T(0), ld(q), acc);
+        const T lv = L(q < N ? q : N - 1, j);
+        acc = M::op(q < N ? -lv : T(0), ld(q), acc);
       }
     }
     st(I, acc);
@@ -227,13 +244,15 @@ __device__ __forceinline__ double residual_tiles(MAcc Mf, XAcc X, BFn B, Out out
     const bool cok = c < ncol;
     const int ia = 16 * I + li;
     dx4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int iac = ia < N ? ia : N - 1, cc = cok ? c : 0;
+#pragma unroll 4
     for (int J = 0; J < NT; ++J) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int q = 16 * J + 4 * s + lk;
-        const double a = (ia < N && q < N) ? Mf(ia, q) : 0.0;
-        const double b = (cok && q < N) ? static_cast<double>(X(q, c)) : 0.0;
-        acc = M::op(a, b, acc);
+        // loads at clamped (valid) positions, masked values
+        const int q = 16 * J + 4 * s + lk, qc = q < N ? q : N - 1;
+        const double av = Mf(iac, qc), bv = static_cast<double>(X(qc, cc));
+        acc = M::op((ia < N && q < N) ? av : 0.0, (cok && q < N) ? bv : 0.0, acc);
       }
     }
 #pragma unroll
@@ -481,9 +500,9 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
   }
   element_qd<K, TEAM>(mp, es, al, be, fv, true, rhs, xe, qd, lane, live, a.status, e);
 
-  // M_T (FP64, packed lower): by sum factorization (k >= 1), on the matrix
-  // cores for k = 0; the partial sums or tables staged in FW
-  if constexpr (K >= 1) {
+  // M_T (FP64, packed lower): by sum factorization (k = 3) or the dense sum
+  // on the matrix cores; the partial sums or tables staged in FW
+  if constexpr (use_sumfact<K>()) {
     static_assert(Lay::fw >= sumfact_stage<K>(), "the sum factorization's partial sums fit in FW");
     assemble_sumfact<K, TEAM>(mp, qd, FW, lane, [&](int i, int j, double v) { M64[pk(i, j)] = v; });
   } else {

@@ -148,7 +148,13 @@ __device__ __forceinline__ bool chol_diag16(T* A, int c0, int w, int l) {
   T d[16];
   const int i = c0 + l;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) d[j] = (l < w && j <= l) ? A[pk(i, c0 + j)] : T(0);
+  for (int j = 0; j < 16; ++j) {
+    // every lane loads (a valid address), then keeps its own entries: no
+    // lane-dependent branch around the loads
+    const bool in = l < w && j <= l;
+    const T v = A[in ? pk(i, c0 + j) : pk(c0, c0)];
+    d[j] = in ? v : T(0);
+  }
   bool bad = false;
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
@@ -231,15 +237,19 @@ __device__ __forceinline__ bool chol_packed_mfma(double* A, int lane) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * I + lc + 4 * r, j = 16 * J + li;
-        acc[r] = (i < N && j <= i) ? A[pk(i, j)] : 0.0;
+        const bool in = i < N && j <= i;
+        const double v = A[in ? pk(i, j) : 0];
+        acc[r] = in ? v : 0.0;
       }
       const int ia = 16 * I + li, jb = 16 * J + li;
+      // operand loads at clamped (valid) addresses, masked values: no
+      // lane-dependent branches
+      const int iac = ia < N ? ia : N - 1, jbc = jb < N ? jb : N - 1;
 #pragma unroll
       for (int kk = 0; kk < NB / 4; ++kk) {
-        const int q = 4 * kk + lc;
-        const double av = (ia < N && q < w) ? -A[pk(ia, c0 + q)] : 0.0;
-        const double bv = (jb < N && q < w) ? A[pk(jb, c0 + q)] : 0.0;
-        acc = mfma16x16x4(av, bv, acc);
+        const int q = 4 * kk + lc, qc = q < w ? q : w - 1;
+        const double av = A[pk(iac, c0 + qc)], bv = A[pk(jbc, c0 + qc)];
+        acc = mfma16x16x4((ia < N && q < w) ? -av : 0.0, (jb < N && q < w) ? bv : 0.0, acc);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -447,8 +457,11 @@ __device__ __forceinline__ void wave_forward(const double* L, double* y, int lan
         const double yc = wave_bcast(yr[s], c - 64 * s) / L[pk(c, c)];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
+          // unconditional load (clamped address), masked product: no branch
           const int i = lane + 64 * r;
-          if (i > c && i < NI) yr[r] -= L[pk(i, c)] * yc;
+          const bool in = i > c && i < NI;
+          const double lic = L[in ? pk(i, c) : pk(c, c)];
+          yr[r] -= (in ? lic : 0.0) * yc;
         }
         if (lane == c - 64 * s) yr[s] = yc;
       }
@@ -481,7 +494,9 @@ __device__ __forceinline__ void wave_backward(const double* L, double* z, int la
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           const int j = lane + 64 * r;
-          if (j < c) zr[r] -= L[pk(c, j)] * uc;
+          const bool in = j < c;
+          const double lcj = L[in ? pk(c, j) : pk(c, c)];
+          zr[r] -= (in ? lcj : 0.0) * uc;
         }
         if (lane == c - 64 * s) zr[s] = uc;
       }
@@ -574,7 +589,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   // must not overwrite it, and computes the entries it needs directly)
   const bool store_matrix = need_matrix && (!Lay::kGlobal || (a.mode & MODE_MATRIX));
   if (store_matrix) {
-    if constexpr (K >= 1) {
+    if constexpr (use_sumfact<K>()) {
       static_assert(Lay::stage >= sumfact_stage<K>(), "the sum factorization's partial sums fit in the staging area");
       assemble_sumfact<K, TEAM>(mp, qd, stg, lane, [&](int i, int j, double v) {
         if (own) A[pk(i, j)] = v;
@@ -713,7 +728,7 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       // registers (reading the block's original columns), then, after a
       // barrier, finishes its row of the block from right to left with the
       // block's diagonal part of L kept in Dg (the block's columns are being
-      // overwritten).  Three barriers per block instead of two per column.
+      // overwritten).  Two barriers per block instead of two per column.
       static_assert(Lay::stage >= R::nbpk + 136, "the face block and a diagonal block fit in the staging area");
       static_assert(TEAM >= nb, "a lane per row of the face block");
       double* Dg = Fb + R::nbpk;

@@ -22,11 +22,12 @@ struct K3Layout {
   static constexpr int n = R::n, ni = R::ni, nb = R::nb;
   static constexpr int npi = ni * (ni + 1) / 2;                 // packed interior block
   // staging: the sum factorization's partial sums, then the inverses of the
-  // diagonal blocks of L_ii, then S (its factor, its inverse) and the
-  // diagonal part of the blocked inverse
+  // diagonal blocks of L_ii, then S (its factor L_bb) and the inverses of
+  // L_bb's diagonal blocks; L_bb^{-1} (full nb x nb) goes where L_ii was
   static constexpr int stage0 = sumfact_stage<3>();
   static constexpr int stage1 = ((ni + 15) / 16) * 256;
-  static constexpr int stage2 = R::nbpk + 136;
+  static constexpr int stage2 = R::nbpk + (nb / 16) * 256;   // L_bb and its diagonal blocks' inverses
+  static_assert(nb * nb <= npi, "the full inverse of L_bb fits where L_ii was");
   static constexpr int stage = stage0 > stage1 ? (stage0 > stage2 ? stage0 : stage2) : (stage1 > stage2 ? stage1 : stage2);
   static constexpr int per = npi + stage + R::Q * 10 + n + 24 + nb + 8;
 };
@@ -50,10 +51,12 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
   double* tb = xe + 24;
   int* flag = reinterpret_cast<int*>(tb + nb);
   double* rec = a.factor + es * R::npk;   // the packed factor of the element (HBM)
-  double* Sb = stg;                       // S, L_bb, L_bb^{-1} (packed nb x nb)
-  auto LI = [&](int i, int j) -> double& { return Sb[pk(i, j)]; };
+  double* Sb = stg;                       // S, then L_bb (packed nb x nb)
+  double* Xb = A;                         // L_bb^{-1}, full nb x nb row-major (setup)
   const DeviceMaps& mp = a.mp;
   const bool matrix = (a.mode & MODE_MATRIX) != 0, rhs = (a.mode & MODE_RHS) != 0;
+  // L_bb^{-1}: full in LDS after a setup, packed (from the record) for a right-hand side alone
+  auto LI = [&](int i, int j) -> double { return matrix ? Xb[i * nb + j] : Sb[pk(i, j)]; };
 
   int fid[6], pic[6];
 #pragma unroll
@@ -117,15 +120,21 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
   }
 
   if (matrix) {
-    // essential face dofs: identity rows and columns (the interior block has none)
-    for (int t = pk(ni, 0) + lane; t < R::npk; t += TEAM) {
-      int i, j;
-      unpk(t, i, j);
-      if (own && (is_ess(i) || is_ess(j))) rec[t] = (i == j) ? 1.0 : 0.0;
+    // essential face dofs: identity rows and columns (the interior block has
+    // none), face by face; an entry between two essential faces is cleared
+    // by both passes, a diagonal entry set by its own face's pass only
+    for (int f = 0; f < 6; ++f) {
+      if (!is_ess(ni + f * K2)) continue;   // uniform across the team
+      for (int t = lane; t < K2 * n; t += TEAM) {
+        const int i = ni + f * K2 + t / n, j = t % n;
+        if (own) rec[i >= j ? pk(i, j) : pk(j, i)] = (i == j) ? 1.0 : 0.0;
+      }
     }
     // L_ii = chol(A_ii) in LDS; the inverses of its diagonal blocks
     const bool bad_i = chol_mfma_t<double, ni, TEAM>(A, lane, true, flag);
     auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
+    // y_i = L_ii^{-1} f_i while L_ii is in LDS
+    if (rhs) wave_forward<ni>(A, fh, lane);
     diag_inverses<double, ni, TEAM>(Lii, stg, lane, true);
     __syncthreads();
     // L_bi^T = L_ii^{-1} A_bi^T: forward tile solves on the record's face rows
@@ -166,6 +175,7 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       if (own) rec[t] = A[t];
     if (a.stat) {
       // static condensation: S_hat_T = L_bb L_bb^T (lower triangle), sigma-signed, into S
+      auto Lbb = [&](int i, int j) { return Sb[pk(i, j)]; };
       if (live) {
         for (int t = lane; t < R::nbpk; t += TEAM) {
           int aa, bb;
@@ -173,7 +183,7 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
           const int fa = aa / K2, fb = bb / K2;
           if (fid[fa] < 0 || fid[fb] < 0) continue;
           double h = 0.0;
-          for (int c = 0; c <= bb; ++c) h += LI(aa, c) * LI(bb, c);
+          for (int c = 0; c <= bb; ++c) h += Lbb(aa, c) * Lbb(bb, c);
           const double v = sigma(aa) * sigma(bb) * h;
           int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
           frame_map(pic[fa], K, a0, a1);
@@ -193,96 +203,76 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
           }
         }
       }
+      __syncthreads();
+      for (int t = lane; t < R::nbpk; t += TEAM) {
+        int i, j;
+        unpk(t, i, j);
+        if (own) rec[pk(ni + i, ni + j)] = Sb[t];
+      }
+      __syncthreads();
     } else {
-      // L_bb^{-1} in place, by blocks of 16 columns right to left (a lane per
-      // row sums the terms of the finished columns into registers, then
-      // finishes its row of the block from the block's diagonal part Dg)
-      double* Fb = Sb;
-      double* Dg = Fb + R::nbpk;
-      for (int j0 = ((nb - 1) / 16) * 16; j0 >= 0; j0 -= 16) {
-        const int w = nb - j0 < 16 ? nb - j0 : 16;
-        for (int t = lane; t < w * (w + 1) / 2; t += TEAM) {
-          int aa, bb;
-          unpk(t, aa, bb);
-          Dg[t] = Fb[pk(j0 + aa, j0 + bb)];
-        }
-        const int i = j0 + lane;
-        double pr[16];
+      // L_bb^{-1} = L_bb^{-1} I by forward tile solves (one wave per column
+      // tile, every 16-row block on the matrix cores), into Xb where L_ii was
+      double* LiB = Sb + R::nbpk;
+      auto Lbb = [&](int i, int j) -> double { return Sb[pk(i, j)]; };
+      diag_inverses<double, nb, TEAM>(Lbb, LiB, lane, true);
+      __syncthreads();   // L_ii is in the record
+      for (int t = lane; t < nb * nb; t += TEAM) Xb[t] = (t / nb == t % nb) ? 1.0 : 0.0;
+      __syncthreads();
+      auto Wx = [&](int i, int c) -> double& { return Xb[i * nb + c]; };
+      for (int ct = w_id; ct < nb / 16; ct += NW) tile_solve<double, nb, false>(Lbb, LiB, Wx, 16 * ct, 16, l);
+      __syncthreads();
+      // H_T = D L_bb^{-T} L_bb^{-1} D: the lower 16 x 16 tiles of X^T X on the
+      // FP64 matrix cores (X lower triangular: the sum starts at row block I),
+      // scattered into H from the accumulators (same-face blocks receive two
+      // element terms by atomic add; the mirror entry written as well)
+      {
+        using M = MfmaT<double>;
+        constexpr int NT = nb / 16;
+        const int li = l & 15, lk = l >> 4;
+        for (int t = w_id; t < NT * (NT + 1) / 2; t += NW) {
+          int I = 0;
+          while ((I + 1) * (I + 2) / 2 <= t) ++I;
+          const int J = t - I * (I + 1) / 2;
+          dx4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+          for (int c0 = 16 * I; c0 < nb; c0 += 4)
+            acc = M::op(Xb[(c0 + lk) * nb + 16 * I + li], Xb[(c0 + lk) * nb + 16 * J + li], acc);
+          if (!live) continue;
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) pr[jj] = 0.0;
-        if (i >= j0 + w && i < nb) {
-          for (int c = j0 + w; c <= i; ++c) {
-            const double xic = Fb[pk(i, c)];
-            const double* Lc = Fb + pk(c, j0);
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj)
-              if (jj < w) pr[jj] += xic * Lc[jj];
-          }
-        }
-        __syncthreads();   // the block's columns of L are read, Dg is complete
-        if (i < nb) {
-          double x[16];
-#pragma unroll
-          for (int jj = 15; jj >= 0; --jj) {
-            x[jj] = 0.0;
-            const int j = j0 + jj;
-            if (jj < w && j <= i) {
-              if (j == i) {
-                x[jj] = 1.0 / Dg[pk(jj, jj)];
-              } else {
-                double sacc = pr[jj];
-#pragma unroll
-                for (int cc = jj + 1; cc < 16; ++cc)
-                  if (cc < w && j0 + cc <= i) sacc += x[cc] * Dg[pk(cc, jj)];
-                x[jj] = -sacc / Dg[pk(jj, jj)];
-              }
+          for (int r = 0; r < 4; ++r) {
+            const int aa = 16 * I + M::row(l, r), bb = 16 * J + li;
+            const int fa = aa / K2, fb = bb / K2;
+            if (bb > aa || fid[fa] < 0 || fid[fb] < 0) continue;
+            const double v = ((fa ^ fb) & 1) ? -acc[r] : acc[r];
+            int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
+            frame_map(pic[fa], K, a0, a1);
+            frame_map(pic[fb], K, b0, b1);
+            const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
+            const int Fa = fid[fa], Fb2 = fid[fb];
+            const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
+                                mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
+            const int64_t pba = mp.face_rowbase[Fb2] + int64_t(jb) * mp.face_nslots[Fb2] * K2 +
+                                mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
+            const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
+            if (fa == fb) {
+              atomicAdd(&a.Hval[pab], vw);
+              if (aa != bb) atomicAdd(&a.Hval[pba], vw);
+            } else {
+              a.Hval[pab] = vw;
+              a.Hval[pba] = vw;
             }
           }
-#pragma unroll
-          for (int jj = 0; jj < 16; ++jj)
-            if (jj < w && j0 + jj <= i) Fb[pk(i, j0 + jj)] = x[jj];
-        }
-        __syncthreads();
-      }
-      // H_T = D L_bb^{-T} L_bb^{-1} D, scattered into H (lower triangle
-      // computed, mirrored; same-face blocks receive two terms by atomic add)
-      if (live) {
-        for (int t = lane; t < R::nbpk; t += TEAM) {
-          int aa, bb;
-          unpk(t, aa, bb);
-          const int fa = aa / K2, fb = bb / K2;
-          if (fid[fa] < 0 || fid[fb] < 0) continue;
-          double h = 0.0;
-          for (int c = aa; c < nb; ++c) h += LI(c, aa) * LI(c, bb);
-          const double v = ((fa ^ fb) & 1) ? -h : h;
-          int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
-          frame_map(pic[fa], K, a0, a1);
-          frame_map(pic[fb], K, b0, b1);
-          const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
-          const int Fa = fid[fa], Fb2 = fid[fb];
-          const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
-                              mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
-          const int64_t pba = mp.face_rowbase[Fb2] + int64_t(jb) * mp.face_nslots[Fb2] * K2 +
-                              mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
-          const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
-          if (fa == fb) {
-            atomicAdd(&a.Hval[pab], vw);
-            if (aa != bb) atomicAdd(&a.Hval[pba], vw);
-          } else {
-            a.Hval[pab] = vw;
-            a.Hval[pba] = vw;
-          }
         }
       }
+      // the face block of the record: L_bb^{-1} (lower)
+      for (int t = lane; t < R::nbpk; t += TEAM) {
+        int i, j;
+        unpk(t, i, j);
+        if (own) rec[pk(ni + i, ni + j)] = Xb[i * nb + j];
+      }
+      __syncthreads();
     }
-    // the face block (inverted, or L_bb for static condensation) to the record
-    __syncthreads();
-    for (int t = lane; t < R::nbpk; t += TEAM) {
-      int i, j;
-      unpk(t, i, j);
-      if (own) rec[pk(ni + i, ni + j)] = Sb[t];
-    }
-    __syncthreads();
   } else if (rhs) {
     // a right-hand side alone: the stored L_ii and face block back into LDS
     for (int t = lane; t < Lay::npi; t += TEAM) A[t] = rec[t];
@@ -292,11 +282,11 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       Sb[t] = rec[pk(ni + i, ni + j)];
     }
     __syncthreads();
+    // y_i = L_ii^{-1} f_i
+    wave_forward<ni>(A, fh, lane);
   }
 
   if (rhs) {
-    // y_i = L_ii^{-1} f_i
-    wave_forward<ni>(A, fh, lane);
     // y_b = L_bb^{-1} (f_b - L_bi y_i)
     for (int b = lane; b < nb; b += TEAM) {
       const double* rb = rec + pk(ni + b, 0);

@@ -153,6 +153,11 @@ class Server:
                 for r, f in enumerate(req.loads):
                     if r == 0:
                         plan.setup(req.alpha, req.beta, f)
+                        # a failed element (non-SPD matrix, det J <= 0) ends
+                        # the request here, before its solve
+                        rc, det = plan.status()
+                        if rc != 0:
+                            raise RuntimeError(f"device error {rc} at element {det}")
                     else:
                         plan.rhs(f)
                     lam, info = plan.pcg(self.rtol, self.maxit)

@@ -82,3 +82,40 @@ def test_admission_by_memory_budget():
             srv.submit(reqs[0][1]).result(timeout=60)
     finally:
         srv.close()
+
+
+def test_a_failing_request_leaves_the_others_unchanged():
+    """One request in the mix has an indefinite element matrix (negative mass
+    coefficient on one element): it fails with HYB_E_NOT_SPD and that
+    element, the requests around it complete with the bits they have alone."""
+    require_gpu()
+    import dataclasses
+
+    from paper_1801_08914_amd import _abi
+    from paper_1801_08914_amd.serving import Server
+    reqs = _requests()
+    bad_at = 2
+    _, r = reqs[bad_at]
+    alpha = r.alpha.copy()
+    alpha[1] = -5.0
+    bad = dataclasses.replace(r, alpha=alpha, beta=r.beta * 1e-3, tag="bad")
+    good = [q for i, (_, q) in enumerate(reqs) if i != bad_at]
+    alone = _run(1, 1 << 40, [(0.0, q) for q in good], together=False)
+    srv = Server(1 << 40, slots=4, rtol=1e-13)
+    try:
+        order = good[:bad_at] + [bad] + good[bad_at:]
+        futs = [srv.submit(q) for q in order]
+        out = []
+        for q, fu in zip(order, futs):
+            if q.tag == "bad":
+                with pytest.raises(RuntimeError) as ei:
+                    fu.result(timeout=240)
+                assert f"device error {_abi.HYB_E_NOT_SPD} at element 1" in str(ei.value)
+            else:
+                out.append(fu.result(timeout=240))
+    finally:
+        srv.close()
+    for a, b in zip(alone, out):
+        assert a.tag == b.tag
+        for ua, ub in zip(a.u, b.u):
+            assert np.array_equal(ua, ub), a.tag
