@@ -341,7 +341,8 @@ void hyb_destroy(hyb_plan_t* plan);
  * setup of every element of every problem runs in ONE persistent launch (after
  * one launch that clears the same-face blocks of every H), the recovery in
  * another; work items (problem, run of element blocks) are sorted by cost and
- * dealt round-robin to a grid of blocks_per_cu x (compute units) workgroups.
+ * taken from a work queue (an atomic counter, most expensive first) by a
+ * grid of blocks_per_cu x (compute units) workgroups.
  * Every order uses the generic element routines (Gauss quadrature, packed
  * Cholesky, inverse of the face block), so a batch sets its plans to that
  * record layout; H, r, y and u of each problem equal those of the plan's own

@@ -59,6 +59,17 @@ __device__ __attribute__((noinline)) void batch_setup_mx(const SetupArgs& a, dou
   setup_mixed_body<K, TEAM, EPB>(a, smem, blk, sweeps, scratch);
 }
 
+// The next work item of a persistent workgroup from the launch's queue
+// counter (cleared by a kernel before the launch): thread 0 takes it, the
+// workgroup reads it after a barrier.  Items are sorted by cost, so the
+// most expensive ones are taken first.
+__device__ __forceinline__ int64_t next_item(int32_t* queue, int64_t* slot) {
+  __syncthreads();   // every thread has read the previous item
+  if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
+  __syncthreads();
+  return *slot;
+}
+
 // Zero the same-face blocks of H (and r) of every problem: blockIdx.y is the
 // problem.
 __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
@@ -81,9 +92,10 @@ __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
 }
 
 __global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* probs, const BatchItem* items,
-                                                               int64_t nitems) {
+                                                               int64_t nitems, int32_t* queue) {
   extern __shared__ double smem[];
-  for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+  __shared__ int64_t item;
+  for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem it = items[w];
     const BatchProb& P = probs[it.prob];
     for (int b = 0; b < it.nblk; ++b) {
@@ -100,9 +112,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* 
 }
 
 __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb* probs, const BatchItem* items,
-                                                                 int64_t nitems) {
+                                                                 int64_t nitems, int32_t* queue) {
   extern __shared__ double smem[];
-  for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+  __shared__ int64_t item;
+  for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem it = items[w];
     const BatchProb& P = probs[it.prob];
     for (int b = 0; b < it.nblk; ++b) {
@@ -122,11 +135,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
 // items follow the FP64 ones in the list; a separate launch, so the FP64
 // kernels keep their own LDS size).
 __global__ __launch_bounds__(kBatchThreads) void k_setup_batch_mixed(const BatchProb* probs, const BatchItem* items,
-                                                                     int64_t nitems, double* scratch) {
+                                                                     int64_t nitems, double* scratch,
+                                                                     int32_t* queue) {
   extern __shared__ double smem[];
+  __shared__ int64_t item;
   // workgroup b owns scratch slot b (k = 3; the grid has at most kMixedSlots workgroups)
   double* slot = scratch ? scratch + int64_t(blockIdx.x) * MixedLayout<3, 512, 1>::slot : nullptr;
-  for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+  for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem it = items[w];
     const BatchProb& P = probs[it.prob];
     for (int b = 0; b < it.nblk; ++b) {
@@ -143,9 +158,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_setup_batch_mixed(const Batch
 }
 
 __global__ __launch_bounds__(kBatchThreads) void k_recover_batch_mixed(const BatchProb* probs,
-                                                                       const BatchItem* items, int64_t nitems) {
+                                                                       const BatchItem* items, int64_t nitems,
+                                                                       int32_t* queue) {
   extern __shared__ double smem[];
-  for (int64_t w = blockIdx.x; w < nitems; w += gridDim.x) {
+  __shared__ int64_t item;
+  for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem it = items[w];
     const BatchProb& P = probs[it.prob];
     for (int b = 0; b < it.nblk; ++b) {

@@ -824,6 +824,7 @@ struct hyb_batch {
   hipStream_t gstream = nullptr;           // capture/replay stream (graphs need a non-null stream)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   double* scratch = nullptr;               // k = 3 mixed: a slot per workgroup of the mixed launch
+  int32_t* d_queue = nullptr;              // work-queue counters of the four persistent launches
   // optional HIP-event timing of each phase (start/stop pairs, launch order)
   bool timing = false;
   std::vector<hipEvent_t> ev_setup, ev_recover, ev_pool;
@@ -912,15 +913,18 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
   hipLaunchKernelGGL(hyb::k_batch_zero, dim3(zx, unsigned(b->probs.size())), dim3(256), 0, st, b->d_probs);
   HYB_HIP(hipGetLastError());
   const size_t nmx = b->items.size() - b->n64;
+  // the queue counters start at zero (a kernel, not a memset: graph replays)
+  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue, int64_t(2), 0);
+  HYB_HIP(hipGetLastError());
   if (b->n64) {
     hipLaunchKernelGGL(hyb::k_setup_batch, dim3(batch_grid(b, b->n64)), dim3(hyb::kBatchThreads), b->lds_setup, st,
-                       b->d_probs, b->d_items, int64_t(b->n64));
+                       b->d_probs, b->d_items, int64_t(b->n64), b->d_queue);
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {
     const unsigned gm = std::min<unsigned>(batch_grid(b, nmx), unsigned(hyb::kMixedSlots));
     hipLaunchKernelGGL(hyb::k_setup_batch_mixed, dim3(gm), dim3(hyb::kBatchThreads), b->lds_setup_mx, st,
-                       b->d_probs, b->d_items + b->n64, int64_t(nmx), b->scratch);
+                       b->d_probs, b->d_items + b->n64, int64_t(nmx), b->scratch, b->d_queue + 1);
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
@@ -928,14 +932,16 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
 
 int batch_launch_recover(hyb_batch* b, hipStream_t st) {
   const size_t nmx = b->items.size() - b->n64;
+  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue + 2, int64_t(2), 0);
+  HYB_HIP(hipGetLastError());
   if (b->n64) {
     hipLaunchKernelGGL(hyb::k_recover_batch, dim3(batch_grid(b, b->n64)), dim3(hyb::kBatchThreads), b->lds_recover,
-                       st, b->d_probs, b->d_items, int64_t(b->n64));
+                       st, b->d_probs, b->d_items, int64_t(b->n64), b->d_queue + 2);
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {
     hipLaunchKernelGGL(hyb::k_recover_batch_mixed, dim3(batch_grid(b, nmx)), dim3(hyb::kBatchThreads),
-                       b->lds_recover_mx, st, b->d_probs, b->d_items + b->n64, int64_t(nmx));
+                       b->lds_recover_mx, st, b->d_probs, b->d_items + b->n64, int64_t(nmx), b->d_queue + 3);
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
@@ -1054,6 +1060,7 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
   bool mixed3 = false;
   for (int32_t i = 0; i < count; ++i) mixed3 |= plans[i]->P.mixed && plans[i]->P.ord.k == 3;
   hipError_t e1 = hipMalloc(&b->d_probs, sizeof(hyb::BatchProb) * b->probs.size());
+  if (e1 == hipSuccess) e1 = hipMalloc(&b->d_queue, 4 * sizeof(int32_t));
   if (e1 == hipSuccess && mixed3) e1 = hipMalloc(&b->scratch, size_t(mixed_scratch_bytes(3)));
   if (e1 == hipSuccess) e1 = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
   if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
@@ -1237,6 +1244,7 @@ void hyb_batch_destroy(hyb_batch_t* b) {
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_probs) (void)hipFree(b->d_probs);
   if (b->scratch) (void)hipFree(b->scratch);
+  if (b->d_queue) (void)hipFree(b->d_queue);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->gstream) (void)hipStreamDestroy(b->gstream);
