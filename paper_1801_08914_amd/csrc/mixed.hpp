@@ -229,6 +229,60 @@ __device__ __forceinline__ void tile_solve(LAcc L, const T* Linv, WAcc W, int c0
   }
 }
 
+// FP64 forward substitution W := L^{-1} W on one column tile (columns c0 ..
+// c0 + ncol - 1, ncol <= 16) by one wave with the whole tile in registers:
+// the FP64 matrix-core result layout (rows l/16 + 4r of column l % 16) is the
+// layout of the B operand at k-step r (rows 4r + l/16), so a solved 16-row
+// block feeds the next blocks' products straight from its accumulator, and
+// the tile touches memory only when it is loaded and stored.  load(i, c) /
+// store(i, c, v) read and write the tile (i < N, c < c0 + ncol); L(i, j) is
+// the factor (j <= i < N, LDS) and Linv its diagonal blocks' inverses.  The
+// tile's row blocks before I0 are zero (and stay so), and are skipped.
+template <int N, class LAcc, class Load, class Store>
+__device__ __forceinline__ void tile_forward_reg(LAcc L, const double* Linv, Load load, Store store, int c0, int ncol,
+                                                 int l, int I0 = 0) {
+  using M = MfmaT<double>;
+  constexpr int NT = (N + 15) / 16;
+  const int li = l & 15, lk = l >> 4;
+  const int c = c0 + li;
+  const bool cok = li < ncol;
+  const int cc = cok ? c : c0;
+  dx4 X[NT];
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + M::row(l, r);
+      const double v = load(i < N ? i : N - 1, cc);
+      X[I][r] = (cok && i < N) ? v : 0.0;
+    }
+#pragma unroll
+  for (int I = 0; I < NT; ++I) {
+    if (I < I0) continue;   // uniform
+    const int i = 16 * I + li, ic = i < N ? i : N - 1;
+    dx4 acc = X[I];
+#pragma unroll
+    for (int J = 0; J < I; ++J)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (J < I0) continue;
+        const double lv = L(ic, 16 * J + 4 * s + lk);
+        acc = M::op(i < N ? -lv : 0.0, X[J][s], acc);
+      }
+    dx4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x = M::op(Linv[256 * I + 16 * li + 4 * s + lk], acc[s], x);
+    X[I] = x;
+  }
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + M::row(l, r);
+      if (cok && i < N) store(i, c, X[I][r]);
+    }
+}
+
 // R = B - M X (FP64) on the output tiles (16 rows x 16 columns) dealt to the
 // team's waves; out(i, c, R) receives every entry i < N, c < ncol.  Returns
 // the lane's largest |R|.  Mf(i, j): the symmetric FP64 matrix, any i, j < N.

@@ -133,14 +133,20 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     // L_ii = chol(A_ii) in LDS; the inverses of its diagonal blocks
     const bool bad_i = chol_mfma_t<double, ni, TEAM>(A, lane, true, flag);
     auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
-    // y_i = L_ii^{-1} f_i while L_ii is in LDS
-    if (rhs) wave_forward<ni>(A, fh, lane);
     diag_inverses<double, ni, TEAM>(Lii, stg, lane, true);
     __syncthreads();
-    // L_bi^T = L_ii^{-1} A_bi^T: forward tile solves on the record's face rows
-    // (column c of W is face row ni + c), six column tiles over the waves
-    auto Wbi = [&](int i, int c) -> double& { return rec[pk(ni + c, i)]; };
-    for (int ct = own ? w_id : nb / 16; ct < nb / 16; ct += NW) tile_solve<double, ni, false>(Lii, stg, Wbi, 16 * ct, 16, l);
+    // L_bi^T = L_ii^{-1} A_bi^T by forward tile solves held in registers, on
+    // the record's face rows (column c of the tile is face row ni + c): six
+    // column tiles over the waves, and y_i = L_ii^{-1} f_i as a seventh
+    // (one column) while L_ii is in LDS
+    if (w_id < nb / 16) {
+      if (own)
+        tile_forward_reg<ni>(Lii, stg, [&](int i, int c) { return rec[pk(ni + c, i)]; },
+                             [&](int i, int c, double v) { rec[pk(ni + c, i)] = v; }, 16 * w_id, 16, l);
+    } else if (w_id == nb / 16 && rhs) {
+      tile_forward_reg<ni>(Lii, stg, [&](int i, int) { return fh[i]; }, [&](int i, int, double v) { fh[i] = v; }, 0, 1,
+                           l);
+    }
     __syncthreads();
     // S = A_bb - L_bi L_bi^T (lower 16 x 16 tiles on the FP64 matrix cores)
     {
@@ -217,10 +223,9 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       auto Lbb = [&](int i, int j) -> double { return Sb[pk(i, j)]; };
       diag_inverses<double, nb, TEAM>(Lbb, LiB, lane, true);
       __syncthreads();   // L_ii is in the record
-      for (int t = lane; t < nb * nb; t += TEAM) Xb[t] = (t / nb == t % nb) ? 1.0 : 0.0;
-      __syncthreads();
-      auto Wx = [&](int i, int c) -> double& { return Xb[i * nb + c]; };
-      for (int ct = w_id; ct < nb / 16; ct += NW) tile_solve<double, nb, false>(Lbb, LiB, Wx, 16 * ct, 16, l);
+      if (w_id < nb / 16)
+        tile_forward_reg<nb>(Lbb, LiB, [&](int i, int c) { return i == c ? 1.0 : 0.0; },
+                             [&](int i, int c, double v) { Xb[i * nb + c] = v; }, 16 * w_id, 16, l, w_id);
       __syncthreads();
       // H_T = D L_bb^{-T} L_bb^{-1} D: the lower 16 x 16 tiles of X^T X on the
       // FP64 matrix cores (X lower triangular: the sum starts at row block I),
@@ -274,16 +279,23 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       __syncthreads();
     }
   } else if (rhs) {
-    // a right-hand side alone: the stored L_ii and face block back into LDS
+    // a right-hand side alone: y_i = L_ii^{-1} f_i from the stored L_ii, as
+    // the setup computes it, then the stored face block into LDS
     for (int t = lane; t < Lay::npi; t += TEAM) A[t] = rec[t];
+    __syncthreads();
+    auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
+    diag_inverses<double, ni, TEAM>(Lii, stg, lane, true);
+    __syncthreads();
+    if (w_id == 0)
+      tile_forward_reg<ni>(Lii, stg, [&](int i, int) { return fh[i]; }, [&](int i, int, double v) { fh[i] = v; }, 0, 1,
+                           l);
+    __syncthreads();
     for (int t = lane; t < R::nbpk; t += TEAM) {
       int i, j;
       unpk(t, i, j);
       Sb[t] = rec[pk(ni + i, ni + j)];
     }
     __syncthreads();
-    // y_i = L_ii^{-1} f_i
-    wave_forward<ni>(A, fh, lane);
   }
 
   if (rhs) {
