@@ -64,9 +64,10 @@ __device__ __forceinline__ void wave_sync() {
 // broadcasts), the rows below it one per lane, the trailing lower 16 x 16
 // tiles on the matrix cores of T.  With active false the team only takes
 // part in the barriers.  Returns true in every lane of the team when a pivot
-// was not positive (replaced by 1); flag: one int of team LDS.
+// was not positive (replaced by 1); flag: one int of team LDS, rd: 16 T of
+// team LDS.
 template <class T, int N, int TEAM>
-__device__ __forceinline__ bool chol_mfma_t(T* A, int lane, bool active, int* flag) {
+__device__ __forceinline__ bool chol_mfma_t(T* A, int lane, bool active, int* flag, T* rd) {
   using M = MfmaT<T>;
   constexpr int NB = 16, NT = (N + 15) / 16, NW = TEAM / 64;
   static_assert(TEAM % 64 == 0, "whole waves per team");
@@ -76,9 +77,9 @@ __device__ __forceinline__ bool chol_mfma_t(T* A, int lane, bool active, int* fl
   bool bad = false;
   for (int c0 = 0; c0 < N; c0 += NB) {
     const int w = N - c0 < NB ? N - c0 : NB;
-    if (active && w_id == 0) bad |= chol_diag16(A, c0, w, l);
+    if (active && w_id == 0) bad |= chol_diag16(A, rd, c0, w, l);
     __syncthreads();
-    if (active) chol_panel_rows<T, N, TEAM>(A, c0, w, lane);
+    if (active) chol_panel_rows<T, N, TEAM>(A, rd, c0, w, lane);
     __syncthreads();
     const int T0 = (c0 + w + 15) / 16, m = NT - T0;
     for (int t = active ? w_id : (1 << 30); t < m * (m + 1) / 2; t += NW) {
@@ -473,7 +474,7 @@ struct MixedLayout {
   static constexpr int li = (kGlobal || li64_in_m) ? NT * 128 : li64;
   static constexpr int m64 = kGlobal ? 0 : R::npk;
   static constexpr int x64 = kGlobal ? 0 : n * nb;
-  static constexpr int per = m64 + x64 + fw + li + R::Q * 10 + 3 * n + 24 + 16;
+  static constexpr int per = m64 + x64 + fw + li + R::Q * 10 + 3 * n + 24 + 32;
   // HBM scratch per workgroup (k = 3): M64 and the FP32 work columns
   static constexpr int64_t slot = kGlobal ? int64_t(R::npk) + w32 : 0;
   static_assert(!kGlobal || fw >= hbm_panel + li64, "the HBM Cholesky's panel and FP64 block inverses fit in FW");
@@ -520,6 +521,7 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
   double* xe = yv + n;
   double* red = xe + 24;
   int* flag = reinterpret_cast<int*>(red + 12);
+  double* rdv = red + 16;   // the Cholesky's pivot reciprocals (16)
   const DeviceMaps& mp = a.mp;
 
   auto Mrow = [&](int i, int j) { return i >= j ? M64[pk(i, j)] : M64[pk(j, i)]; };
@@ -601,7 +603,7 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
   const double anrm = norm_inf<n, TEAM>(Mrow, red + 10, lane);
   // FP32 Cholesky of S M_T S; a breakdown means kappa(S M_T S) 2^-24 >= 1
   // (or M_T is not SPD): such an element is solved in FP64
-  const bool broke = chol_mfma_t<float, n, TEAM>(L32, lane, true, flag);
+  const bool broke = chol_mfma_t<float, n, TEAM>(L32, lane, true, flag, reinterpret_cast<float*>(rdv));
   diag_inverses<float, n, TEAM>(L32a, Li32, lane, !broke);
   __syncthreads();
 
@@ -629,7 +631,7 @@ __device__ __forceinline__ void setup_mixed_body(const SetupArgs& a, double* sme
       __syncthreads();
     } else {
       for (int p = fb ? lane : R::npk; p < R::npk; p += TEAM) F[p] = M64[p];
-      notspd = chol_mfma_t<double, n, TEAM>(F, lane, fb, flag);
+      notspd = chol_mfma_t<double, n, TEAM>(F, lane, fb, flag, rdv);
     }
     if (fb && notspd && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
     auto Fa = [&](int i, int j) -> double { return F[pk(i, j)]; };

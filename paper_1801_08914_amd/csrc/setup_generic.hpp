@@ -139,12 +139,35 @@ __device__ __forceinline__ float wave_bcast(float v, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
+// 1/sqrt(x) for a positive normal x: the hardware estimate refined by Newton
+// steps on y^-2 = x (y <- y + y (1 - x y^2) / 2, each step roughly squaring
+// the relative error; two steps reach the FP64 rounding level from the
+// estimate's, one the FP32 level).
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+__device__ __forceinline__ float rsqrt_refined(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float e = fmaf(-x * y, y, 1.0f);
+  return fmaf(0.5f * y, e, y);
+}
+
 // The w x w (w <= 16) diagonal block at (c0, c0) of a packed lower triangle,
 // factored on one wave: lane l < w holds row c0 + l in registers, pivots and
-// column entries come by wave broadcast (no barrier).  A non-positive pivot is
+// column entries come by wave broadcast (no barrier).  Each pivot costs one
+// refined reciprocal square root: L_cc = p / sqrt(p), the column below it
+// scaled by 1 / sqrt(p), which also goes to rd[c] (LDS, for the rows below the
+// block).  The updates run unmasked: a lane's entries right of its diagonal
+// take values that are never read or stored.  A non-positive pivot is
 // replaced by 1 and reported.
 template <class T>
-__device__ __forceinline__ bool chol_diag16(T* A, int c0, int w, int l) {
+__device__ __forceinline__ bool chol_diag16(T* A, T* rd, int c0, int w, int l) {
   T d[16];
   const int i = c0 + l;
 #pragma unroll
@@ -156,6 +179,7 @@ __device__ __forceinline__ bool chol_diag16(T* A, int c0, int w, int l) {
     d[j] = in ? v : T(0);
   }
   bool bad = false;
+  T rs = T(0);
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     if (c < w) {
@@ -164,32 +188,32 @@ __device__ __forceinline__ bool chol_diag16(T* A, int c0, int w, int l) {
         bad = true;
         piv = T(1);
       }
-      const T s = sqrt(piv), is = T(1) / s;
-      d[c] = l == c ? s : (l > c ? d[c] * is : d[c]);
+      const T y = rsqrt_refined(piv);
+      if (l == c) rs = y;
+      d[c] = l == c ? piv * y : d[c] * y;
 #pragma unroll
-      for (int j = c + 1; j < 16; ++j) {
-        const T ljc = wave_bcast(d[c], j);
-        if (l >= j) d[j] -= d[c] * ljc;
-      }
+      for (int j = c + 1; j < 16; ++j) d[j] = fma(-d[c], wave_bcast(d[c], j), d[j]);
     }
   }
 #pragma unroll
   for (int j = 0; j < 16; ++j)
     if (l < w && j <= l) A[pk(i, c0 + j)] = d[j];
+  if (l < w) rd[l] = rs;
   return bad;
 }
 
 // Rows c0 + w .. N - 1 of the panel: L_21 = A_21 L_11^{-T} with the factored
-// diagonal block L_11, one row per lane (its w entries in registers).
+// diagonal block L_11 and the reciprocals of its diagonal rd (LDS), one row
+// per lane (its w entries in registers).
 template <class T, int N, int TEAM>
-__device__ __forceinline__ void chol_panel_rows(T* A, int c0, int w, int lane) {
+__device__ __forceinline__ void chol_panel_rows(T* A, const T* rd, int c0, int w, int lane) {
   for (int i = c0 + w + lane; i < N; i += TEAM) {
     T* Ai = A + i * (i + 1) / 2 + c0;
     T x[16], r[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       x[c] = c < w ? Ai[c] : T(0);
-      r[c] = c < w ? T(1) / A[pk(c0 + c, c0 + c)] : T(0);
+      r[c] = c < w ? rd[c] : T(0);
     }
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
@@ -212,18 +236,19 @@ __device__ __forceinline__ void chol_panel_rows(T* A, int c0, int w, int lane) {
 // wave, the rows below it one per lane, and the trailing update of every
 // lower tile (I, J) as C -= L_I L_J^T over the panel on the FP64 matrix
 // cores (four v_mfma_f64_16x16x4 per tile; the team's waves share out the
-// tiles; each trailing entry belongs to one tile).
+// tiles; each trailing entry belongs to one tile).  rd: 16 doubles of team
+// LDS.
 template <int N, int TEAM>
-__device__ __forceinline__ bool chol_packed_mfma(double* A, int lane) {
+__device__ __forceinline__ bool chol_packed_mfma(double* A, int lane, double* rd) {
   constexpr int NB = 16, NT = (N + 15) / 16, NW = TEAM / 64;
   static_assert(TEAM % 64 == 0, "whole waves per team");
   const int w_id = lane / 64, l = lane % 64, li = l % 16, lc = l / 16;
   bool bad = false;
   for (int c0 = 0; c0 < N; c0 += NB) {
     const int w = N - c0 < NB ? N - c0 : NB;
-    if (w_id == 0) bad |= chol_diag16(A, c0, w, l);
+    if (w_id == 0) bad |= chol_diag16(A, rd, c0, w, l);
     __syncthreads();
-    chol_panel_rows<double, N, TEAM>(A, c0, w, lane);
+    chol_panel_rows<double, N, TEAM>(A, rd, c0, w, lane);
     __syncthreads();
     // trailing tiles I >= J >= T0 (c0 + w = 16 T0 except after the last panel,
     // which leaves none)
@@ -270,10 +295,11 @@ __device__ __forceinline__ bool chol_packed_mfma(double* A, int lane) {
 // entry once per panel.  In the trailing update S = TEAM / N lanes share a
 // row and each keeps the row's NB panel entries in registers.  Returns true
 // (in every lane) when a pivot was not positive (replaced by 1).  FP64 on
-// LDS with teams of whole waves takes chol_packed_mfma.
+// LDS with teams of whole waves takes chol_packed_mfma (rd: 16 T of team LDS
+// for it).
 template <class T, int N, int TEAM>
-__device__ __forceinline__ bool chol_packed(T* A, int lane) {
-  if constexpr (std::is_same<T, double>::value && TEAM % 64 == 0 && N >= 32) return chol_packed_mfma<N, TEAM>(A, lane);
+__device__ __forceinline__ bool chol_packed(T* A, int lane, T* rd) {
+  if constexpr (std::is_same<T, double>::value && TEAM % 64 == 0 && N >= 32) return chol_packed_mfma<N, TEAM>(A, lane, rd);
   constexpr int NB = N >= 64 ? 8 : 4;
   constexpr int S = TEAM / N > 0 ? TEAM / N : 1;
   bool bad = false;
@@ -642,7 +668,8 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       static_assert(Lay::stage >= 32 * (n | 1), "the panel fits in the staging area");
       notspd = chol_hbm32<n, TEAM>(A, stg, lane, own);
     } else {
-      notspd = chol_packed<double, n, TEAM>(A, lane);
+      static_assert(TEAM % 64 != 0 || n < 32 || Lay::stage >= 16, "the pivots' reciprocals fit in the staging area");
+      notspd = chol_packed<double, n, TEAM>(A, lane, stg);
     }
     if (notspd && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
     __syncthreads();

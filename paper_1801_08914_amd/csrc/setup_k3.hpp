@@ -131,7 +131,7 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       }
     }
     // L_ii = chol(A_ii) in LDS; the inverses of its diagonal blocks
-    const bool bad_i = chol_mfma_t<double, ni, TEAM>(A, lane, true, flag);
+    const bool bad_i = chol_mfma_t<double, ni, TEAM>(A, lane, true, flag, stg);
     auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
     diag_inverses<double, ni, TEAM>(Lii, stg, lane, true);
     __syncthreads();
@@ -174,7 +174,7 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       }
     }
     // L_bb = chol(S) in LDS
-    const bool bad_b = chol_mfma_t<double, nb, TEAM>(Sb, lane, true, flag);
+    const bool bad_b = chol_mfma_t<double, nb, TEAM>(Sb, lane, true, flag, Sb + R::nbpk);
     if ((bad_i || bad_b) && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
     // L_ii back to the record (its packed rows lead the record)
     for (int t = lane; t < Lay::npi; t += TEAM)
