@@ -14,6 +14,36 @@ __device__ __forceinline__ dx4 mfma16x16x4(double a, double b, dx4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+// 16 x 16 x 4 matrix-core step D = A B + C on one wave for FP32 and FP64:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element r of
+// lane l's result is D[row(l, r)][l % 16] (both layouts measured on the
+// device: FP32 rows 4 (l / 16) + r, FP64 rows l / 16 + 4 r).
+template <class T>
+struct MfmaT;
+template <>
+struct MfmaT<float> {
+  using v4 = fx4;
+  __device__ static v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct MfmaT<double> {
+  using v4 = dx4;
+  __device__ static v4 op(double a, double b, v4 c) { return mfma16x16x4(a, b, c); }
+  __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+// Makes the wave's earlier LDS and global stores visible to its later loads
+// (other lanes of the same wave) without a block barrier: work that one wave
+// owns.  Workgroup-scope fences wait for the stores to complete.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // index of the symmetric 3x3 pair (d, e) in (00, 01, 02, 11, 12, 22)
 __device__ __forceinline__ int gidx(int d, int e) {
   int lo = d < e ? d : e, hi = d < e ? e : d;

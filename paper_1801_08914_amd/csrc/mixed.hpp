@@ -29,90 +29,14 @@
 
 namespace hyb {
 
-typedef float fx4 __attribute__((ext_vector_type(4)));
-
-// 16 x 16 x 4 matrix-core step D = A B + C on one wave for FP32 and FP64:
-// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element r of
-// lane l's result is D[row(l, r)][l % 16] (both layouts measured on the
-// device: FP32 rows 4 (l / 16) + r, FP64 rows l / 16 + 4 r).
-template <class T>
-struct MfmaT;
-template <>
-struct MfmaT<float> {
-  using v4 = fx4;
-  __device__ static v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
-};
-template <>
-struct MfmaT<double> {
-  using v4 = dx4;
-  __device__ static v4 op(double a, double b, v4 c) { return mfma16x16x4(a, b, c); }
-  __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
-};
-
-// Makes the wave's earlier LDS and global stores visible to its later loads
-// (other lanes of the same wave) without a block barrier: work that one wave
-// owns.  Workgroup-scope fences wait for the stores to complete.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// Packed lower Cholesky factorization in place in LDS (teams of whole waves)
-// by panels of 16 columns: the diagonal block on one wave (registers and wave
-// broadcasts), the rows below it one per lane, the trailing lower 16 x 16
-// tiles on the matrix cores of T.  With active false the team only takes
-// part in the barriers.  Returns true in every lane of the team when a pivot
-// was not positive (replaced by 1); flag: one int of team LDS, rd: 16 T of
-// team LDS.
+// chol_tiles16 with the result in every lane of the team: true when a pivot
+// was not positive (replaced by 1).  With active false the team only takes
+// part in the barriers.  flag: one int of team LDS, rd: 16 T of team LDS.
 template <class T, int N, int TEAM>
 __device__ __forceinline__ bool chol_mfma_t(T* A, int lane, bool active, int* flag, T* rd) {
-  using M = MfmaT<T>;
-  constexpr int NB = 16, NT = (N + 15) / 16, NW = TEAM / 64;
-  static_assert(TEAM % 64 == 0, "whole waves per team");
-  const int w_id = lane / 64, l = lane % 64, li = l % 16, lc = l / 16;
   __syncthreads();
   if (lane == 0) *flag = 0;
-  bool bad = false;
-  for (int c0 = 0; c0 < N; c0 += NB) {
-    const int w = N - c0 < NB ? N - c0 : NB;
-    if (active && w_id == 0) bad |= chol_diag16(A, rd, c0, w, l);
-    __syncthreads();
-    if (active) chol_panel_rows<T, N, TEAM>(A, rd, c0, w, lane);
-    __syncthreads();
-    const int T0 = (c0 + w + 15) / 16, m = NT - T0;
-    for (int t = active ? w_id : (1 << 30); t < m * (m + 1) / 2; t += NW) {
-      int I = 0;
-      while ((I + 1) * (I + 2) / 2 <= t) ++I;
-      const int J = T0 + (t - I * (I + 1) / 2);
-      I += T0;
-      typename M::v4 acc;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * I + M::row(l, r), j = 16 * J + li;
-        const bool in = i < N && j <= i;
-        const T v = A[in ? pk(i, j) : 0];
-        acc[r] = in ? v : T(0);
-      }
-      const int ia = 16 * I + li, jb = 16 * J + li;
-      // operand loads at clamped (valid) addresses, masked values: no
-      // lane-dependent branches around the loads
-      const int iac = ia < N ? ia : N - 1, jbc = jb < N ? jb : N - 1;
-#pragma unroll
-      for (int kk = 0; kk < NB / 4; ++kk) {
-        const int q = 4 * kk + lc, qc = q < w ? q : w - 1;
-        const T av = A[pk(iac, c0 + qc)], bv = A[pk(jbc, c0 + qc)];
-        acc = M::op((ia < N && q < w) ? -av : T(0), (jb < N && q < w) ? bv : T(0), acc);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * I + M::row(l, r), j = 16 * J + li;
-        if (i < N && j <= i) A[pk(i, j)] = acc[r];
-      }
-    }
-    __syncthreads();
-  }
+  const bool bad = chol_tiles16<T, N, TEAM>(A, rd, lane, active);
   if (active && lane == 0 && bad) *flag = 1;
   __syncthreads();
   const bool out = *flag != 0;

@@ -158,23 +158,54 @@ __device__ __forceinline__ float rsqrt_refined(float x) {
   return fmaf(0.5f * y, e, y);
 }
 
+// Lane J's value of v in every lane of its row of 16 lanes (DPP
+// row_newbcast: one instruction for 32- and 64-bit values, the result in a
+// vector register).  row_bcast takes j as an argument for unrolled loops, where
+// it is a constant.
+template <int J, class T>
+__device__ __forceinline__ T row_bcast_t(T v) {
+  return __builtin_amdgcn_update_dpp(T(0), v, 0x150 + J, 0xf, 0xf, true);
+}
+template <class T>
+__device__ __forceinline__ T row_bcast(T v, int j) {
+  switch (j) {
+    case 0: return row_bcast_t<0>(v);
+    case 1: return row_bcast_t<1>(v);
+    case 2: return row_bcast_t<2>(v);
+    case 3: return row_bcast_t<3>(v);
+    case 4: return row_bcast_t<4>(v);
+    case 5: return row_bcast_t<5>(v);
+    case 6: return row_bcast_t<6>(v);
+    case 7: return row_bcast_t<7>(v);
+    case 8: return row_bcast_t<8>(v);
+    case 9: return row_bcast_t<9>(v);
+    case 10: return row_bcast_t<10>(v);
+    case 11: return row_bcast_t<11>(v);
+    case 12: return row_bcast_t<12>(v);
+    case 13: return row_bcast_t<13>(v);
+    case 14: return row_bcast_t<14>(v);
+    default: return row_bcast_t<15>(v);
+  }
+}
+
 // The w x w (w <= 16) diagonal block at (c0, c0) of a packed lower triangle,
-// factored on one wave: lane l < w holds row c0 + l in registers, pivots and
-// column entries come by wave broadcast (no barrier).  Each pivot costs one
-// refined reciprocal square root: L_cc = p / sqrt(p), the column below it
-// scaled by 1 / sqrt(p), which also goes to rd[c] (LDS, for the rows below the
-// block).  The updates run unmasked: a lane's entries right of its diagonal
-// take values that are never read or stored.  A non-positive pivot is
-// replaced by 1 and reported.
+// factored on one wave: lane l holds row c0 + l % 16 in registers (the four
+// rows of 16 lanes compute the same), pivots and column entries come by row
+// broadcast (no barrier, no scalar registers).  Each pivot costs one refined
+// reciprocal square root: L_cc = p / sqrt(p), the column below it scaled by
+// 1 / sqrt(p), which also goes to rd[c] (LDS, for the rows below the block).
+// The updates run unmasked: a lane's entries right of its diagonal take
+// values that are never read or stored.  A non-positive pivot is replaced by
+// 1 and reported (in every lane of the wave).
 template <class T>
 __device__ __forceinline__ bool chol_diag16(T* A, T* rd, int c0, int w, int l) {
   T d[16];
-  const int i = c0 + l;
+  const int r = l & 15, i = c0 + r;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     // every lane loads (a valid address), then keeps its own entries: no
     // lane-dependent branch around the loads
-    const bool in = l < w && j <= l;
+    const bool in = r < w && j <= r;
     const T v = A[in ? pk(i, c0 + j) : pk(c0, c0)];
     d[j] = in ? v : T(0);
   }
@@ -183,16 +214,16 @@ __device__ __forceinline__ bool chol_diag16(T* A, T* rd, int c0, int w, int l) {
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     if (c < w) {
-      T piv = wave_bcast(d[c], c);
+      T piv = row_bcast(d[c], c);
       if (!(piv > T(0))) {
         bad = true;
         piv = T(1);
       }
       const T y = rsqrt_refined(piv);
-      if (l == c) rs = y;
-      d[c] = l == c ? piv * y : d[c] * y;
+      if (r == c) rs = y;
+      d[c] = r == c ? piv * y : d[c] * y;
 #pragma unroll
-      for (int j = c + 1; j < 16; ++j) d[j] = fma(-d[c], wave_bcast(d[c], j), d[j]);
+      for (int j = c + 1; j < 16; ++j) d[j] = fma(-d[c], row_bcast(d[c], j), d[j]);
     }
   }
 #pragma unroll
@@ -202,89 +233,112 @@ __device__ __forceinline__ bool chol_diag16(T* A, T* rd, int c0, int w, int l) {
   return bad;
 }
 
-// Rows c0 + w .. N - 1 of the panel: L_21 = A_21 L_11^{-T} with the factored
-// diagonal block L_11 and the reciprocals of its diagonal rd (LDS), one row
-// per lane (its w entries in registers).
+// Rows c0 + 16 .. N - 1 of a full-width panel: L_21 = A_21 L_11^{-T} with
+// the factored diagonal block L_11 and the reciprocals of its diagonal rd
+// (LDS), one row per lane (its 16 entries in registers).  Column by column:
+// entry c is finished, then taken off the entries after it, so the dependent
+// chain is one multiply-add per column (the operations per entry, and their
+// order, those of the dot-product form).
 template <class T, int N, int TEAM>
-__device__ __forceinline__ void chol_panel_rows(T* A, const T* rd, int c0, int w, int lane) {
-  for (int i = c0 + w + lane; i < N; i += TEAM) {
+__device__ __forceinline__ void chol_panel_rows(T* A, const T* rd, int c0, int lane) {
+  for (int i = c0 + 16 + lane; i < N; i += TEAM) {
     T* Ai = A + i * (i + 1) / 2 + c0;
-    T x[16], r[16];
+    T x[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) x[c] = Ai[c];
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      x[c] = c < w ? Ai[c] : T(0);
-      r[c] = c < w ? rd[c] : T(0);
+      x[c] *= rd[c];
+#pragma unroll
+      for (int j = c + 1; j < 16; ++j) x[j] -= x[c] * A[pk(c0 + j, c0 + c)];
     }
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      if (c < w) {
-        const T* Lc = A + pk(c0 + c, c0);
-        T s = x[c];
-#pragma unroll
-        for (int q = 0; q < c; ++q) s -= x[q] * Lc[q];
-        x[c] = s * r[c];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (c < w) Ai[c] = x[c];
+    for (int c = 0; c < 16; ++c) Ai[c] = x[c];
   }
 }
 
-// The FP64 form for LDS-resident matrices and teams of whole waves, by panels
-// of 16 columns aligned with 16 x 16 tiles: the panel's diagonal block on one
-// wave, the rows below it one per lane, and the trailing update of every
-// lower tile (I, J) as C -= L_I L_J^T over the panel on the FP64 matrix
-// cores (four v_mfma_f64_16x16x4 per tile; the team's waves share out the
-// tiles; each trailing entry belongs to one tile).  rd: 16 doubles of team
-// LDS.
-template <int N, int TEAM>
-__device__ __forceinline__ bool chol_packed_mfma(double* A, int lane, double* rd) {
+// Packed lower Cholesky factorization in place in LDS, teams of whole waves,
+// right-looking by panels of 16 columns aligned with 16 x 16 tiles: the
+// panel's diagonal block on one wave (chol_diag16), the rows below it one
+// per lane, and the trailing update of every lower tile (I, J) as
+// C -= L_I L_J^T over the panel on the matrix cores of T (four 16 x 16 x 4
+// steps per tile; each trailing entry belongs to one tile).  Look-ahead: of
+// the trailing tiles, wave 0 takes the next diagonal tile and then factors it
+// while the other waves update the rest, so each panel costs two barriers and
+// the diagonal blocks (a serial chain of 16 pivots) overlap the updates.  A
+// panel with rows below it is full width (only the last may be narrower).
+// With active false the team only takes part in the barriers.  rd: 16 T of
+// team LDS.  Returns true in the lanes of wave 0 when a pivot was not
+// positive (replaced by 1).
+template <class T, int N, int TEAM>
+__device__ __forceinline__ bool chol_tiles16(T* A, T* rd, int lane, bool active) {
+  using M = MfmaT<T>;
   constexpr int NB = 16, NT = (N + 15) / 16, NW = TEAM / 64;
   static_assert(TEAM % 64 == 0, "whole waves per team");
   const int w_id = lane / 64, l = lane % 64, li = l % 16, lc = l / 16;
   bool bad = false;
-  for (int c0 = 0; c0 < N; c0 += NB) {
-    const int w = N - c0 < NB ? N - c0 : NB;
-    if (w_id == 0) bad |= chol_diag16(A, rd, c0, w, l);
+  __syncthreads();
+  if (active && w_id == 0) bad |= chol_diag16(A, rd, 0, N < NB ? N : NB, l);
+  __syncthreads();
+  for (int K = 0; K + 1 < NT; ++K) {
+    const int c0 = NB * K;
+    if (active) chol_panel_rows<T, N, TEAM>(A, rd, c0, lane);
     __syncthreads();
-    chol_panel_rows<double, N, TEAM>(A, rd, c0, w, lane);
-    __syncthreads();
-    // trailing tiles I >= J >= T0 (c0 + w = 16 T0 except after the last panel,
-    // which leaves none)
-    const int T0 = (c0 + w + 15) / 16, m = NT - T0;
-    for (int t = w_id; t < m * (m + 1) / 2; t += NW) {
+    // trailing tiles (I, J), K < J <= I < NT, numbered row by row from (K + 1, K + 1)
+    const int T0 = K + 1, m = NT - T0;
+    auto tile = [&](int t) {
       int I = 0;
       while ((I + 1) * (I + 2) / 2 <= t) ++I;
       const int J = T0 + (t - I * (I + 1) / 2);
       I += T0;
-      dx4 acc;
+      typename M::v4 acc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * I + lc + 4 * r, j = 16 * J + li;
+        const int i = 16 * I + M::row(l, r), j = 16 * J + li;
         const bool in = i < N && j <= i;
-        const double v = A[in ? pk(i, j) : 0];
-        acc[r] = in ? v : 0.0;
+        const T v = A[in ? pk(i, j) : 0];
+        acc[r] = in ? v : T(0);
       }
-      const int ia = 16 * I + li, jb = 16 * J + li;
       // operand loads at clamped (valid) addresses, masked values: no
-      // lane-dependent branches
+      // lane-dependent branches around the loads
+      const int ia = 16 * I + li, jb = 16 * J + li;
       const int iac = ia < N ? ia : N - 1, jbc = jb < N ? jb : N - 1;
 #pragma unroll
       for (int kk = 0; kk < NB / 4; ++kk) {
-        const int q = 4 * kk + lc, qc = q < w ? q : w - 1;
-        const double av = A[pk(iac, c0 + qc)], bv = A[pk(jbc, c0 + qc)];
-        acc = mfma16x16x4((ia < N && q < w) ? -av : 0.0, (jb < N && q < w) ? bv : 0.0, acc);
+        const int q = c0 + 4 * kk + lc;
+        const T av = A[pk(iac, q)], bv = A[pk(jbc, q)];
+        acc = M::op(ia < N ? -av : T(0), jb < N ? bv : T(0), acc);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 16 * I + lc + 4 * r, j = 16 * J + li;
+        const int i = 16 * I + M::row(l, r), j = 16 * J + li;
         if (i < N && j <= i) A[pk(i, j)] = acc[r];
+      }
+    };
+    const int c1 = c0 + NB, w1 = N - c1 < NB ? N - c1 : NB;
+    if (active) {
+      if (NW == 1) {
+        for (int t = 0; t < m * (m + 1) / 2; ++t) tile(t);
+        wave_sync();
+        bad |= chol_diag16(A, rd, c1, w1, l);
+      } else if (w_id == 0) {
+        tile(0);
+        wave_sync();
+        bad |= chol_diag16(A, rd, c1, w1, l);
+      } else {
+        for (int t = w_id; t < m * (m + 1) / 2; t += NW - 1) tile(t);
       }
     }
     __syncthreads();
   }
   return bad;
+}
+
+// The FP64 form for LDS-resident matrices and teams of whole waves
+// (chol_tiles16).  rd: 16 doubles of team LDS.
+template <int N, int TEAM>
+__device__ __forceinline__ bool chol_packed_mfma(double* A, int lane, double* rd) {
+  return chol_tiles16<double, N, TEAM>(A, rd, lane, true);
 }
 
 // Packed lower Cholesky factorization in place (LDS or global), right-
