@@ -159,20 +159,19 @@ __device__ __forceinline__ void tile_solve(LAcc L, const T* Linv, WAcc W, int c0
 // the FP64 matrix-core result layout (rows l/16 + 4r of column l % 16) is the
 // layout of the B operand at k-step r (rows 4r + l/16), so a solved 16-row
 // block feeds the next blocks' products straight from its accumulator, and
-// the tile touches memory only when it is loaded and stored.  load(i, c) /
-// store(i, c, v) read and write the tile (i < N, c < c0 + ncol); L(i, j) is
-// the factor (j <= i < N, LDS) and Linv its diagonal blocks' inverses.  The
-// tile's row blocks before I0 are zero (and stay so), and are skipped.
-template <int N, class LAcc, class Load, class Store>
-__device__ __forceinline__ void tile_forward_reg(LAcc L, const double* Linv, Load load, Store store, int c0, int ncol,
-                                                 int l, int I0 = 0) {
+// the tile touches memory only when it is loaded.  load(i, c) reads the tile
+// (i < N, c < c0 + ncol); L(i, j) is the factor (j <= i < N, LDS) and Linv
+// its diagonal blocks' inverses.  The tile's row blocks before I0 are zero
+// (and stay so), and are skipped.  On return X[I][r] holds row 16 I + l/16 +
+// 4 r of column c0 + l % 16 (zero past N and for columns past ncol).
+template <int N, class LAcc, class Load>
+__device__ __forceinline__ void tile_forward_regs(LAcc L, const double* Linv, Load load, dx4 (&X)[(N + 15) / 16], int c0,
+                                                  int ncol, int l, int I0 = 0) {
   using M = MfmaT<double>;
   constexpr int NT = (N + 15) / 16;
   const int li = l & 15, lk = l >> 4;
-  const int c = c0 + li;
   const bool cok = li < ncol;
-  const int cc = cok ? c : c0;
-  dx4 X[NT];
+  const int cc = cok ? c0 + li : c0;
 #pragma unroll
   for (int I = 0; I < NT; ++I)
 #pragma unroll
@@ -199,12 +198,24 @@ __device__ __forceinline__ void tile_forward_reg(LAcc L, const double* Linv, Loa
     for (int s = 0; s < 4; ++s) x = M::op(Linv[256 * I + 16 * li + 4 * s + lk], acc[s], x);
     X[I] = x;
   }
+}
+
+// tile_forward_regs with the result stored through store(i, c, v) (i < N,
+// c < c0 + ncol).
+template <int N, class LAcc, class Load, class Store>
+__device__ __forceinline__ void tile_forward_reg(LAcc L, const double* Linv, Load load, Store store, int c0, int ncol,
+                                                 int l, int I0 = 0) {
+  using M = MfmaT<double>;
+  constexpr int NT = (N + 15) / 16;
+  dx4 X[NT];
+  tile_forward_regs<N>(L, Linv, load, X, c0, ncol, l, I0);
+  const int li = l & 15;
 #pragma unroll
   for (int I = 0; I < NT; ++I)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * I + M::row(l, r);
-      if (cok && i < N) store(i, c, X[I][r]);
+      if (li < ncol && i < N) store(i, c0 + li, X[I][r]);
     }
 }
 

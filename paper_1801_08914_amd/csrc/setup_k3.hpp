@@ -27,8 +27,13 @@ struct K3Layout {
   static constexpr int stage0 = sumfact_stage<3>();
   static constexpr int stage1 = ((ni + 15) / 16) * 256;
   static constexpr int stage2 = R::nbpk + (nb / 16) * 256;   // L_bb and its diagonal blocks' inverses
-  static_assert(nb * nb <= npi, "the full inverse of L_bb fits where L_ii was");
+  // row strides of L_bb^{-1} (nb + 1: a lane per row reads conflict-free) and
+  // of L_bi^T (rows of the four lane groups 32 banks apart)
+  static constexpr int XLD = nb + 1, LDE = nb + 16;
+  static_assert(nb * XLD <= npi, "the full inverse of L_bb fits where L_ii was");
   static constexpr int stage = stage0 > stage1 ? (stage0 > stage2 ? stage0 : stage2) : (stage1 > stage2 ? stage1 : stage2);
+  static_assert(ni % 16 == 0 && nb % 16 == 0, "whole 16-row blocks");
+  static_assert(ni * LDE <= npi + stage, "L_bi^T fits where L_ii and the staging area were");
   static constexpr int per = npi + stage + R::Q * 10 + n + 24 + nb + 8;
 };
 
@@ -52,11 +57,16 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
   int* flag = reinterpret_cast<int*>(tb + nb);
   double* rec = a.factor + es * R::npk;   // the packed factor of the element (HBM)
   double* Sb = stg;                       // S, then L_bb (packed nb x nb)
-  double* Xb = A;                         // L_bb^{-1}, full nb x nb row-major (setup)
+  double* Xb = A;                         // L_bb^{-1}, full nb x nb, rows XLD apart (setup)
+  double* E = A;                          // L_bi^T, rows LDE apart (setup, before S is factored)
+  using M = MfmaT<double>;
+  constexpr int NTi = ni / 16;
+  const int li = l & 15, lk = l >> 4;
+  const bool tw = w_id < nb / 16;         // the waves of the column tiles of L_bi^T and L_bb^{-1}
   const DeviceMaps& mp = a.mp;
   const bool matrix = (a.mode & MODE_MATRIX) != 0, rhs = (a.mode & MODE_RHS) != 0;
   // L_bb^{-1}: full in LDS after a setup, packed (from the record) for a right-hand side alone
-  auto LI = [&](int i, int j) -> double { return matrix ? Xb[i * nb + j] : Sb[pk(i, j)]; };
+  auto LI = [&](int i, int j) -> double { return matrix ? Xb[i * Lay::XLD + j] : Sb[pk(i, j)]; };
 
   int fid[6], pic[6];
 #pragma unroll
@@ -73,6 +83,21 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     const int f = b / K2;
     const double eps = (f & 1) ? 1.0 : -1.0;
     return mp.face_owner[fid[f]] == e ? eps : -eps;
+  };
+
+  // tb = f_b - L_bi y_i on the face rows of one column tile (the calling
+  // wave's, 16 w_id ..) from the tile of L_bi^T in registers: per lane the
+  // products over its rows in register order, then the sum over the lanes
+  // of the column (the same order in a setup and for a right-hand side alone)
+  auto lbi_yi = [&](const dx4(&X)[NTi]) {
+    double p = 0.0;
+#pragma unroll
+    for (int I = 0; I < NTi; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) p += X[I][r] * fh[16 * I + M::row(l, r)];
+    p += __shfl_xor(p, 16);
+    p += __shfl_xor(p, 32);
+    if (lk == 0) tb[16 * w_id + li] = fh[ni + 16 * w_id + li] - p;
   };
 
   const double al = a.alpha ? a.alpha[es] : 0.0, be = a.beta ? a.beta[es] : 0.0;
@@ -135,25 +160,46 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
     diag_inverses<double, ni, TEAM>(Lii, stg, lane, true);
     __syncthreads();
-    // L_bi^T = L_ii^{-1} A_bi^T by forward tile solves held in registers, on
-    // the record's face rows (column c of the tile is face row ni + c): six
-    // column tiles over the waves, and y_i = L_ii^{-1} f_i as a seventh
-    // (one column) while L_ii is in LDS
-    if (w_id < nb / 16) {
-      if (own)
-        tile_forward_reg<ni>(Lii, stg, [&](int i, int c) { return rec[pk(ni + c, i)]; },
-                             [&](int i, int c, double v) { rec[pk(ni + c, i)] = v; }, 16 * w_id, 16, l);
+    // L_bi^T = L_ii^{-1} A_bi^T by forward tile solves held in registers (the
+    // record's face rows: column c of the tile is face row ni + c), six
+    // column tiles over the waves, stored to the record and kept; y_i =
+    // L_ii^{-1} f_i as a seventh (one column) while L_ii is in LDS
+    dx4 Xr[NTi];
+    if (tw) {
+      tile_forward_regs<ni>(Lii, stg, [&](int i, int c) { return rec[pk(ni + c, i)]; }, Xr, 16 * w_id, 16, l);
+#pragma unroll
+      for (int I = 0; I < NTi; ++I)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (own) rec[pk(ni + 16 * w_id + li, 16 * I + M::row(l, r))] = Xr[I][r];
     } else if (w_id == nb / 16 && rhs) {
       tile_forward_reg<ni>(Lii, stg, [&](int i, int) { return fh[i]; }, [&](int i, int, double v) { fh[i] = v; }, 0, 1,
                            l);
     }
     __syncthreads();
-    // S = A_bb - L_bi L_bi^T (lower 16 x 16 tiles on the FP64 matrix cores)
+    // L_ii back to the record; then L_bi^T from the registers into LDS where
+    // L_ii was (E[k * LDE + c] = L_bi(c, k)), and f_b - L_bi y_i
+    for (int t = lane; t < Lay::npi; t += TEAM)
+      if (own) rec[t] = A[t];
+    __syncthreads();
+    if (tw) {
+#pragma unroll
+      for (int I = 0; I < NTi; ++I)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) E[(16 * I + M::row(l, r)) * Lay::LDE + 16 * w_id + li] = Xr[I][r];
+      if (rhs) lbi_yi(Xr);
+    }
+    __syncthreads();
+    // S = A_bb - L_bi L_bi^T: the 21 lower 16 x 16 tiles over the waves on the
+    // FP64 matrix cores, operands from E; the accumulators stay in registers
+    // until every wave is done with E (S goes where E ends)
     {
-      using M = MfmaT<double>;
-      constexpr int NT = nb / 16;
-      const int li = l & 15, lk = l >> 4;
-      for (int t = w_id; t < NT * (NT + 1) / 2; t += NW) {
+      constexpr int NT = nb / 16, NS = NT * (NT + 1) / 2, SU = (NS + NW - 1) / NW;
+      dx4 Sacc[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int t = w_id + NW * u;
+        if (t >= NS) continue;   // uniform
         int I = 0;
         while ((I + 1) * (I + 2) / 2 <= t) ++I;
         const int J = t - I * (I + 1) / 2;
@@ -163,22 +209,30 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
           const int i = 16 * I + M::row(l, r), j = 16 * J + li;
           acc[r] = j <= i ? rec[pk(ni + i, ni + j)] : 0.0;
         }
-        const double* ra = rec + pk(ni + 16 * I + li, 0);
-        const double* rb = rec + pk(ni + 16 * J + li, 0);
-        for (int q0 = 0; q0 < ni; q0 += 4) acc = M::op(-ra[q0 + lk], rb[q0 + lk], acc);
+        const double* ea = E + lk * Lay::LDE + 16 * I + li;
+        const double* eb = E + lk * Lay::LDE + 16 * J + li;
+#pragma unroll 4
+        for (int k0 = 0; k0 < ni; k0 += 4) acc = M::op(-ea[k0 * Lay::LDE], eb[k0 * Lay::LDE], acc);
+        Sacc[u] = acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int t = w_id + NW * u;
+        if (t >= NS) continue;
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        const int J = t - I * (I + 1) / 2;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 16 * I + M::row(l, r), j = 16 * J + li;
-          if (j <= i) Sb[pk(i, j)] = acc[r];
+          if (j <= i) Sb[pk(i, j)] = Sacc[u][r];
         }
       }
     }
     // L_bb = chol(S) in LDS
     const bool bad_b = chol_mfma_t<double, nb, TEAM>(Sb, lane, true, flag, Sb + R::nbpk);
     if ((bad_i || bad_b) && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
-    // L_ii back to the record (its packed rows lead the record)
-    for (int t = lane; t < Lay::npi; t += TEAM)
-      if (own) rec[t] = A[t];
     if (a.stat) {
       // static condensation: S_hat_T = L_bb L_bb^T (lower triangle), sigma-signed, into S
       auto Lbb = [&](int i, int j) { return Sb[pk(i, j)]; };
@@ -222,19 +276,17 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       double* LiB = Sb + R::nbpk;
       auto Lbb = [&](int i, int j) -> double { return Sb[pk(i, j)]; };
       diag_inverses<double, nb, TEAM>(Lbb, LiB, lane, true);
-      __syncthreads();   // L_ii is in the record
-      if (w_id < nb / 16)
+      __syncthreads();
+      if (tw)
         tile_forward_reg<nb>(Lbb, LiB, [&](int i, int c) { return i == c ? 1.0 : 0.0; },
-                             [&](int i, int c, double v) { Xb[i * nb + c] = v; }, 16 * w_id, 16, l, w_id);
+                             [&](int i, int c, double v) { Xb[i * Lay::XLD + c] = v; }, 16 * w_id, 16, l, w_id);
       __syncthreads();
       // H_T = D L_bb^{-T} L_bb^{-1} D: the lower 16 x 16 tiles of X^T X on the
       // FP64 matrix cores (X lower triangular: the sum starts at row block I),
       // scattered into H from the accumulators (same-face blocks receive two
       // element terms by atomic add; the mirror entry written as well)
       {
-        using M = MfmaT<double>;
         constexpr int NT = nb / 16;
-        const int li = l & 15, lk = l >> 4;
         for (int t = w_id; t < NT * (NT + 1) / 2; t += NW) {
           int I = 0;
           while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -242,7 +294,7 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
           dx4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
           for (int c0 = 16 * I; c0 < nb; c0 += 4)
-            acc = M::op(Xb[(c0 + lk) * nb + 16 * I + li], Xb[(c0 + lk) * nb + 16 * J + li], acc);
+            acc = M::op(Xb[(c0 + lk) * Lay::XLD + 16 * I + li], Xb[(c0 + lk) * Lay::XLD + 16 * J + li], acc);
           if (!live) continue;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -274,13 +326,14 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       for (int t = lane; t < R::nbpk; t += TEAM) {
         int i, j;
         unpk(t, i, j);
-        if (own) rec[pk(ni + i, ni + j)] = Xb[i * nb + j];
+        if (own) rec[pk(ni + i, ni + j)] = Xb[i * Lay::XLD + j];
       }
       __syncthreads();
     }
   } else if (rhs) {
-    // a right-hand side alone: y_i = L_ii^{-1} f_i from the stored L_ii, as
-    // the setup computes it, then the stored face block into LDS
+    // a right-hand side alone: y_i = L_ii^{-1} f_i from the stored L_ii and
+    // f_b - L_bi y_i from the stored L_bi, as the setup computes them, then
+    // the stored face block into LDS
     for (int t = lane; t < Lay::npi; t += TEAM) A[t] = rec[t];
     __syncthreads();
     auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
@@ -290,6 +343,14 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       tile_forward_reg<ni>(Lii, stg, [&](int i, int) { return fh[i]; }, [&](int i, int, double v) { fh[i] = v; }, 0, 1,
                            l);
     __syncthreads();
+    if (tw) {
+      dx4 Xr[NTi];
+#pragma unroll
+      for (int I = 0; I < NTi; ++I)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xr[I][r] = rec[pk(ni + 16 * w_id + li, 16 * I + M::row(l, r))];
+      lbi_yi(Xr);
+    }
     for (int t = lane; t < R::nbpk; t += TEAM) {
       int i, j;
       unpk(t, i, j);
@@ -299,15 +360,8 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
   }
 
   if (rhs) {
-    // y_b = L_bb^{-1} (f_b - L_bi y_i)
-    for (int b = lane; b < nb; b += TEAM) {
-      const double* rb = rec + pk(ni + b, 0);
-      double s = fh[ni + b];
-      for (int j = 0; j < ni; ++j) s -= rb[j] * fh[j];
-      tb[b] = s;
-    }
-    __syncthreads();
-    // static condensation keeps f_b - L_bi y_i (on boundary faces: their data g)
+    // y_b = L_bb^{-1} (f_b - L_bi y_i); static condensation keeps
+    // f_b - L_bi y_i (on boundary faces: their data g)
     for (int b = lane; b < nb; b += TEAM) {
       double s = tb[b];
       if (!a.stat) {
