@@ -6,6 +6,9 @@
 namespace hyb {
 
 typedef double dx4 __attribute__((ext_vector_type(4)));
+// a double in LDS (address space 3), for stores the compiler must not turn
+// into flat ones
+typedef __attribute__((address_space(3))) double lds_double;
 
 // D = A B + C for a 16 x 4 block A and a 4 x 16 block B on one wave: lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element r of lane l's
@@ -143,24 +146,139 @@ __device__ __forceinline__ int dof_index(int d, int a0, int a1, int a2) {
 
 // Whether the element assembly of order k uses sum factorization.  It needs
 // about 1.1 Mflop per RT3 element against 14.4 for the dense Gram sum on the
-// matrix cores and is then much faster (measured 50 against about 370 us per
-// element in a workgroup); for k <= 2 the saving is small in absolute terms
-// (0.17 against 1.49 Mflop for RT2) and the dense sum's independent tiles hide
-// latency better than the sum factorization's 18 barrier-separated passes
-// (RT2 48^3 setup 37.5 ms dense against 49.9 ms factored).
+// matrix cores and is then much faster; for k <= 2 the saving is small in
+// absolute terms (0.17 against 1.49 Mflop for RT2) and the dense sum's
+// independent tiles keep the lanes busier (RT2 48^3 setup measured 37.5 ms
+// dense against 49.9 ms factored).
 template <int K>
 constexpr bool use_sumfact() { return K >= 3; }
 
-// LDS doubles used by assemble_sumfact: the 1D tables, then the axis-0 and
-// axis-1 partial sums of both terms.
+// The six component blocks (d, e), d <= e, of the sum-factorized assembly:
+// (0,0) (0,1) (0,2) (1,1) (1,2) (2,2).  Component d has np(d, x) 1D factors
+// along axis x (K + 2 closed ones on its own axis, K + 1 open ones on the
+// others).  Pass 1 (axis 0) has, per block, a task per (part, point pair
+// (q1, q2), a0) and writes S1[part][a0][b0][q1][q2]; pass 2 (axes 1 and 2)
+// has a task per (a0, b0, a1, b1).  Offsets into the LDS partial sums and the
+// task ranges are prefix sums over the blocks.
+template <int K>
+struct SfBlocks {
+  static constexpr int KC = K + 2, K1 = K + 1, q1 = K + 2;
+  static constexpr int d_of(int b) { return b < 3 ? 0 : (b < 5 ? 1 : 2); }
+  static constexpr int e_of(int b) { return b < 3 ? b : (b < 5 ? b - 2 : 2); }
+  static constexpr int np(int d, int x) { return d == x ? KC : K1; }
+  static constexpr int s1_size(int b) { return 2 * np(d_of(b), 0) * np(e_of(b), 0) * q1 * q1; }
+  static constexpr int t1_count(int b) { return 2 * q1 * q1 * np(d_of(b), 0); }
+  static constexpr int t2_count(int b) {
+    return np(d_of(b), 0) * np(e_of(b), 0) * np(d_of(b), 1) * np(e_of(b), 1);
+  }
+  static constexpr int s1_off(int b) { return b == 0 ? 0 : s1_off(b - 1) + s1_size(b - 1); }
+  static constexpr int t1_off(int b) { return b == 0 ? 0 : t1_off(b - 1) + t1_count(b - 1); }
+  static constexpr int t2_off(int b) { return b == 0 ? 0 : t2_off(b - 1) + t2_count(b - 1); }
+};
+
+// LDS doubles used by assemble_sumfact: the 1D tables, then the axis-0
+// partial sums of both terms for all six blocks.
 template <int K>
 constexpr int sumfact_tables() {
   return (2 * (K + 2) + (K + 1)) * (K + 2);
 }
 template <int K>
 constexpr int sumfact_stage() {
-  constexpr int KC = K + 2, K1 = K + 1, q1 = K + 2;
-  return sumfact_tables<K>() + 2 * (KC * KC * q1 * q1 + KC * KC * K1 * K1 * q1);
+  return sumfact_tables<K>() + SfBlocks<K>::s1_off(6);
+}
+
+// 1D factor a at point q of component d along axis x: closed (x == d; the
+// derivative for the divergence term, part 1) or open.  Tables in LDS:
+// Lc[KC][q1], Dc[KC][q1], Lo[K1][q1].
+template <int K>
+struct SfTables {
+  const double* Lc;
+  const double* Dc;
+  const double* Lo;
+  __device__ double operator()(int d, int part, int x, int a, int q) const {
+    constexpr int q1 = K + 2;
+    return x == d ? (part ? Dc[a * q1 + q] : Lc[a * q1 + q]) : Lo[a * q1 + q];
+  }
+};
+
+// Pass 1 task t of block B: S1[part][a0][b0][qq] = sum over the points q0
+// along axis 0 of (A_0[a0][q0] w(q)) B_0[b0][q0], w the metric weight of
+// (d, e) (part 0) or the div-div weight (part 1).
+template <int K, int B>
+__device__ __forceinline__ void sf_pass1(int t, const double* qd, SfTables<K> fac, double* S1) {
+  using SB = SfBlocks<K>;
+  constexpr int d = SB::d_of(B), e = SB::e_of(B), q1 = SB::q1, QD = 10;
+  constexpr int pa0 = SB::np(d, 0), pb0 = SB::np(e, 0), S1P = pa0 * pb0 * q1 * q1;
+  const int gi = gidx(d, e);
+  const int part = t / (q1 * q1 * pa0), r = t % (q1 * q1 * pa0), a0 = r % pa0, qq = r / pa0;
+  double aw[q1];
+#pragma unroll
+  for (int q0 = 0; q0 < q1; ++q0) aw[q0] = fac(d, part, 0, a0, q0) * qd[(q0 + q1 * qq) * QD + (part ? 6 : gi)];
+  // every load before the first store (the tables and S1 share LDS)
+  double res[pb0];
+#pragma unroll
+  for (int b0 = 0; b0 < pb0; ++b0) {
+    double s = 0.0;
+#pragma unroll
+    for (int q0 = 0; q0 < q1; ++q0) s += aw[q0] * fac(e, part, 0, b0, q0);
+    res[b0] = s;
+  }
+  double* out = S1 + SB::s1_off(B) + part * S1P + a0 * pb0 * q1 * q1 + qq;
+#pragma unroll
+  for (int b0 = 0; b0 < pb0; ++b0) out[b0 * q1 * q1] = res[b0];
+}
+
+// Pass 2 task t of block B, (a0, b0, a1, b1): both terms summed over the
+// points along axis 1 into registers (S2[part][q2]), then over axis 2 into
+// every entry (a2, b2) of the task (the lower triangle of a diagonal block).
+template <int K, int B, class Store>
+__device__ __forceinline__ void sf_pass2(int t, SfTables<K> fac, const double* S1, Store store) {
+  using SB = SfBlocks<K>;
+  constexpr int d = SB::d_of(B), e = SB::e_of(B), q1 = SB::q1;
+  constexpr int pa0 = SB::np(d, 0), pb0 = SB::np(e, 0), pa1 = SB::np(d, 1), pb1 = SB::np(e, 1);
+  constexpr int pa2 = SB::np(d, 2), pb2 = SB::np(e, 2), S1P = pa0 * pb0 * q1 * q1;
+  const int b1 = t % pb1, a1 = (t / pb1) % pa1, b0 = (t / (pb1 * pa1)) % pb0, a0 = t / (pb1 * pa1 * pb0);
+  const double* s1 = S1 + SB::s1_off(B) + (a0 * pb0 + b0) * q1 * q1;
+  double s2[2][q1];
+#pragma unroll
+  for (int part = 0; part < 2; ++part)
+#pragma unroll
+    for (int qz = 0; qz < q1; ++qz) {
+      double s = 0.0;
+#pragma unroll
+      for (int qy = 0; qy < q1; ++qy)
+        s += fac(d, part, 1, a1, qy) * s1[part * S1P + qy + q1 * qz] * fac(e, part, 1, b1, qy);
+      s2[part][qz] = s;
+    }
+  // every entry of the task in registers before the first store (the
+  // tables and the stored entries may share LDS)
+  double ent[pa2][pb2];
+#pragma unroll
+  for (int a2 = 0; a2 < pa2; ++a2) {
+    double am[q1], ad[q1];
+#pragma unroll
+    for (int qz = 0; qz < q1; ++qz) {
+      am[qz] = fac(d, 0, 2, a2, qz) * s2[0][qz];
+      ad[qz] = fac(d, 1, 2, a2, qz) * s2[1][qz];
+    }
+#pragma unroll
+    for (int b2 = 0; b2 < pb2; ++b2) {
+      double s = 0.0;
+#pragma unroll
+      for (int qz = 0; qz < q1; ++qz) s += am[qz] * fac(e, 0, 2, b2, qz) + ad[qz] * fac(e, 1, 2, b2, qz);
+      ent[a2][b2] = s;
+    }
+  }
+#pragma unroll
+  for (int a2 = 0; a2 < pa2; ++a2) {
+    const int ia = dof_index<K>(d, a0, a1, a2);
+#pragma unroll
+    for (int b2 = 0; b2 < pb2; ++b2) {
+      const int ib = dof_index<K>(e, b0, b1, b2);
+      if (d == e && ib > ia) continue;
+      if (ia >= ib) store(ia, ib, ent[a2][b2]); else store(ib, ia, ent[a2][b2]);
+    }
+  }
 }
 
 // Element matrix M_T by sum factorization (k >= 1, any trilinear element).
@@ -171,95 +289,43 @@ constexpr int sumfact_stage() {
 //     + w_div(q) prod_x A'_x[a_x][q_x] B'_x[b_x][q_x],
 // (A, B: the 1D factors of components d and e, A', B' those of the
 // divergences: derivatives of the closed factor on the own axis) is summed
-// one axis at a time: over the points along axis 0 into S1[a0][b0][q1][q2],
-// along axis 1 into S2[a0][b0][a1][b1][q2], along axis 2 into the entries.
-// The per-point weights come from element_qd (qd: 6 metric weights
-// w alpha (J^T J)_de / det J, the div-div weight w beta / det J).  Team-wide,
-// three barriers per block of components; store(i, j, v) receives every
-// entry with j <= i < n once.  stage: sumfact_stage<K>() doubles of LDS.
+// one axis at a time: over the points along axis 0 into S1[a0][b0][q1][q2]
+// (all six blocks in one team-wide pass), then per (a0, b0, a1, b1) along
+// axes 1 and 2 into the entries (a second pass), two barriers in all.  The
+// per-point weights come from element_qd (qd: 6 metric weights
+// w alpha (J^T J)_de / det J, the div-div weight w beta / det J).
+// store(i, j, v) receives every entry with j <= i < n once.  stage:
+// sumfact_stage<K>() doubles of LDS.
 template <int K, int TEAM, class Store>
 __device__ __forceinline__ void assemble_sumfact(const DeviceMaps& mp, const double* qd, double* stage, int lane,
                                                  Store store) {
-  constexpr int KC = K + 2, K1 = K + 1, q1 = K + 2, QD = 10;
+  using SB = SfBlocks<K>;
   static_assert(K >= 1, "sum factorization for k >= 1");
-  // the 1D tables into LDS (read in every inner loop below)
+  constexpr int KC = K + 2, q1 = K + 2;
   constexpr int TB = sumfact_tables<K>();
   __syncthreads();   // the team is done with the staging area
   for (int t = lane; t < TB; t += TEAM) stage[t] = mp.tab1d[t];
-  const double* Lc = stage;             // [KC][q1]
-  const double* Dc = Lc + KC * q1;      // [KC][q1]
-  const double* Lo = Dc + KC * q1;      // [K1][q1]
-  double* S1 = stage + TB;                             // [2][a0][b0][q1][q2]
-  double* S2 = S1 + 2 * KC * KC * q1 * q1;             // [2][a0][b0][a1][b1][q2]
-  constexpr int S1P = KC * KC * q1 * q1, S2P = KC * KC * K1 * K1 * q1;
+  const SfTables<K> fac{stage, stage + KC * q1, stage + 2 * KC * q1};
+  double* S1 = stage + TB;
   __syncthreads();
-  for (int d = 0; d < 3; ++d) {
-    for (int e = d; e < 3; ++e) {
-      const int gi = gidx(d, e);
-      // 1D factor of the own (x == c) or another axis; part 1: divergence
-      auto fac = [&](int c, int part, int x, int a, int q) {
-        return x == c ? (part ? Dc[a * q1 + q] : Lc[a * q1 + q]) : Lo[a * q1 + q];
-      };
-      const int pa0 = d == 0 ? KC : K1, pb0 = e == 0 ? KC : K1;
-      const int pa1 = d == 1 ? KC : K1, pb1 = e == 1 ? KC : K1;
-      const int pa2 = d == 2 ? KC : K1, pb2 = e == 2 ? KC : K1;
-      // axis 0: task (part, q1 q2, a0)
-      const int n1 = 2 * q1 * q1 * pa0;
-      for (int t = lane; t < n1; t += TEAM) {
-        const int part = t / (q1 * q1 * pa0), r = t % (q1 * q1 * pa0), a0 = r % pa0, qq = r / pa0;
-        double aw[q1];
-#pragma unroll
-        for (int q0 = 0; q0 < q1; ++q0)
-          aw[q0] = fac(d, part, 0, a0, q0) * qd[(q0 + q1 * qq) * QD + (part ? 6 : gi)];
-        for (int b0 = 0; b0 < pb0; ++b0) {
-          double s = 0.0;
-#pragma unroll
-          for (int q0 = 0; q0 < q1; ++q0) s += aw[q0] * fac(e, part, 0, b0, q0);
-          S1[part * S1P + (a0 * pb0 + b0) * q1 * q1 + qq] = s;
-        }
-      }
-      __syncthreads();
-      // axis 1: task (part, a0 b0, q2, a1)
-      const int n2 = 2 * pa0 * pb0 * q1 * pa1;
-      for (int t = lane; t < n2; t += TEAM) {
-        const int part = t / (pa0 * pb0 * q1 * pa1), r = t % (pa0 * pb0 * q1 * pa1);
-        const int a1 = r % pa1, q2 = (r / pa1) % q1, ab0 = r / (pa1 * q1);
-        double aw[q1];
-#pragma unroll
-        for (int qy = 0; qy < q1; ++qy)
-          aw[qy] = fac(d, part, 1, a1, qy) * S1[part * S1P + ab0 * q1 * q1 + qy + q1 * q2];
-        for (int b1 = 0; b1 < pb1; ++b1) {
-          double s = 0.0;
-#pragma unroll
-          for (int qy = 0; qy < q1; ++qy) s += aw[qy] * fac(e, part, 1, b1, qy);
-          S2[part * S2P + ((ab0 * pa1 + a1) * pb1 + b1) * q1 + q2] = s;
-        }
-      }
-      __syncthreads();
-      // axis 2: task (a0 b0 a1 b1, a2), both terms into the entries
-      const int n3 = pa0 * pb0 * pa1 * pb1 * pa2;
-      for (int t = lane; t < n3; t += TEAM) {
-        const int a2 = t % pa2, r = t / pa2;
-        const int b1 = r % pb1, a1 = (r / pb1) % pa1, b0 = (r / (pb1 * pa1)) % pb0, a0 = r / (pb1 * pa1 * pb0);
-        double am[q1], ad[q1];
-#pragma unroll
-        for (int qz = 0; qz < q1; ++qz) {
-          am[qz] = fac(d, 0, 2, a2, qz) * S2[r * q1 + qz];
-          ad[qz] = fac(d, 1, 2, a2, qz) * S2[S2P + r * q1 + qz];
-        }
-        const int ia = dof_index<K>(d, a0, a1, a2);
-        for (int b2 = 0; b2 < pb2; ++b2) {
-          const int ib = dof_index<K>(e, b0, b1, b2);
-          if (d == e && ib > ia) continue;
-          double s = 0.0;
-#pragma unroll
-          for (int qz = 0; qz < q1; ++qz) s += am[qz] * fac(e, 0, 2, b2, qz) + ad[qz] * fac(e, 1, 2, b2, qz);
-          if (ia >= ib) store(ia, ib, s); else store(ib, ia, s);
-        }
-      }
-      __syncthreads();
-    }
+  for (int t = lane; t < SB::t1_off(6); t += TEAM) {
+    if (t < SB::t1_off(1)) sf_pass1<K, 0>(t, qd, fac, S1);
+    else if (t < SB::t1_off(2)) sf_pass1<K, 1>(t - SB::t1_off(1), qd, fac, S1);
+    else if (t < SB::t1_off(3)) sf_pass1<K, 2>(t - SB::t1_off(2), qd, fac, S1);
+    else if (t < SB::t1_off(4)) sf_pass1<K, 3>(t - SB::t1_off(3), qd, fac, S1);
+    else if (t < SB::t1_off(5)) sf_pass1<K, 4>(t - SB::t1_off(4), qd, fac, S1);
+    else sf_pass1<K, 5>(t - SB::t1_off(5), qd, fac, S1);
   }
+  __syncthreads();
+  for (int t = lane; t < SB::t2_off(6); t += TEAM) {
+    if (t < SB::t2_off(1)) sf_pass2<K, 0>(t, fac, S1, store);
+    else if (t < SB::t2_off(2)) sf_pass2<K, 1>(t - SB::t2_off(1), fac, S1, store);
+    else if (t < SB::t2_off(3)) sf_pass2<K, 2>(t - SB::t2_off(2), fac, S1, store);
+    else if (t < SB::t2_off(4)) sf_pass2<K, 3>(t - SB::t2_off(3), fac, S1, store);
+    else if (t < SB::t2_off(5)) sf_pass2<K, 4>(t - SB::t2_off(4), fac, S1, store);
+    else sf_pass2<K, 5>(t - SB::t2_off(5), fac, S1, store);
+  }
+  __syncthreads();
 }
 
 }  // namespace hyb

@@ -119,8 +119,11 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
   };
 
   if (matrix) {
-    assemble_sumfact<K, TEAM>(mp, qd, stg, lane, [&](int i, int j, double v) {
-      if (i < ni) A[pk(i, j)] = v;
+    // (the interior entries through an LDS-qualified pointer: the two stores
+    // are not merged into one flat store)
+    lds_double* As = (lds_double*)(A);
+    assemble_sumfact<K, TEAM>(mp, qd, stg, lane, [=](int i, int j, double v) {
+      if (i < ni) As[pk(i, j)] = v;
       else if (own) rec[pk(i, j)] = v;
     });
     __syncthreads();
@@ -157,7 +160,7 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     }
     // L_ii = chol(A_ii) in LDS; the inverses of its diagonal blocks
     const bool bad_i = chol_mfma_t<double, ni, TEAM>(A, lane, true, flag, stg);
-    auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
+    auto Lii = [=](int i, int j) -> double { return A[pk(i, j)]; };
     diag_inverses<double, ni, TEAM>(Lii, stg, lane, true);
     __syncthreads();
     // L_bi^T = L_ii^{-1} A_bi^T by forward tile solves held in registers (the
@@ -166,14 +169,14 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     // L_ii^{-1} f_i as a seventh (one column) while L_ii is in LDS
     dx4 Xr[NTi];
     if (tw) {
-      tile_forward_regs<ni>(Lii, stg, [&](int i, int c) { return rec[pk(ni + c, i)]; }, Xr, 16 * w_id, 16, l);
+      tile_forward_regs<ni>(Lii, stg, [=](int i, int c) { return rec[pk(ni + c, i)]; }, Xr, 16 * w_id, 16, l);
 #pragma unroll
       for (int I = 0; I < NTi; ++I)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           if (own) rec[pk(ni + 16 * w_id + li, 16 * I + M::row(l, r))] = Xr[I][r];
     } else if (w_id == nb / 16 && rhs) {
-      tile_forward_reg<ni>(Lii, stg, [&](int i, int) { return fh[i]; }, [&](int i, int, double v) { fh[i] = v; }, 0, 1,
+      tile_forward_reg<ni>(Lii, stg, [=](int i, int) { return fh[i]; }, [=](int i, int, double v) { fh[i] = v; }, 0, 1,
                            l);
     }
     __syncthreads();
@@ -235,7 +238,7 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     if ((bad_i || bad_b) && live && lane == 0) report_error(a.status, HYB_E_NOT_SPD, e);
     if (a.stat) {
       // static condensation: S_hat_T = L_bb L_bb^T (lower triangle), sigma-signed, into S
-      auto Lbb = [&](int i, int j) { return Sb[pk(i, j)]; };
+      auto Lbb = [=](int i, int j) { return Sb[pk(i, j)]; };
       if (live) {
         for (int t = lane; t < R::nbpk; t += TEAM) {
           int aa, bb;
@@ -274,12 +277,12 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
       // L_bb^{-1} = L_bb^{-1} I by forward tile solves (one wave per column
       // tile, every 16-row block on the matrix cores), into Xb where L_ii was
       double* LiB = Sb + R::nbpk;
-      auto Lbb = [&](int i, int j) -> double { return Sb[pk(i, j)]; };
+      auto Lbb = [=](int i, int j) -> double { return Sb[pk(i, j)]; };
       diag_inverses<double, nb, TEAM>(Lbb, LiB, lane, true);
       __syncthreads();
       if (tw)
-        tile_forward_reg<nb>(Lbb, LiB, [&](int i, int c) { return i == c ? 1.0 : 0.0; },
-                             [&](int i, int c, double v) { Xb[i * Lay::XLD + c] = v; }, 16 * w_id, 16, l, w_id);
+        tile_forward_reg<nb>(Lbb, LiB, [=](int i, int c) { return i == c ? 1.0 : 0.0; },
+                             [=](int i, int c, double v) { Xb[i * Lay::XLD + c] = v; }, 16 * w_id, 16, l, w_id);
       __syncthreads();
       // H_T = D L_bb^{-T} L_bb^{-1} D: the lower 16 x 16 tiles of X^T X on the
       // FP64 matrix cores (X lower triangular: the sum starts at row block I),
@@ -336,11 +339,11 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     // the stored face block into LDS
     for (int t = lane; t < Lay::npi; t += TEAM) A[t] = rec[t];
     __syncthreads();
-    auto Lii = [&](int i, int j) -> double { return A[pk(i, j)]; };
+    auto Lii = [=](int i, int j) -> double { return A[pk(i, j)]; };
     diag_inverses<double, ni, TEAM>(Lii, stg, lane, true);
     __syncthreads();
     if (w_id == 0)
-      tile_forward_reg<ni>(Lii, stg, [&](int i, int) { return fh[i]; }, [&](int i, int, double v) { fh[i] = v; }, 0, 1,
+      tile_forward_reg<ni>(Lii, stg, [=](int i, int) { return fh[i]; }, [=](int i, int, double v) { fh[i] = v; }, 0, 1,
                            l);
     __syncthreads();
     if (tw) {
