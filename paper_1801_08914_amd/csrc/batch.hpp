@@ -1,6 +1,8 @@
-// Batches of independent problems of mixed order: one persistent launch
-// walks a cost-sorted list of work items (problem, run of element blocks)
-// and runs the order's generic element routine on each.
+// Batches of independent problems of mixed order: per order present, one
+// persistent launch walks that order's part of a cost-sorted list of work
+// items (problem, run of element blocks) and runs the order's element
+// routine on each (a kernel per order: each gets the register allocation,
+// and so the occupancy, of the single-plan kernel of that order).
 #pragma once
 
 #include "kernels_common.hpp"
@@ -39,20 +41,9 @@ __host__ __device__ constexpr int batch_epb_mixed(int k) { return k == 0 ? 8 : (
 constexpr int kBatchThreads = 512;
 constexpr int kBatchThreadsK3 = 512;
 
-// The order-specific element routines as separate functions: inlined into
+// The mixed-precision element routines as separate functions: inlined into
 // one persistent kernel, the four bodies share one register allocation (and
 // spill); called, each keeps its own.  A call per element block.
-template <int K, int TEAM, int EPB>
-__device__ __attribute__((noinline)) void batch_setup_fp64(const SetupArgs& a, double* smem, int64_t blk) {
-  setup_generic_body<K, TEAM, EPB>(a, smem, blk);
-}
-__device__ __attribute__((noinline)) void batch_setup_k3(const SetupArgs& a, double* smem, int64_t blk) {
-  setup_k3_body<kBatchThreadsK3>(a, smem, blk);
-}
-template <int K, int TEAM, int EPB>
-__device__ __attribute__((noinline)) void batch_recover_fp64(const RecoverArgs& a, double* smem, int64_t blk) {
-  recover_generic_body<K, TEAM, EPB>(a, smem, blk);
-}
 template <int K, int TEAM, int EPB>
 __device__ __attribute__((noinline)) void batch_setup_mx(const SetupArgs& a, double* smem, int64_t blk, int sweeps,
                                                          double* scratch) {
@@ -91,41 +82,52 @@ __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
   if (P.mixed && blockIdx.x == 0 && threadIdx.x == 0) P.s.status[2] = 0;
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_setup_batch(const BatchProb* probs, const BatchItem* items,
-                                                               int64_t nitems, int32_t* queue) {
+// The FP64 problems of order K: setup, then recovery.  The descriptors and
+// items are read-only and not aliased, and the item index is made
+// wave-uniform, so the arguments load into scalar registers.  Setup bodies
+// per order as measured best: RT2 inline, with the register budget of the
+// single-plan kernel (at most 128, two workgroups per CU; without the bound
+// the persistent loop takes 183 and one); the others called (their own
+// register allocation; inlined, the RT3 body spills).
+template <int K>
+__device__ __attribute__((noinline)) void batch_setup_call(const SetupArgs& a, double* smem, int64_t blk) {
+  if constexpr (K == 0) setup_generic_body<0, 16, 32>(a, smem, blk);
+  else if constexpr (K == 1) setup_generic_body<1, 64, 8>(a, smem, blk);
+  else setup_k3_body<kBatchThreadsK3>(a, smem, blk);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBatchThreads, K == 2 ? 4 : 2) void k_setup_batch(const BatchProb* __restrict__ probs,
+                                                                               const BatchItem* __restrict__ items,
+                                                                               int64_t nitems, int32_t* queue) {
   extern __shared__ double smem[];
   __shared__ int64_t item;
   for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
-    const BatchItem it = items[w];
-    const BatchProb& P = probs[it.prob];
+    const BatchItem& it = items[__builtin_amdgcn_readfirstlane(int(w))];
+    const SetupArgs& a = probs[it.prob].s;
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
-      switch (P.k) {
-        case 0: batch_setup_fp64<0, 16, 32>(P.s, smem, blk); break;
-        case 1: batch_setup_fp64<1, 64, 8>(P.s, smem, blk); break;
-        case 2: batch_setup_fp64<2, 512, 1>(P.s, smem, blk); break;
-        default: batch_setup_k3(P.s, smem, blk); break;
-      }
+      if constexpr (K == 2) setup_generic_body<2, 512, 1>(a, smem, blk);
+      else batch_setup_call<K>(a, smem, blk);
       __syncthreads();   // the next block reuses the LDS
     }
   }
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb* probs, const BatchItem* items,
-                                                                 int64_t nitems, int32_t* queue) {
+template <int K>
+__global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb* __restrict__ probs,
+                                                                 const BatchItem* __restrict__ items, int64_t nitems,
+                                                                 int32_t* queue) {
   extern __shared__ double smem[];
   __shared__ int64_t item;
   for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
-    const BatchItem it = items[w];
-    const BatchProb& P = probs[it.prob];
+    const BatchItem& it = items[__builtin_amdgcn_readfirstlane(int(w))];
+    const RecoverArgs& a = probs[it.prob].r;
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
-      switch (P.k) {
-        case 0: batch_recover_fp64<0, 16, 32>(P.r, smem, blk); break;
-        case 1: batch_recover_fp64<1, 64, 8>(P.r, smem, blk); break;
-        case 2: batch_recover_fp64<2, 512, 1>(P.r, smem, blk); break;
-        default: batch_recover_fp64<3, 512, 1>(P.r, smem, blk); break;
-      }
+      if constexpr (K == 0) recover_generic_body<0, 16, 32>(a, smem, blk);
+      else if constexpr (K == 1) recover_generic_body<1, 64, 8>(a, smem, blk);
+      else recover_generic_body<K, 512, 1>(a, smem, blk);
       __syncthreads();
     }
   }

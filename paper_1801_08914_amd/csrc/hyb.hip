@@ -812,25 +812,30 @@ struct hyb_batch {
   int cus = 0;
   hyb_batch_tiles tiles{0, 0};
   std::vector<hyb::BatchProb> probs;       // host copy of the descriptors
-  std::vector<hyb::BatchItem> items;       // cost-sorted work list: FP64 problems' items, then mixed
+  std::vector<hyb::BatchItem> items;       // cost-sorted work list: FP64 problems' items by order, then mixed
   size_t n64 = 0;                          // items of FP64 problems (the first n64)
+  size_t beg[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};   // the FP64 items of order k
   hyb::BatchProb* d_probs = nullptr;
   hyb::BatchItem* d_items = nullptr;
   size_t cap_items = 0;
-  size_t lds_setup = 0, lds_recover = 0, lds_setup_mx = 0, lds_recover_mx = 0;
+  size_t lds_setup_mx = 0, lds_recover_mx = 0;
   bool dirty = true;                       // descriptors or items changed since upload
   bool use_graph = false;
   hipGraphExec_t g_setup = nullptr, g_recover = nullptr;
   hipStream_t gstream = nullptr;           // capture/replay stream (graphs need a non-null stream)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   double* scratch = nullptr;               // k = 3 mixed: a slot per workgroup of the mixed launch
-  int32_t* d_queue = nullptr;              // work-queue counters of the four persistent launches
+  int32_t* d_queue = nullptr;              // work-queue counters of the persistent launches (kQueues)
   // optional HIP-event timing of each phase (start/stop pairs, launch order)
   bool timing = false;
   std::vector<hipEvent_t> ev_setup, ev_recover, ev_pool;
 };
 
 namespace {
+
+// queue counters: FP64 setup per order (0..3), mixed setup, FP64 recovery per
+// order (5..8), mixed recovery
+constexpr int kQueues = 10;
 
 int batch_epb_of(const hyb::Plan& P) { return P.mixed ? hyb::batch_epb_mixed(P.ord.k) : hyb::batch_epb(P.ord.k); }
 
@@ -864,15 +869,22 @@ void batch_build_items(hyb_batch* b) {
       b->items.push_back(it);
     }
   }
-  // FP64 problems' items first, then the mixed ones; within each most
-  // expensive first (orders descending), stable: deterministic order
+  // FP64 problems' items first, by order (descending), then the mixed ones;
+  // within each group most expensive first, stable: deterministic order
   std::stable_sort(b->items.begin(), b->items.end(), [&](const hyb::BatchItem& x, const hyb::BatchItem& y) {
     const hyb::Plan &px = b->plans[x.prob]->P, &py = b->plans[y.prob]->P;
     if (px.mixed != py.mixed) return !px.mixed;
+    if (!px.mixed && px.ord.k != py.ord.k) return px.ord.k > py.ord.k;
     return batch_block_cost(px) * x.nblk > batch_block_cost(py) * y.nblk;
   });
   b->n64 = 0;
-  while (b->n64 < b->items.size() && !b->plans[b->items[b->n64].prob]->P.mixed) ++b->n64;
+  for (int k = 0; k < 4; ++k) b->beg[k] = b->cnt[k] = 0;
+  while (b->n64 < b->items.size() && !b->plans[b->items[b->n64].prob]->P.mixed) {
+    const int k = b->plans[b->items[b->n64].prob]->P.ord.k;
+    if (b->cnt[k] == 0) b->beg[k] = b->n64;
+    ++b->cnt[k];
+    ++b->n64;
+  }
   b->dirty = true;
 }
 
@@ -914,17 +926,23 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
   HYB_HIP(hipGetLastError());
   const size_t nmx = b->items.size() - b->n64;
   // the queue counters start at zero (a kernel, not a memset: graph replays)
-  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue, int64_t(2), 0);
+  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue, int64_t(5), 0);
   HYB_HIP(hipGetLastError());
-  if (b->n64) {
-    hipLaunchKernelGGL(hyb::k_setup_batch, dim3(batch_grid(b, b->n64)), dim3(hyb::kBatchThreads), b->lds_setup, st,
-                       b->d_probs, b->d_items, int64_t(b->n64), b->d_queue);
+  // the orders' launches, most expensive first
+  for (int k = 3; k >= 0; --k) {
+    if (!b->cnt[k]) continue;
+    const auto kern = k == 3 ? hyb::k_setup_batch<3>
+                      : k == 2 ? hyb::k_setup_batch<2>
+                      : k == 1 ? hyb::k_setup_batch<1>
+                               : hyb::k_setup_batch<0>;
+    hipLaunchKernelGGL(kern, dim3(batch_grid(b, b->cnt[k])), dim3(hyb::kBatchThreads), hyb::batch_setup_lds(k), st,
+                       b->d_probs, b->d_items + b->beg[k], int64_t(b->cnt[k]), b->d_queue + k);
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {
     const unsigned gm = std::min<unsigned>(batch_grid(b, nmx), unsigned(hyb::kMixedSlots));
     hipLaunchKernelGGL(hyb::k_setup_batch_mixed, dim3(gm), dim3(hyb::kBatchThreads), b->lds_setup_mx, st,
-                       b->d_probs, b->d_items + b->n64, int64_t(nmx), b->scratch, b->d_queue + 1);
+                       b->d_probs, b->d_items + b->n64, int64_t(nmx), b->scratch, b->d_queue + 4);
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
@@ -932,16 +950,21 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
 
 int batch_launch_recover(hyb_batch* b, hipStream_t st) {
   const size_t nmx = b->items.size() - b->n64;
-  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue + 2, int64_t(2), 0);
+  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue + 5, int64_t(5), 0);
   HYB_HIP(hipGetLastError());
-  if (b->n64) {
-    hipLaunchKernelGGL(hyb::k_recover_batch, dim3(batch_grid(b, b->n64)), dim3(hyb::kBatchThreads), b->lds_recover,
-                       st, b->d_probs, b->d_items, int64_t(b->n64), b->d_queue + 2);
+  for (int k = 3; k >= 0; --k) {
+    if (!b->cnt[k]) continue;
+    const auto kern = k == 3 ? hyb::k_recover_batch<3>
+                      : k == 2 ? hyb::k_recover_batch<2>
+                      : k == 1 ? hyb::k_recover_batch<1>
+                               : hyb::k_recover_batch<0>;
+    hipLaunchKernelGGL(kern, dim3(batch_grid(b, b->cnt[k])), dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st,
+                       b->d_probs, b->d_items + b->beg[k], int64_t(b->cnt[k]), b->d_queue + 5 + k);
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {
     hipLaunchKernelGGL(hyb::k_recover_batch_mixed, dim3(batch_grid(b, nmx)), dim3(hyb::kBatchThreads),
-                       b->lds_recover_mx, st, b->d_probs, b->d_items + b->n64, int64_t(nmx), b->d_queue + 3);
+                       b->lds_recover_mx, st, b->d_probs, b->d_items + b->n64, int64_t(nmx), b->d_queue + 9);
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
@@ -1052,25 +1075,31 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
     if (P.mixed) {
       b->lds_setup_mx = std::max(b->lds_setup_mx, hyb::batch_setup_lds_mixed(P.ord.k));
       b->lds_recover_mx = std::max(b->lds_recover_mx, hyb::batch_recover_lds_mixed(P.ord.k));
-    } else {
-      b->lds_setup = std::max(b->lds_setup, hyb::batch_setup_lds(P.ord.k));
-      b->lds_recover = std::max(b->lds_recover, hyb::batch_recover_lds(P.ord.k));
     }
   }
   bool mixed3 = false;
   for (int32_t i = 0; i < count; ++i) mixed3 |= plans[i]->P.mixed && plans[i]->P.ord.k == 3;
   hipError_t e1 = hipMalloc(&b->d_probs, sizeof(hyb::BatchProb) * b->probs.size());
-  if (e1 == hipSuccess) e1 = hipMalloc(&b->d_queue, 4 * sizeof(int32_t));
+  if (e1 == hipSuccess) e1 = hipMalloc(&b->d_queue, kQueues * sizeof(int32_t));
   if (e1 == hipSuccess && mixed3) e1 = hipMalloc(&b->scratch, size_t(mixed_scratch_bytes(3)));
   if (e1 == hipSuccess) e1 = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
   if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
-  if (e1 == hipSuccess)
-    e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(hyb::k_setup_batch),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_setup));
-  if (e1 == hipSuccess)
-    e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(hyb::k_recover_batch),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_recover));
+  {
+    const void* ks[4] = {reinterpret_cast<const void*>(hyb::k_setup_batch<0>),
+                         reinterpret_cast<const void*>(hyb::k_setup_batch<1>),
+                         reinterpret_cast<const void*>(hyb::k_setup_batch<2>),
+                         reinterpret_cast<const void*>(hyb::k_setup_batch<3>)};
+    const void* kr[4] = {reinterpret_cast<const void*>(hyb::k_recover_batch<0>),
+                         reinterpret_cast<const void*>(hyb::k_recover_batch<1>),
+                         reinterpret_cast<const void*>(hyb::k_recover_batch<2>),
+                         reinterpret_cast<const void*>(hyb::k_recover_batch<3>)};
+    for (int k = 0; k < 4 && e1 == hipSuccess; ++k) {
+      e1 = hipFuncSetAttribute(ks[k], hipFuncAttributeMaxDynamicSharedMemorySize, int(hyb::batch_setup_lds(k)));
+      if (e1 == hipSuccess)
+        e1 = hipFuncSetAttribute(kr[k], hipFuncAttributeMaxDynamicSharedMemorySize, int(hyb::batch_recover_lds(k)));
+    }
+  }
   if (e1 == hipSuccess && b->lds_setup_mx)
     e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(hyb::k_setup_batch_mixed),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_setup_mx));

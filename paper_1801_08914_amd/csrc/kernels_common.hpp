@@ -19,7 +19,7 @@ struct RT {
   static constexpr int npk = n * (n + 1) / 2;    // packed lower triangle
   static constexpr int nbpk = nb * (nb + 1) / 2;
   // component (axis) of the local dof i
-  __device__ __host__ static constexpr int comp(int i) {
+  __device__ __host__ __forceinline__ static constexpr int comp(int i) {
     return i < ni ? i / (K * K2 > 0 ? K * K2 : 1) : ((i - ni) / K2) >> 1;
   }
 };
