@@ -281,6 +281,64 @@ __device__ __forceinline__ void sf_pass2(int t, SfTables<K> fac, const double* S
   }
 }
 
+// The load vector by sum factorization: entry i (component d, 1D indices
+// a0, a1, a2) is sum_q prod_x A_x[a_x][q_x] w_d(q), w_d(q) the per-point load
+// weight of component d from element_qd (qd[q * 10 + 7 + d]), summed over the
+// points along axis 0 into T1[d][a0][q1][q2] (one team-wide pass), then per
+// (d, a0, a1) along axes 1 and 2 into the entries.  out(i, v) receives every
+// entry once; stage: load_sumfact_stage<K>() doubles of LDS.  Ends with a
+// barrier.
+template <int K>
+constexpr int load_sumfact_stage() {
+  return sumfact_tables<K>() + (3 * (K + 1) + 2) * (K + 2) * (K + 2);
+}
+template <int K, int TEAM, class Out>
+__device__ __forceinline__ void load_sumfact(const DeviceMaps& mp, const double* qd, double* stage, int lane, Out out) {
+  using SB = SfBlocks<K>;
+  constexpr int KC = K + 2, q1 = K + 2, QD = 10, TB = sumfact_tables<K>();
+  __syncthreads();   // the team is done with the staging area
+  for (int t = lane; t < TB; t += TEAM) stage[t] = mp.tab1d[t];
+  const SfTables<K> fac{stage, stage + KC * q1, stage + 2 * KC * q1};
+  double* T1 = stage + TB;
+  // T1 of component d at (KC + (d - 1) K1) q1^2 for d >= 1: d = 0 has KC factors along axis 0
+  auto t1_off = [](int d) { return d == 0 ? 0 : (SB::KC + (d - 1) * SB::K1) * q1 * q1; };
+  constexpr int n1 = (SB::KC + 2 * SB::K1) * q1 * q1;
+  __syncthreads();
+  for (int t = lane; t < n1; t += TEAM) {
+    const int d = t < SB::KC * q1 * q1 ? 0 : (t < (SB::KC + SB::K1) * q1 * q1 ? 1 : 2);
+    const int r = t - t1_off(d), a0 = r / (q1 * q1), qq = r % (q1 * q1);
+    double s = 0.0;
+#pragma unroll
+    for (int q0 = 0; q0 < q1; ++q0) s += fac(d, 0, 0, a0, q0) * qd[(q0 + q1 * qq) * QD + 7 + d];
+    T1[t] = s;
+  }
+  __syncthreads();
+  // tasks (d, a0, a1): KC K1 for d = 0 and d = 1, K1 K1 for d = 2
+  constexpr int n2 = 2 * SB::KC * SB::K1 + SB::K1 * SB::K1;
+  for (int t = lane; t < n2; t += TEAM) {
+    const int d = t < SB::KC * SB::K1 ? 0 : (t < 2 * SB::KC * SB::K1 ? 1 : 2);
+    const int r = t - (d == 0 ? 0 : (d == 1 ? SB::KC * SB::K1 : 2 * SB::KC * SB::K1));
+    const int pa1 = SB::np(d, 1), pa2 = SB::np(d, 2);
+    const int a0 = r / pa1, a1 = r % pa1;
+    const double* t1 = T1 + t1_off(d) + a0 * q1 * q1;
+    double t2[q1];
+#pragma unroll
+    for (int qz = 0; qz < q1; ++qz) {
+      double s = 0.0;
+#pragma unroll
+      for (int qy = 0; qy < q1; ++qy) s += fac(d, 0, 1, a1, qy) * t1[qy + q1 * qz];
+      t2[qz] = s;
+    }
+    for (int a2 = 0; a2 < pa2; ++a2) {
+      double s = 0.0;
+#pragma unroll
+      for (int qz = 0; qz < q1; ++qz) s += fac(d, 0, 2, a2, qz) * t2[qz];
+      out(dof_index<K>(d, a0, a1, a2), s);
+    }
+  }
+  __syncthreads();
+}
+
 // Element matrix M_T by sum factorization (k >= 1, any trilinear element).
 // The basis is a tensor product (per component d: the closed Lagrange factor
 // along axis d, open ones along the other two) and the Gauss rule is a

@@ -32,6 +32,7 @@ struct K3Layout {
   static constexpr int XLD = nb + 1, LDE = nb + 16;
   static_assert(nb * XLD <= npi, "the full inverse of L_bb fits where L_ii was");
   static constexpr int stage = stage0 > stage1 ? (stage0 > stage2 ? stage0 : stage2) : (stage1 > stage2 ? stage1 : stage2);
+  static_assert(load_sumfact_stage<3>() <= stage, "the load vector's partial sums fit in the staging area");
   static_assert(ni % 16 == 0 && nb % 16 == 0, "whole 16-row blocks");
   static_assert(ni * LDE <= npi + stage, "L_bi^T fits where L_ii and the staging area were");
   static constexpr int per = npi + stage + R::Q * 10 + n + 24 + nb + 8;
@@ -66,7 +67,6 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
   const DeviceMaps& mp = a.mp;
   const bool matrix = (a.mode & MODE_MATRIX) != 0, rhs = (a.mode & MODE_RHS) != 0;
   // L_bb^{-1}: full in LDS after a setup, packed (from the record) for a right-hand side alone
-  auto LI = [&](int i, int j) -> double { return matrix ? Xb[i * Lay::XLD + j] : Sb[pk(i, j)]; };
 
   int fid[6], pic[6];
 #pragma unroll
@@ -129,11 +129,10 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     __syncthreads();
   }
   if (rhs) {
+    // the load vector by sum factorization, then the boundary data
+    load_sumfact<K, TEAM>(mp, qd, stg, lane, [=](int i, double v) { fh[i] = v; });
     for (int i = lane; i < n; i += TEAM) {
-      const int d = R::comp(i);
-      double s = 0.0;
-#pragma unroll 8
-      for (int q = 0; q < Q; ++q) s += mp.tab_s[q * n + i] * qd[q * QD + 7 + d];
+      double s = fh[i];
       if (is_ess(i)) {
         s = a.g ? a.g[es * nb + (i - ni)] : 0.0;
       } else if (a.g) {
@@ -298,26 +297,33 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
 #pragma unroll 4
           for (int c0 = 16 * I; c0 < nb; c0 += 4)
             acc = M::op(Xb[(c0 + lk) * Lay::XLD + 16 * I + li], Xb[(c0 + lk) * Lay::XLD + 16 * J + li], acc);
-          if (!live) continue;
+          // tile (I, J) couples faces I and J (K2 = 16 dofs per face): the
+          // face data are the tile's, the frame maps the lane's
+          static_assert(K2 == 16, "a 16 x 16 tile per face pair");
+          const int Fa = fid[I], Fb = fid[J];
+          if (!live || Fa < 0 || Fb < 0) continue;   // uniform
+          const int64_t rba = mp.face_rowbase[Fa], rbb = mp.face_rowbase[Fb];
+          const int64_t nsa = int64_t(mp.face_nslots[Fa]) * K2, nsb = int64_t(mp.face_nslots[Fb]) * K2;
+          const int64_t sab = int64_t(mp.elem_slot[e * 36 + I * 6 + J]) * K2;
+          const int64_t sba = int64_t(mp.elem_slot[e * 36 + J * 6 + I]) * K2;
+          const bool flip = ((I ^ J) & 1) != 0;
+          int b0 = li % K1, b1 = li / K1;
+          frame_map(pic[J], K, b0, b1);
+          const int jb = b0 + K1 * b1;
+          const double wb = mp.face_w[jb];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int aa = 16 * I + M::row(l, r), bb = 16 * J + li;
-            const int fa = aa / K2, fb = bb / K2;
-            if (bb > aa || fid[fa] < 0 || fid[fb] < 0) continue;
-            const double v = ((fa ^ fb) & 1) ? -acc[r] : acc[r];
-            int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
-            frame_map(pic[fa], K, a0, a1);
-            frame_map(pic[fb], K, b0, b1);
-            const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
-            const int Fa = fid[fa], Fb2 = fid[fb];
-            const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
-                                mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
-            const int64_t pba = mp.face_rowbase[Fb2] + int64_t(jb) * mp.face_nslots[Fb2] * K2 +
-                                mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
-            const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
-            if (fa == fb) {
+            const int ra = M::row(l, r);   // row of the tile: dof ra of face I
+            if (I == J && li > ra) continue;
+            int a0 = ra % K1, a1 = ra / K1;
+            frame_map(pic[I], K, a0, a1);
+            const int ja = a0 + K1 * a1;
+            const double vw = (flip ? -acc[r] : acc[r]) * (mp.face_w[ja] * wb);   // M_s H_T M_s (weighted C)
+            const int64_t pab = rba + ja * nsa + sab + jb;
+            const int64_t pba = rbb + jb * nsb + sba + ja;
+            if (I == J) {
               atomicAdd(&a.Hval[pab], vw);
-              if (aa != bb) atomicAdd(&a.Hval[pba], vw);
+              if (li != ra) atomicAdd(&a.Hval[pba], vw);
             } else {
               a.Hval[pab] = vw;
               a.Hval[pba] = vw;
@@ -368,8 +374,13 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
     for (int b = lane; b < nb; b += TEAM) {
       double s = tb[b];
       if (!a.stat) {
+        // row b of L_bb^{-1}: full rows after a setup, packed from the record
+        // (the same products in the same order; loops unrolled so that the
+        // loads run ahead of the chain of sums)
         s = 0.0;
-        for (int c = 0; c <= b; ++c) s += LI(b, c) * tb[c];
+        const double* lr = matrix ? Xb + b * Lay::XLD : Sb + pk(b, 0);
+#pragma unroll 8
+        for (int c = 0; c <= b; ++c) s += lr[c] * tb[c];
       }
       fh[ni + b] = s;
     }
@@ -384,8 +395,20 @@ __device__ __forceinline__ void setup_k3_body(const SetupArgs& a, double* smem, 
         if (a.stat) {
           s = sigma(b) * fh[ni + b];
         } else {
+          // column b of L_bb^{-1}
           s = 0.0;
-          for (int c = b; c < nb; ++c) s += LI(c, b) * fh[ni + c];
+          if (matrix) {
+            const double* lc = Xb + b;
+#pragma unroll 8
+            for (int c = b; c < nb; ++c) s += lc[c * Lay::XLD] * fh[ni + c];
+          } else {
+            int p = pk(b, b);
+#pragma unroll 8
+            for (int c = b; c < nb; ++c) {
+              s += Sb[p] * fh[ni + c];
+              p += c + 1;
+            }
+          }
           if (!(fb & 1)) s = -s;
         }
         int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
