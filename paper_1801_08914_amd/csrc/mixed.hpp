@@ -44,37 +44,6 @@ __device__ __forceinline__ bool chol_mfma_t(T* A, int lane, bool active, int* fl
   return out;
 }
 
-// Inverses of the 16 x 16 diagonal blocks of a lower factor L (lower
-// triangular, the identity past N), one block per wave in turn and a lane
-// per column (forward substitution, x_i = (delta_ij - sum_k L_ik x_k) / L_ii):
-// Linv[256 I + 16 i + j].  L(i, j) reads the factor for j <= i < N.
-template <class T, int N, int TEAM, class LAcc>
-__device__ __forceinline__ void diag_inverses(LAcc L, T* Linv, int lane, bool active) {
-  constexpr int NT = (N + 15) / 16, NW = TEAM / 64;
-  const int w_id = lane / 64, j = lane % 64;
-  if (!active || j >= 16) return;
-  for (int I = w_id; I < NT; I += NW) {
-    const int c0 = 16 * I;
-    T x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      // x_k = 0 for k < j, so the sum needs no lane-dependent bounds (no
-      // branch around the loads)
-      T s = i == j ? T(1) : T(0);
-      if (c0 + i < N) {   // uniform
-#pragma unroll
-        for (int k = 0; k < i; ++k) s -= L(c0 + i, c0 + k) * x[k];
-        const T xi = s / L(c0 + i, c0 + i);
-        x[i] = i >= j ? xi : T(0);
-      } else {
-        x[i] = s;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Linv[256 * I + 16 * i + j] = x[i];
-  }
-}
-
 // W := (L L^T)^{-1} W (BACK) or L^{-1} W on one column tile (columns c0 ..
 // c0 + ncol - 1 of W, ncol <= 16) by one wave: forward, then backward
 // substitution by blocks of 16 rows; every block is first updated by the
@@ -152,71 +121,6 @@ __device__ __forceinline__ void tile_solve(LAcc L, const T* Linv, WAcc W, int c0
     st(I, x);
     wave_sync();
   }
-}
-
-// FP64 forward substitution W := L^{-1} W on one column tile (columns c0 ..
-// c0 + ncol - 1, ncol <= 16) by one wave with the whole tile in registers:
-// the FP64 matrix-core result layout (rows l/16 + 4r of column l % 16) is the
-// layout of the B operand at k-step r (rows 4r + l/16), so a solved 16-row
-// block feeds the next blocks' products straight from its accumulator, and
-// the tile touches memory only when it is loaded.  load(i, c) reads the tile
-// (i < N, c < c0 + ncol); L(i, j) is the factor (j <= i < N, LDS) and Linv
-// its diagonal blocks' inverses.  The tile's row blocks before I0 are zero
-// (and stay so), and are skipped.  On return X[I][r] holds row 16 I + l/16 +
-// 4 r of column c0 + l % 16 (zero past N and for columns past ncol).
-template <int N, class LAcc, class Load>
-__device__ __forceinline__ void tile_forward_regs(LAcc L, const double* Linv, Load load, dx4 (&X)[(N + 15) / 16], int c0,
-                                                  int ncol, int l, int I0 = 0) {
-  using M = MfmaT<double>;
-  constexpr int NT = (N + 15) / 16;
-  const int li = l & 15, lk = l >> 4;
-  const bool cok = li < ncol;
-  const int cc = cok ? c0 + li : c0;
-#pragma unroll
-  for (int I = 0; I < NT; ++I)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * I + M::row(l, r);
-      const double v = load(i < N ? i : N - 1, cc);
-      X[I][r] = (cok && i < N) ? v : 0.0;
-    }
-#pragma unroll
-  for (int I = 0; I < NT; ++I) {
-    if (I < I0) continue;   // uniform
-    const int i = 16 * I + li, ic = i < N ? i : N - 1;
-    dx4 acc = X[I];
-#pragma unroll
-    for (int J = 0; J < I; ++J)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        if (J < I0) continue;
-        const double lv = L(ic, 16 * J + 4 * s + lk);
-        acc = M::op(i < N ? -lv : 0.0, X[J][s], acc);
-      }
-    dx4 x = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) x = M::op(Linv[256 * I + 16 * li + 4 * s + lk], acc[s], x);
-    X[I] = x;
-  }
-}
-
-// tile_forward_regs with the result stored through store(i, c, v) (i < N,
-// c < c0 + ncol).
-template <int N, class LAcc, class Load, class Store>
-__device__ __forceinline__ void tile_forward_reg(LAcc L, const double* Linv, Load load, Store store, int c0, int ncol,
-                                                 int l, int I0 = 0) {
-  using M = MfmaT<double>;
-  constexpr int NT = (N + 15) / 16;
-  dx4 X[NT];
-  tile_forward_regs<N>(L, Linv, load, X, c0, ncol, l, I0);
-  const int li = l & 15;
-#pragma unroll
-  for (int I = 0; I < NT; ++I)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * I + M::row(l, r);
-      if (li < ncol && i < N) store(i, c0 + li, X[I][r]);
-    }
 }
 
 // R = B - M X (FP64) on the output tiles (16 rows x 16 columns) dealt to the

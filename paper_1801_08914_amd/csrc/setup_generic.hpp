@@ -334,6 +334,102 @@ __device__ __forceinline__ bool chol_tiles16(T* A, T* rd, int lane, bool active)
   return bad;
 }
 
+// Inverses of the 16 x 16 diagonal blocks of a lower factor L (lower
+// triangular, the identity past N), one block per wave in turn and a lane
+// per column (forward substitution, x_i = (delta_ij - sum_k L_ik x_k) / L_ii):
+// Linv[256 I + 16 i + j].  L(i, j) reads the factor for j <= i < N.
+template <class T, int N, int TEAM, class LAcc>
+__device__ __forceinline__ void diag_inverses(LAcc L, T* Linv, int lane, bool active) {
+  constexpr int NT = (N + 15) / 16, NW = TEAM / 64;
+  const int w_id = lane / 64, j = lane % 64;
+  if (!active || j >= 16) return;
+  for (int I = w_id; I < NT; I += NW) {
+    const int c0 = 16 * I;
+    T x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      // x_k = 0 for k < j, so the sum needs no lane-dependent bounds (no
+      // branch around the loads)
+      T s = i == j ? T(1) : T(0);
+      if (c0 + i < N) {   // uniform
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L(c0 + i, c0 + k) * x[k];
+        const T xi = s / L(c0 + i, c0 + i);
+        x[i] = i >= j ? xi : T(0);
+      } else {
+        x[i] = s;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Linv[256 * I + 16 * i + j] = x[i];
+  }
+}
+
+// FP64 forward substitution W := L^{-1} W on one column tile (columns c0 ..
+// c0 + ncol - 1, ncol <= 16) by one wave with the whole tile in registers:
+// the FP64 matrix-core result layout (rows l/16 + 4r of column l % 16) is the
+// layout of the B operand at k-step r (rows 4r + l/16), so a solved 16-row
+// block feeds the next blocks' products straight from its accumulator, and
+// the tile touches memory only when it is loaded.  load(i, c) reads the tile
+// (i < N, c < c0 + ncol); L(i, j) is the factor (j <= i < N, LDS) and Linv
+// its diagonal blocks' inverses.  The tile's row blocks before I0 are zero
+// (and stay so), and are skipped.  On return X[I][r] holds row 16 I + l/16 +
+// 4 r of column c0 + l % 16 (zero past N and for columns past ncol).
+template <int N, class LAcc, class Load>
+__device__ __forceinline__ void tile_forward_regs(LAcc L, const double* Linv, Load load, dx4 (&X)[(N + 15) / 16], int c0,
+                                                  int ncol, int l, int I0 = 0) {
+  using M = MfmaT<double>;
+  constexpr int NT = (N + 15) / 16;
+  const int li = l & 15, lk = l >> 4;
+  const bool cok = li < ncol;
+  const int cc = cok ? c0 + li : c0;
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + M::row(l, r);
+      const double v = load(i < N ? i : N - 1, cc);
+      X[I][r] = (cok && i < N) ? v : 0.0;
+    }
+#pragma unroll
+  for (int I = 0; I < NT; ++I) {
+    if (I < I0) continue;   // uniform
+    const int i = 16 * I + li, ic = i < N ? i : N - 1;
+    dx4 acc = X[I];
+#pragma unroll
+    for (int J = 0; J < I; ++J)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (J < I0) continue;
+        const double lv = L(ic, 16 * J + 4 * s + lk);
+        acc = M::op(i < N ? -lv : 0.0, X[J][s], acc);
+      }
+    dx4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x = M::op(Linv[256 * I + 16 * li + 4 * s + lk], acc[s], x);
+    X[I] = x;
+  }
+}
+
+// tile_forward_regs with the result stored through store(i, c, v) (i < N,
+// c < c0 + ncol).
+template <int N, class LAcc, class Load, class Store>
+__device__ __forceinline__ void tile_forward_reg(LAcc L, const double* Linv, Load load, Store store, int c0, int ncol,
+                                                 int l, int I0 = 0) {
+  using M = MfmaT<double>;
+  constexpr int NT = (N + 15) / 16;
+  dx4 X[NT];
+  tile_forward_regs<N>(L, Linv, load, X, c0, ncol, l, I0);
+  const int li = l & 15;
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * I + M::row(l, r);
+      if (li < ncol && i < N) store(i, c0 + li, X[I][r]);
+    }
+}
+
 // The FP64 form for LDS-resident matrices and teams of whole waves
 // (chol_tiles16).  rd: 16 doubles of team LDS.
 template <int N, int TEAM>
@@ -756,6 +852,22 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
           }
         }
       }
+    } else if constexpr (!Lay::kGlobal && TEAM % 64 == 0 && TEAM / 64 >= (nb + 15) / 16) {
+      // Inverse of the face block L_bb by forward tile solves held in
+      // registers, a wave per 16-column tile, the 16-row blocks on the FP64
+      // matrix cores (the inverses of L_bb's diagonal blocks staged after Li)
+      double* LiB = stg + R::nbpk;
+      static_assert(Lay::area >= R::nbpk + ((nb + 15) / 16) * 256, "Li and the diagonal blocks' inverses fit");
+      auto Lbb = [=](int i, int j) -> double { return A[pk(ni + i, ni + j)]; };
+      diag_inverses<double, nb, TEAM>(Lbb, LiB, lane, true);
+      __syncthreads();
+      const int wv = lane / 64;
+      if (wv < (nb + 15) / 16)
+        tile_forward_reg<nb>(Lbb, LiB, [](int i, int c) { return i == c ? 1.0 : 0.0; },
+                             [=](int i, int c, double v) {
+                               if (i >= c) Li[pk(i, c)] = v;
+                             },
+                             16 * wv, nb - 16 * wv < 16 ? nb - 16 * wv : 16, lane % 64, wv);
     } else if constexpr (!Lay::kGlobal && TEAM % 64 == 0 && nb <= 64) {
       // Inverse of the face block L_bb, its columns dealt to the waves: lane
       // l holds row l of RC columns in registers, forward substitution row by
@@ -868,7 +980,57 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
     __syncthreads();
     // H_T = D L_bb^{-T} L_bb^{-1} D, scattered into H (lower triangle computed,
     // mirrored; same-face blocks receive two element terms by atomic add).
-    if (live && !a.stat) {
+    // Where the face block's inverse is in LDS and the team has whole waves,
+    // the lower 16 x 16 tiles of X^T X (X = L_bb^{-1}, lower triangular: the
+    // sum starts at row block I) on the FP64 matrix cores; else per entry.
+    auto scatter = [&](int aa, int bb, double h) {
+      const int fa = aa / K2, fb = bb / K2;
+      if (fid[fa] < 0 || fid[fb] < 0) return;
+      const double v = ((fa ^ fb) & 1) ? -h : h;
+      int a0 = (aa % K2) % K1, a1 = (aa % K2) / K1, b0 = (bb % K2) % K1, b1 = (bb % K2) / K1;
+      frame_map(pic[fa], K, a0, a1);
+      frame_map(pic[fb], K, b0, b1);
+      const int ja = a0 + K1 * a1, jb = b0 + K1 * b1;
+      const int Fa = fid[fa], Fb = fid[fb];
+      const int64_t pab = mp.face_rowbase[Fa] + int64_t(ja) * mp.face_nslots[Fa] * K2 +
+                          mp.elem_slot[e * 36 + fa * 6 + fb] * K2 + jb;
+      const int64_t pba = mp.face_rowbase[Fb] + int64_t(jb) * mp.face_nslots[Fb] * K2 +
+                          mp.elem_slot[e * 36 + fb * 6 + fa] * K2 + ja;
+      const double vw = v * (mp.face_w[ja] * mp.face_w[jb]);   // M_s H_T M_s (weighted C)
+      if (fa == fb) {
+        atomicAdd(&a.Hval[pab], vw);
+        if (aa != bb) atomicAdd(&a.Hval[pba], vw);
+      } else {
+        a.Hval[pab] = vw;
+        a.Hval[pba] = vw;
+      }
+    };
+    if constexpr (!Lay::kGlobal && TEAM % 64 == 0 && nb >= 16) {
+      using M = MfmaT<double>;
+      constexpr int NTb = (nb + 15) / 16, NW = TEAM / 64;
+      const int wv = lane / 64, l = lane % 64, li = l & 15, lk = l >> 4;
+      for (int t = a.stat ? (1 << 30) : wv; t < NTb * (NTb + 1) / 2; t += NW) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        const int J = t - I * (I + 1) / 2;
+        // column 16 I + li (A operand) and 16 J + li (B operand) of X, rows
+        // c >= the column (zero above the diagonal), clamped loads
+        const int ca = 16 * I + li, cb = 16 * J + li;
+        const int cac = ca < nb ? ca : nb - 1, cbc = cb < nb ? cb : nb - 1;
+        dx4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int c0 = 16 * I; c0 < nb; c0 += 4) {
+          const int c = c0 + lk, cc = c < nb ? c : nb - 1;
+          const double xa = Li[pk(cc, cc >= cac ? cac : cc)], xb = Li[pk(cc, cc >= cbc ? cbc : cc)];
+          acc = M::op((c < nb && ca < nb && c >= ca) ? xa : 0.0, (c < nb && cb < nb && c >= cb) ? xb : 0.0, acc);
+        }
+        if (!live) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int aa = 16 * I + M::row(l, r), bb = cb;
+          if (aa < nb && bb < nb && bb <= aa) scatter(aa, bb, acc[r]);
+        }
+      }
+    } else if (live && !a.stat) {
       for (int t = lane; t < R::nbpk; t += TEAM) {
         int aa, bb;
         unpk(t, aa, bb);
@@ -923,10 +1085,13 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       }
       __syncthreads();
     }
-    // y_b = L_bb^{-1} (f_b - L_bi y_i)
+    // y_b = L_bb^{-1} (f_b - L_bi y_i) (loops unrolled so that the loads run
+    // ahead of the chain of sums)
     for (int b = lane; b < nb; b += TEAM) {
       double s = fh[ni + b];
-      for (int j = 0; j < ni; ++j) s -= A[pk(ni + b, j)] * fh[j];
+      const double* rb = A + pk(ni + b, 0);
+#pragma unroll 8
+      for (int j = 0; j < ni; ++j) s -= rb[j] * fh[j];
       tb[b] = s;
     }
     __syncthreads();
@@ -935,7 +1100,13 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
       double s = tb[b];
       if (!a.stat) {
         s = 0.0;
-        for (int c = 0; c <= b; ++c) s += LI(b, c) * tb[c];
+        if constexpr (!Lay::kGlobal) {
+          const double* lr = Li + pk(b, 0);
+#pragma unroll 8
+          for (int c = 0; c <= b; ++c) s += lr[c] * tb[c];
+        } else {
+          for (int c = 0; c <= b; ++c) s += LI(b, c) * tb[c];
+        }
       }
       fh[ni + b] = s;
     }
@@ -951,7 +1122,16 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
           s = sigma(b) * fh[ni + b];
         } else {
           s = 0.0;
-          for (int c = b; c < nb; ++c) s += LI(c, b) * fh[ni + c];
+          if constexpr (!Lay::kGlobal) {
+            int p = pk(b, b);
+#pragma unroll 8
+            for (int c = b; c < nb; ++c) {
+              s += Li[p] * fh[ni + c];
+              p += c + 1;
+            }
+          } else {
+            for (int c = b; c < nb; ++c) s += LI(c, b) * fh[ni + c];
+          }
           if (!(fb & 1)) s = -s;
         }
         int b0 = (b % K2) % K1, b1 = (b % K2) / K1;
