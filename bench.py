@@ -410,7 +410,11 @@ def run_c4(args):
     lams = [rng.standard_normal(max(pl.m, 1)) for pl in plans]
     for i, p in enumerate(probs):
         b.set(i, p.alpha, p.beta, p.f, lam=lams[i])
-    tiles = b.autotune(reps=1)
+    if args.tiles:
+        tiles = tuple(int(x) for x in args.tiles.split(","))
+        b.tiles(*tiles)
+    else:
+        tiles = b.autotune(reps=1)
     b.graph(True)
     ts, setup_ms, rec_ms = _batch_run_timed(b, args.steps, args.warmup)
     if args.copy_calib:
@@ -423,7 +427,8 @@ def run_c4(args):
           file=sys.stderr, flush=True)
     flops = sum(algo_counts(p.k)["setup_flops"] * p.mesh.ne for p in probs)
     rbytes = sum(algo_counts(p.k)["recover_bytes"] * p.mesh.ne for p in probs)
-    roof = {"bound": "mfma", "kernel": "k_setup_batch (setup phase: k_batch_zero + k_setup_batch)",
+    roof = {"bound": "mfma", "kernel": "k_setup_batch<3,2,1,0> (setup phase: k_batch_zero, then one "
+                                        "persistent launch per order)",
             "achieved": flops / (setup_ms * 1e-3) / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": flops / (setup_ms * 1e-3) / FP64_PEAK,
             "traffic": traffic_from_profile("k_setup_batch", ne, "hbm_traffic_uneven_batch_64.json"),
@@ -679,6 +684,8 @@ def main():
                          "latency; c2: RT1 32^3; c3: RT2 48^3 jittered; c5: the serving stream; softhard: the "
                          "soft-hard materials study; spe10: the SPE10-shaped stand-in")
     ap.add_argument("--no-legs", action="store_true", help="c4: skip the C2 and C3 legs")
+    ap.add_argument("--tiles", default="", help="c4: fixed batch tiles 'blocks_per_cu,items_per_block' "
+                                                "instead of the autotuner's (profiling runs)")
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the stream")
     ap.add_argument("--nmin", type=int, default=8, help="c5: smallest mesh edge")
     ap.add_argument("--nmax", type=int, default=16, help="c5: largest mesh edge")

@@ -1163,8 +1163,9 @@ __global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
 // static condensation u_b = sigma x_b and u_i = L_ii^{-T} (y_i - L_bi^T u_b).
 // (k <= 2 also stage the factor's interior block, for a wave-level back
 // substitution, and its face block, read by rows and by columns, with
-// coalesced copies; for k = 3 the interior block alone would take 83 KB of
-// LDS per element)
+// coalesced copies; for k = 3 the two would take 125 KB of LDS per element,
+// one element per CU: measured 57 against 33 us per element for reading the
+// record directly with many elements in flight per CU)
 template <int K>
 constexpr bool recover_stages() { return K <= 2; }
 template <int K>
@@ -1188,8 +1189,6 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
   double* Lfb = Lii + ni * (ni + 1) / 2;   // its face block (packed)
   const double* F = a.factor + es * R::npk;
   const DeviceMaps& mp = a.mp;
-  // entry (b, c) of the face block: LDS copy (k <= 2) or the record
-  auto FB = [&](int b, int c) { return recover_stages<K>() ? Lfb[pk(b, c)] : F[pk(ni + b, ni + c)]; };
   for (int i = lane; i < n; i += TEAM) yv[i] = a.y[es * n + i];
   if constexpr (recover_stages<K>()) {
     for (int t = lane; t < ni * (ni + 1) / 2; t += TEAM) Lii[t] = F[t];
@@ -1223,22 +1222,39 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
   }
   __syncthreads();
   if (!a.stat) {
+    // (loops unrolled so that the loads run ahead of the chain of sums)
+    // (face row b: Lfb + pk(b, 0) in LDS, or F + pk(ni + b, ni) in the
+    // record; column b steps by the row lengths in both)
     for (int b = lane; b < nb; b += TEAM) {
       double s = yv[ni + b];
-      for (int c = 0; c <= b; ++c) s -= FB(b, c) * tl[c];
+      const double* fr = recover_stages<K>() ? Lfb + pk(b, 0) : F + pk(ni + b, ni);
+#pragma unroll 8
+      for (int c = 0; c <= b; ++c) s -= fr[c] * tl[c];
       zb[b] = s;
     }
     __syncthreads();
     for (int b = lane; b < nb; b += TEAM) {
       double s = 0.0;
-      for (int c = b; c < nb; ++c) s += FB(c, b) * zb[c];
+      const double* fc = recover_stages<K>() ? Lfb + pk(b, b) : F + pk(ni + b, ni + b);
+      int p = 0;
+#pragma unroll 8
+      for (int c = b; c < nb; ++c) {
+        s += fc[p] * zb[c];
+        p += (recover_stages<K>() ? c : ni + c) + 1;
+      }
       tl[b] = s;  // u_b
     }
     __syncthreads();
   }
   for (int j = lane; j < ni; j += TEAM) {
     double s = yv[j];
-    for (int b = 0; b < nb; ++b) s -= F[pk(ni + b, j)] * tl[b];
+    const double* fc = F + pk(ni, j);
+    int p = 0;
+#pragma unroll 8
+    for (int b = 0; b < nb; ++b) {
+      s -= fc[p] * tl[b];
+      p += ni + b + 1;
+    }
     zb[j] = s;
   }
   __syncthreads();
