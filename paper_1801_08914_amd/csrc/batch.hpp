@@ -123,12 +123,22 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
   for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem& it = items[__builtin_amdgcn_readfirstlane(int(w))];
     const RecoverArgs& a = probs[it.prob].r;
-    for (int b = 0; b < it.nblk; ++b) {
-      const int64_t blk = it.blk0 + b;
-      if constexpr (K == 0) recover_generic_body<0, 16, 32>(a, smem, blk);
-      else if constexpr (K == 1) recover_generic_body<1, 64, 8>(a, smem, blk);
-      else recover_generic_body<K, 512, 1>(a, smem, blk);
-      __syncthreads();
+    if constexpr (K == 3) {
+      // two elements per workgroup, a 256-lane team each (the single-plan
+      // team: the back substitution runs on one wave of a team, so two
+      // teams keep twice the elements in flight per CU)
+      for (int b = 0; b < it.nblk; b += 2) {
+        recover_generic_body<3, 256, 1>(a, smem, it.blk0 + b, it.blk0 + it.nblk);
+        __syncthreads();
+      }
+    } else {
+      for (int b = 0; b < it.nblk; ++b) {
+        const int64_t blk = it.blk0 + b;
+        if constexpr (K == 0) recover_generic_body<0, 16, 32>(a, smem, blk);
+        else if constexpr (K == 1) recover_generic_body<1, 64, 8>(a, smem, blk);
+        else recover_generic_body<K, 512, 1>(a, smem, blk);
+        __syncthreads();
+      }
     }
   }
 }
@@ -194,7 +204,7 @@ inline size_t batch_recover_lds(int k) {
     case 0: return 8 * 32 * size_t(recover_per<0>());
     case 1: return 8 * 8 * size_t(recover_per<1>());
     case 2: return 8 * size_t(recover_per<2>());
-    default: return 8 * size_t(recover_per<3>());
+    default: return 8 * 2 * size_t(recover_per<3>());
   }
 }
 

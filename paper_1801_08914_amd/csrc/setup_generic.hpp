@@ -651,8 +651,10 @@ __device__ __forceinline__ void wave_forward(const double* L, double* y, int lan
   __syncthreads();
 }
 
-// z := L^{-T} z with the same leading block (back substitution).
-template <int NI>
+// z := L^{-T} z with the same leading block (back substitution); UNROLL
+// steps of the column loop at a time, so that a factor in HBM has its loads
+// (which do not depend on z) in flight ahead of the chain of updates.
+template <int NI, int UNROLL = 1>
 __device__ __forceinline__ void wave_backward(const double* L, double* z, int lane) {
   constexpr int RPL = (NI + 63) / 64;
   if (RPL > 0 && lane < 64) {
@@ -665,6 +667,7 @@ __device__ __forceinline__ void wave_backward(const double* L, double* z, int la
 #pragma unroll
     for (int s = RPL - 1; s >= 0; --s) {
       const int cend = NI < 64 * (s + 1) ? NI : 64 * (s + 1);
+#pragma unroll UNROLL
       for (int c = cend - 1; c >= 64 * s; --c) {
         const double uc = wave_bcast(zr[s], c - 64 * s) / L[pk(c, c)];
 #pragma unroll
@@ -1174,13 +1177,16 @@ constexpr int recover_per() {
 }
 
 template <int K, int TEAM, int EPB>
-__device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, double* smem, int64_t blk) {
+__device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, double* smem, int64_t blk,
+                                                     int64_t e_end = INT64_MAX) {
   using R = RT<K>;
   constexpr int n = R::n, ni = R::ni, nb = R::nb, K1 = R::K1, K2 = R::K2;
   constexpr int per = recover_per<K>();
   const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
-  const int64_t e = blk * EPB + team;
-  const bool live = e < a.ne;
+  // element blk * EPB + team; blk counts elements instead when EPB is 1 and
+  // several teams share the workgroup (elements blk, blk + 1, .., below e_end)
+  const int64_t e = EPB == 1 ? blk + team : blk * EPB + team;
+  const bool live = e < a.ne && e < e_end;
   const int64_t es = live ? e : 0;
   double* yv = smem + team * per;   // y, then v / u
   double* zb = yv + n;              // z_b, then u_b
@@ -1260,6 +1266,9 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
   __syncthreads();
   if constexpr (TEAM >= 64 && recover_stages<K>()) {
     wave_backward<ni>(Lii, zb, lane);
+  } else if constexpr (TEAM >= 64) {
+    // one wave, the factor read from the record, 16 columns' loads in flight
+    wave_backward<ni, 16>(F, zb, lane);
   } else {
     const double* Lb = recover_stages<K>() ? Lii : F;
     for (int c = ni - 1; c >= 0; --c) {
