@@ -448,7 +448,7 @@ def run_c4(args):
            "config": {"workload": "uneven batch: 64 jittered n^3 problems, n~U{8..24}, k~U{0..3}, alpha and beta "
                                   "lognormal per problem, seed 4",
                       "elements": ne, "elements_by_order": by_k, "problems": len(probs),
-                      "precision": "fp64-plain", "launch": "one persistent launch per phase, hipGraph replay",
+                      "precision": "fp64-plain", "launch": "one persistent launch per order and phase, hipGraph replay",
                       "autotuned_tiles": {"blocks_per_cu": tiles[0], "items_per_block": tiles[1]}},
            "step_ms_p50": 1e3 * float(np.median(ts)), "step_ms_p90": 1e3 * float(np.percentile(ts, 90)),
            "host_planning_s": plan_s, "roofline": roof}
