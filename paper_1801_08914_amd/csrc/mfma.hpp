@@ -144,14 +144,15 @@ __device__ __forceinline__ int dof_index(int d, int a0, int a1, int a2) {
   return R::ni + (2 * d + (ic == 0 ? 0 : 1)) * R::K2 + j0 + R::K1 * j1;
 }
 
-// Whether the element assembly of order k uses sum factorization.  It needs
-// about 1.1 Mflop per RT3 element against 14.4 for the dense Gram sum on the
-// matrix cores and is then much faster; for k <= 2 the saving is small in
-// absolute terms (0.17 against 1.49 Mflop for RT2) and the dense sum's
-// independent tiles keep the lanes busier (RT2 48^3 setup measured 37.5 ms
-// dense against 49.9 ms factored).
+// Whether the element assembly of order k uses sum factorization: about
+// 1.1 Mflop per RT3 element and 0.17 per RT2 element against 14.4 and 1.49
+// for the dense Gram sum on the matrix cores.  Measured per element and CU:
+// RT2 45 against 59 us (at the single-plan register budget of 128, two
+// workgroups per CU, which its kernels carry as a launch bound; with the
+// compiler's 202 registers, one workgroup per CU, it lost: 65), RT1 9.6
+// against 10.9.  RT0 keeps the per-entry sum.
 template <int K>
-constexpr bool use_sumfact() { return K >= 3; }
+constexpr bool use_sumfact() { return K >= 1; }
 
 // The six component blocks (d, e), d <= e, of the sum-factorized assembly:
 // (0,0) (0,1) (0,2) (1,1) (1,2) (2,2).  Component d has np(d, x) 1D factors

@@ -770,11 +770,11 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   if (store_matrix) {
     if constexpr (use_sumfact<K>()) {
       static_assert(Lay::stage >= sumfact_stage<K>(), "the sum factorization's partial sums fit in the staging area");
-      assemble_sumfact<K, TEAM>(mp, qd, stg, lane, [&](int i, int j, double v) {
+      assemble_sumfact<K, TEAM>(mp, qd, stg, lane, [=](int i, int j, double v) {
         if (own) A[pk(i, j)] = v;
       });
     } else if constexpr (TEAM % 64 == 0) {
-      assemble_mfma<K, TEAM, kAsmQC>(mp, qd, stg, lane, [&](int i, int j, double v) {
+      assemble_mfma<K, TEAM, kAsmQC>(mp, qd, stg, lane, [=](int i, int j, double v) {
         if (own) A[pk(i, j)] = v;
       });
     } else {
@@ -807,11 +807,17 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   }
 
   if (a.mode & MODE_MATRIX) {
-    // boundary faces are essential: identity rows/columns
-    for (int p = lane; p < R::npk; p += TEAM) {
-      int i, j;
-      unpk(p, i, j);
-      if (own && (is_ess(i) || is_ess(j))) A[p] = (i == j) ? 1.0 : 0.0;
+    // boundary faces are essential: identity rows/columns (a pass over the
+    // matrix only for an element with an essential face)
+    bool any_ess = false;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) any_ess |= is_ess(ni + f * K2);
+    if (any_ess) {   // uniform across the team
+      for (int p = lane; p < R::npk; p += TEAM) {
+        int i, j;
+        unpk(p, i, j);
+        if (own && (is_ess(i) || is_ess(j))) A[p] = (i == j) ? 1.0 : 0.0;
+      }
     }
     __syncthreads();
     // Cholesky (interior block first, so L_bb L_bb^T is the element's Schur
@@ -1156,8 +1162,10 @@ __device__ __forceinline__ void setup_generic_body(const SetupArgs& a, double* s
   }
 }
 
+// (RT2: at most 128 registers, two workgroups per CU; measured faster than
+// the compiler's own choice, which takes one)
 template <int K, int TEAM, int EPB>
-__global__ __launch_bounds__(TEAM* EPB) void k_setup_generic(SetupArgs a) {
+__global__ __launch_bounds__(TEAM* EPB, K == 2 ? 4 : 2) void k_setup_generic(SetupArgs a) {
   __shared__ double smem[EPB * GenericLayout<K, TEAM, EPB>::per];
   setup_generic_body<K, TEAM, EPB>(a, smem, blockIdx.x);
 }
