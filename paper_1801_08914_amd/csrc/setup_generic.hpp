@@ -620,17 +620,21 @@ template <int NI>
 __device__ __forceinline__ void wave_forward(const double* L, double* y, int lane) {
   constexpr int RPL = (NI + 63) / 64;
   if (RPL > 0 && lane < 64) {
-    double yr[RPL > 0 ? RPL : 1];
+    // the reciprocals of the lane's diagonal entries first, off the chain of
+    // updates: a step multiplies by one in the lane of its row and
+    // broadcasts the product
+    double yr[RPL > 0 ? RPL : 1], rinv[RPL > 0 ? RPL : 1];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = lane + 64 * r;
       yr[r] = i < NI ? y[i] : 0.0;
+      rinv[r] = i < NI ? 1.0 / L[pk(i, i)] : 0.0;
     }
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
       const int cend = NI < 64 * (s + 1) ? NI : 64 * (s + 1);
       for (int c = 64 * s; c < cend; ++c) {
-        const double yc = wave_bcast(yr[s], c - 64 * s) / L[pk(c, c)];
+        const double yc = wave_bcast(yr[s] * rinv[s], c - 64 * s);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           // unconditional load (clamped address), masked product: no branch
