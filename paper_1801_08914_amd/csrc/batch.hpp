@@ -41,6 +41,72 @@ __host__ __device__ constexpr int batch_epb_mixed(int k) { return k == 0 ? 8 : (
 constexpr int kBatchThreads = 512;
 constexpr int kBatchThreadsK3 = 512;
 
+// A pointer read from a descriptor in memory is generic (flat) to the
+// compiler, and flat accesses count on the LDS wait counter too, so every
+// wait for an LDS result would also wait for the memory accesses in flight.
+// Every buffer of a problem is in device memory: the batch kernels pass each
+// pointer through the global address space, and the element routines
+// compile to global loads and stores.
+// (The pointers are wave-uniform: they are moved to scalar registers, and
+// an empty asm keeps the cast pair from folding away.)
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+  using G = __attribute__((address_space(1))) T*;
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint64_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+  const uint64_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
+  G g = reinterpret_cast<G>(lo | (hi << 32));
+  asm("" : "+s"(g));
+  return (T*)g;
+}
+
+__device__ __forceinline__ DeviceMaps global_maps(DeviceMaps m) {
+  m.e2v = as_global(m.e2v);
+  m.xyz = as_global(m.xyz);
+  m.elem_face = as_global(m.elem_face);
+  m.elem_pi = as_global(m.elem_pi);
+  m.elem_slot = as_global(m.elem_slot);
+  m.face_rowbase = as_global(m.face_rowbase);
+  m.face_nslots = as_global(m.face_nslots);
+  m.tab_s = as_global(m.tab_s);
+  m.tab_d = as_global(m.tab_d);
+  m.tab_w = as_global(m.tab_w);
+  m.tab_ref = as_global(m.tab_ref);
+  m.gauss_x = as_global(m.gauss_x);
+  m.face_selfslot = as_global(m.face_selfslot);
+  m.face_owner = as_global(m.face_owner);
+  m.k1_geo = as_global(m.k1_geo);
+  m.k1_meta = as_global(m.k1_meta);
+  m.face_w = as_global(m.face_w);
+  m.tab1d = as_global(m.tab1d);
+  return m;
+}
+
+__device__ __forceinline__ SetupArgs global_args(const SetupArgs& s) {
+  SetupArgs a = s;
+  a.mp = global_maps(s.mp);
+  a.alpha = as_global(s.alpha);
+  a.beta = as_global(s.beta);
+  a.f = as_global(s.f);
+  a.g = as_global(s.g);
+  a.factor = as_global(s.factor);
+  a.y = as_global(s.y);
+  a.Hval = as_global(s.Hval);
+  a.r = as_global(s.r);
+  a.status = as_global(s.status);
+  return a;
+}
+
+__device__ __forceinline__ RecoverArgs global_args(const RecoverArgs& s) {
+  RecoverArgs a = s;
+  a.mp = global_maps(s.mp);
+  a.factor = as_global(s.factor);
+  a.y = as_global(s.y);
+  a.lambda = as_global(s.lambda);
+  a.u = as_global(s.u);
+  return a;
+}
+
 // The mixed-precision element routines as separate functions: inlined into
 // one persistent kernel, the four bodies share one register allocation (and
 // spill); called, each keeps its own.  A call per element block.
@@ -91,9 +157,9 @@ __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
 // register allocation; inlined, the RT3 body spills).
 template <int K>
 __device__ __attribute__((noinline)) void batch_setup_call(const SetupArgs& a, double* smem, int64_t blk) {
-  if constexpr (K == 0) setup_generic_body<0, 16, 32>(a, smem, blk);
-  else if constexpr (K == 1) setup_generic_body<1, 64, 8>(a, smem, blk);
-  else setup_k3_body<kBatchThreadsK3>(a, smem, blk);
+  if constexpr (K == 0) setup_generic_body<0, 16, 32>(global_args(a), smem, blk);
+  else if constexpr (K == 1) setup_generic_body<1, 64, 8>(global_args(a), smem, blk);
+  else setup_k3_body<kBatchThreadsK3>(global_args(a), smem, blk);
 }
 
 template <int K>
@@ -107,7 +173,7 @@ __global__ __launch_bounds__(kBatchThreads, K == 2 ? 4 : 2) void k_setup_batch(c
     const SetupArgs& a = probs[it.prob].s;
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
-      if constexpr (K == 2) setup_generic_body<2, 512, 1>(a, smem, blk);
+      if constexpr (K == 2) setup_generic_body<2, 512, 1>(global_args(a), smem, blk);
       else batch_setup_call<K>(a, smem, blk);
       __syncthreads();   // the next block reuses the LDS
     }
@@ -122,15 +188,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
   __shared__ int64_t item;
   for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem& it = items[__builtin_amdgcn_readfirstlane(int(w))];
-    const RecoverArgs& a = probs[it.prob].r;
+    const RecoverArgs a = global_args(probs[it.prob].r);
     if constexpr (K == 3) {
-      // two elements per workgroup, a 256-lane team each (the single-plan
-      // team: the back substitution runs on one wave of a team, so two
-      // teams keep twice the elements in flight per CU)
-      for (int b = 0; b < it.nblk; b += 2) {
-        recover_generic_body<3, 256, 1>(a, smem, it.blk0 + b, it.blk0 + it.nblk);
-        __syncthreads();
-      }
+      // an item holds at most kRecoverTeams3 elements: one per wave
+      recover_generic_body<3, 64, 1>(a, smem, it.blk0, it.blk0 + it.nblk);
+      __syncthreads();
     } else {
       for (int b = 0; b < it.nblk; ++b) {
         const int64_t blk = it.blk0 + b;
@@ -204,7 +266,7 @@ inline size_t batch_recover_lds(int k) {
     case 0: return 8 * 32 * size_t(recover_per<0>());
     case 1: return 8 * 8 * size_t(recover_per<1>());
     case 2: return 8 * size_t(recover_per<2>());
-    default: return 8 * 2 * size_t(recover_per<3>());
+    default: return 8 * size_t(kRecoverTeams3) * size_t(recover_per<3>());
   }
 }
 

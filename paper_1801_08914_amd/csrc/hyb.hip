@@ -112,7 +112,7 @@ int dispatch_recover(int k, const hyb::RecoverArgs& a, hipStream_t s) {
     case 0: return launch_recover<0, 16, 16>(a, s);
     case 1: return launch_recover<1, 64, 4>(a, s);
     case 2: return launch_recover<2, 256, 1>(a, s);
-    case 3: return launch_recover<3, 256, 1>(a, s);
+    case 3: return launch_recover<3, 64, hyb::kRecoverTeams3>(a, s);
     default: return HYB_E_ARG;
   }
 }
@@ -815,6 +815,8 @@ struct hyb_batch {
   std::vector<hyb::BatchItem> items;       // cost-sorted work list: FP64 problems' items by order, then mixed
   size_t n64 = 0;                          // items of FP64 problems (the first n64)
   size_t beg[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};   // the FP64 items of order k
+  size_t n_mx = 0;                         // items of mixed problems (after the FP64 ones)
+  size_t beg_r3 = 0, cnt_r3 = 0;           // RT3 recovery items (after the mixed ones)
   hyb::BatchProb* d_probs = nullptr;
   hyb::BatchItem* d_items = nullptr;
   size_t cap_items = 0;
@@ -885,6 +887,23 @@ void batch_build_items(hyb_batch* b) {
     ++b->cnt[k];
     ++b->n64;
   }
+  b->n_mx = b->items.size() - b->n64;
+  // the RT3 recovery runs one element per wave, kRecoverTeams3 waves per
+  // workgroup: its own items of that many elements, whatever the tiles
+  b->beg_r3 = b->items.size();
+  b->cnt_r3 = 0;
+  for (size_t p = 0; p < b->plans.size(); ++p) {
+    const hyb::Plan& P = b->plans[p]->P;
+    if (P.mixed || P.ord.k != 3) continue;
+    for (int64_t q = 0; q < P.ne; q += hyb::kRecoverTeams3) {
+      hyb::BatchItem it{};
+      it.prob = int32_t(p);
+      it.blk0 = q;
+      it.nblk = int32_t(std::min<int64_t>(hyb::kRecoverTeams3, P.ne - q));
+      b->items.push_back(it);
+      ++b->cnt_r3;
+    }
+  }
   b->dirty = true;
 }
 
@@ -924,7 +943,7 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
   const unsigned zx = unsigned(std::min<int64_t>((zmax + 255) / 256, 1024));
   hipLaunchKernelGGL(hyb::k_batch_zero, dim3(zx, unsigned(b->probs.size())), dim3(256), 0, st, b->d_probs);
   HYB_HIP(hipGetLastError());
-  const size_t nmx = b->items.size() - b->n64;
+  const size_t nmx = b->n_mx;
   // the queue counters start at zero (a kernel, not a memset: graph replays)
   hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue, int64_t(5), 0);
   HYB_HIP(hipGetLastError());
@@ -949,7 +968,7 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
 }
 
 int batch_launch_recover(hyb_batch* b, hipStream_t st) {
-  const size_t nmx = b->items.size() - b->n64;
+  const size_t nmx = b->n_mx;
   hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue + 5, int64_t(5), 0);
   HYB_HIP(hipGetLastError());
   for (int k = 3; k >= 0; --k) {
@@ -958,8 +977,9 @@ int batch_launch_recover(hyb_batch* b, hipStream_t st) {
                       : k == 2 ? hyb::k_recover_batch<2>
                       : k == 1 ? hyb::k_recover_batch<1>
                                : hyb::k_recover_batch<0>;
-    hipLaunchKernelGGL(kern, dim3(batch_grid(b, b->cnt[k])), dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st,
-                       b->d_probs, b->d_items + b->beg[k], int64_t(b->cnt[k]), b->d_queue + 5 + k);
+    const size_t beg = k == 3 ? b->beg_r3 : b->beg[k], cnt = k == 3 ? b->cnt_r3 : b->cnt[k];
+    hipLaunchKernelGGL(kern, dim3(batch_grid(b, cnt)), dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st,
+                       b->d_probs, b->d_items + beg, int64_t(cnt), b->d_queue + 5 + k);
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {

@@ -1183,6 +1183,11 @@ __global__ __launch_bounds__(TEAM* EPB, K == 2 ? 4 : 2) void k_setup_generic(Set
 // record directly with many elements in flight per CU)
 template <int K>
 constexpr bool recover_stages() { return K <= 2; }
+// RT3 recovery: one wave per element, this many per workgroup.  Every step
+// waits on record loads (the back substitution on one wave in any case), so
+// the elements in flight per CU set the rate: 16 with 64-lane teams against
+// 4 with 256-lane ones.
+constexpr int kRecoverTeams3 = 8;
 template <int K>
 constexpr int recover_per() {
   return 2 * RT<K>::n + RT<K>::nb + (recover_stages<K>() ? RT<K>::ni * (RT<K>::ni + 1) / 2 + RT<K>::nbpk : 0);

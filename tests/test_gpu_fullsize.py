@@ -19,11 +19,17 @@ from tests.gpu_common import (accuracy_bound, gpu_setup, kappa_of, ld_row_errors
 pytestmark = pytest.mark.gpu
 
 
-def _sampled_parity(prob, nface=24, nel=24, seed=0):
+def _sampled_parity(prob, nface=24, nel=24, seed=0, plan=None, lam=None, u_all=None):
+    """``plan`` None: a single plan is set up here and recovered with a seeded
+    lambda; otherwise ``plan`` holds H and r already and ``u_all`` its
+    recovery for ``lam`` (a batch member)."""
     torch = require_gpu()
     k, mesh = prob.k, prob.mesh
     print(f"workload {prob.name}: {mesh.ne} elements, k={k}", flush=True)
-    plan = gpu_setup(mesh, k, prob.alpha, prob.beta, prob.f)
+    if plan is None:
+        plan = gpu_setup(mesh, k, prob.alpha, prob.beta, prob.f)
+        lam = np.random.default_rng(seed + 1).standard_normal(plan.m)
+        u_all = plan.recover(torch.as_tensor(lam, device="cuda")).cpu().numpy()
     rng = np.random.default_rng(seed)
     topo = otopo.build_topology(mesh.e2v)
     faces = np.sort(rng.choice(topo.nfaces, size=nface, replace=False))
@@ -49,14 +55,13 @@ def _sampled_parity(prob, nface=24, nel=24, seed=0):
     Hg = sp.csr_matrix((np.concatenate(data), np.concatenate(indices), np.array(indptr)), shape=(plan.m, plan.m))
     args = (k, mesh.xyz, mesh.e2v, prob.alpha, prob.beta, prob.f)
     ref = ohyb.hybridize(*args, topo=topo, elements=els)
-    lam = np.random.default_rng(seed + 1).standard_normal(plan.m)
     Hld, rld, U = oext.hybridize_ld(*args, topo, els, lam)
     # normwise over the sampled rows against the FP64 oracle
     nH = sp.linalg.norm(ref.H[rows] - Hg[rows]) / sp.linalg.norm(ref.H[rows])
     nr = norm_rel(ref.r[rows], rg[rows])
     eg, erg = ld_row_errors(Hld, rld, rows, Hg, rg)
     eo, ero = ld_row_errors(Hld, rld, rows, ref.H, ref.r)
-    u = plan.recover(torch.as_tensor(lam, device="cuda")).cpu().numpy()[els]
+    u = u_all[els]
     uref = ohyb.recover(ref, mesh.xyz, mesh.e2v, prob.alpha, prob.beta, prob.f, lam, elements=els)
     ul = np.array([U[e].astype(float) for e in els])
     nu = norm_rel(uref, u)
@@ -96,3 +101,34 @@ def test_c2_rt1_32cubed_sampled():
 
 def test_c3_rt2_48cubed_jittered_sampled():
     _sampled_parity(synth.config_c3(), nface=12, nel=12)
+
+
+def test_c4_uneven_batch_sampled():
+    """The full uneven batch (64 problems, n in 8..24, k in 0..3) in the
+    launch configuration the benchmark times (per-order persistent launches,
+    autotuned tiles, hipGraph replay): sampled rows and elements of one
+    problem of each order against the oracle."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Batch, Plan
+    probs = synth.config_c4()
+    plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True).bind() for p in probs]
+    b = Batch(plans)
+    rng = np.random.default_rng(0)
+    lams = [rng.standard_normal(max(pl.m, 1)) for pl in plans]
+    for i, p in enumerate(probs):
+        b.set(i, p.alpha, p.beta, p.f, lam=lams[i])
+    tiles = b.autotune(reps=1)
+    print(f"batch of {len(probs)}: {sum(p.mesh.ne for p in probs)} elements, tiles {tiles}", flush=True)
+    b.graph(True)
+    for _ in range(2):
+        b.setup()
+        b.recover()
+    torch.cuda.synchronize()
+    for i, pl in enumerate(plans):
+        rc, det = pl.status()
+        assert rc == 0, (i, rc, det)
+    for k in range(4):
+        i = next(i for i, p in enumerate(probs) if p.k == k)
+        n = plans[i].m
+        _sampled_parity(probs[i], nface=8, nel=8, seed=10 + k, plan=plans[i], lam=lams[i][:n],
+                        u_all=b.u(i).cpu().numpy())
