@@ -47,17 +47,15 @@ constexpr int kBatchThreadsK3 = 512;
 // Every buffer of a problem is in device memory: the batch kernels pass each
 // pointer through the global address space, and the element routines
 // compile to global loads and stores.
-// (The pointers are wave-uniform: they are moved to scalar registers, and
-// an empty asm keeps the cast pair from folding away.)
+// (The pointers are wave-uniform: rebuilt from scalar registers as global
+// pointers, a form the compiler does not fold back to the generic one.)
 template <typename T>
 __device__ __forceinline__ T* as_global(T* p) {
   using G = __attribute__((address_space(1))) T*;
   const uint64_t v = reinterpret_cast<uint64_t>(p);
   const uint64_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
   const uint64_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
-  G g = reinterpret_cast<G>(lo | (hi << 32));
-  asm("" : "+s"(g));
-  return (T*)g;
+  return (T*)reinterpret_cast<G>(lo | (hi << 32));
 }
 
 __device__ __forceinline__ DeviceMaps global_maps(DeviceMaps m) {
@@ -151,10 +149,11 @@ __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
 // The FP64 problems of order K: setup, then recovery.  The descriptors and
 // items are read-only and not aliased, and the item index is made
 // wave-uniform, so the arguments load into scalar registers.  Setup bodies
-// per order as measured best: RT2 inline, with the register budget of the
-// single-plan kernel (at most 128, two workgroups per CU; without the bound
-// the persistent loop takes 183 and one); the others called (their own
-// register allocation; inlined, the RT3 body spills).
+// per order: RT2 inline, with the register budget of the single-plan kernel
+// (at most 128, two workgroups per CU; without the bound the persistent loop
+// takes 183 and one); the others called, one call per element block (their
+// own register allocation; inlined, the RT3 body spills 924 bytes against
+// 400 called).
 template <int K>
 __device__ __attribute__((noinline)) void batch_setup_call(const SetupArgs& a, double* smem, int64_t blk) {
   if constexpr (K == 0) setup_generic_body<0, 16, 32>(global_args(a), smem, blk);
@@ -189,16 +188,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
   for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem& it = items[__builtin_amdgcn_readfirstlane(int(w))];
     const RecoverArgs a = global_args(probs[it.prob].r);
-    if constexpr (K == 3) {
-      // an item holds at most kRecoverTeams3 elements: one per wave
-      recover_generic_body<3, 64, 1>(a, smem, it.blk0, it.blk0 + it.nblk);
+    if constexpr (K >= 2) {
+      // an item holds at most recover_teams(K) elements, one per team
+      recover_generic_body<K, recover_team(K), 1>(a, smem, it.blk0, it.blk0 + it.nblk);
       __syncthreads();
     } else {
       for (int b = 0; b < it.nblk; ++b) {
         const int64_t blk = it.blk0 + b;
         if constexpr (K == 0) recover_generic_body<0, 16, 32>(a, smem, blk);
-        else if constexpr (K == 1) recover_generic_body<1, 64, 8>(a, smem, blk);
-        else recover_generic_body<K, 512, 1>(a, smem, blk);
+        else recover_generic_body<1, 64, 8>(a, smem, blk);
         __syncthreads();
       }
     }
@@ -265,8 +263,8 @@ inline size_t batch_recover_lds(int k) {
   switch (k) {
     case 0: return 8 * 32 * size_t(recover_per<0>());
     case 1: return 8 * 8 * size_t(recover_per<1>());
-    case 2: return 8 * size_t(recover_per<2>());
-    default: return 8 * size_t(kRecoverTeams3) * size_t(recover_per<3>());
+    case 2: return 8 * size_t(recover_teams(2)) * size_t(recover_per<2>());
+    default: return 8 * size_t(recover_teams(3)) * size_t(recover_per<3>());
   }
 }
 

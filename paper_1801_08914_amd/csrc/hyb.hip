@@ -111,8 +111,8 @@ int dispatch_recover(int k, const hyb::RecoverArgs& a, hipStream_t s) {
   switch (k) {
     case 0: return launch_recover<0, 16, 16>(a, s);
     case 1: return launch_recover<1, 64, 4>(a, s);
-    case 2: return launch_recover<2, 256, 1>(a, s);
-    case 3: return launch_recover<3, 64, hyb::kRecoverTeams3>(a, s);
+    case 2: return launch_recover<2, hyb::recover_team(2), 1>(a, s);
+    case 3: return launch_recover<3, hyb::recover_team(3), hyb::recover_teams(3)>(a, s);
     default: return HYB_E_ARG;
   }
 }
@@ -816,7 +816,7 @@ struct hyb_batch {
   size_t n64 = 0;                          // items of FP64 problems (the first n64)
   size_t beg[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};   // the FP64 items of order k
   size_t n_mx = 0;                         // items of mixed problems (after the FP64 ones)
-  size_t beg_r3 = 0, cnt_r3 = 0;           // RT3 recovery items (after the mixed ones)
+  size_t beg_r[4] = {0, 0, 0, 0}, cnt_r[4] = {0, 0, 0, 0};   // RT2/RT3 recovery items (after the mixed ones)
   hyb::BatchProb* d_probs = nullptr;
   hyb::BatchItem* d_items = nullptr;
   size_t cap_items = 0;
@@ -888,20 +888,23 @@ void batch_build_items(hyb_batch* b) {
     ++b->n64;
   }
   b->n_mx = b->items.size() - b->n64;
-  // the RT3 recovery runs one element per wave, kRecoverTeams3 waves per
-  // workgroup: its own items of that many elements, whatever the tiles
-  b->beg_r3 = b->items.size();
-  b->cnt_r3 = 0;
-  for (size_t p = 0; p < b->plans.size(); ++p) {
-    const hyb::Plan& P = b->plans[p]->P;
-    if (P.mixed || P.ord.k != 3) continue;
-    for (int64_t q = 0; q < P.ne; q += hyb::kRecoverTeams3) {
-      hyb::BatchItem it{};
-      it.prob = int32_t(p);
-      it.blk0 = q;
-      it.nblk = int32_t(std::min<int64_t>(hyb::kRecoverTeams3, P.ne - q));
-      b->items.push_back(it);
-      ++b->cnt_r3;
+  // the RT2 and RT3 recoveries run several elements per workgroup, one per
+  // team: their own items of that many elements, whatever the tiles
+  for (int k = 3; k >= 2; --k) {
+    const int per = hyb::recover_teams(k);
+    b->beg_r[k] = b->items.size();
+    b->cnt_r[k] = 0;
+    for (size_t p = 0; p < b->plans.size(); ++p) {
+      const hyb::Plan& P = b->plans[p]->P;
+      if (P.mixed || P.ord.k != k) continue;
+      for (int64_t q = 0; q < P.ne; q += per) {
+        hyb::BatchItem it{};
+        it.prob = int32_t(p);
+        it.blk0 = q;
+        it.nblk = int32_t(std::min<int64_t>(per, P.ne - q));
+        b->items.push_back(it);
+        ++b->cnt_r[k];
+      }
     }
   }
   b->dirty = true;
@@ -977,9 +980,12 @@ int batch_launch_recover(hyb_batch* b, hipStream_t st) {
                       : k == 2 ? hyb::k_recover_batch<2>
                       : k == 1 ? hyb::k_recover_batch<1>
                                : hyb::k_recover_batch<0>;
-    const size_t beg = k == 3 ? b->beg_r3 : b->beg[k], cnt = k == 3 ? b->cnt_r3 : b->cnt[k];
-    hipLaunchKernelGGL(kern, dim3(batch_grid(b, cnt)), dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st,
-                       b->d_probs, b->d_items + beg, int64_t(cnt), b->d_queue + 5 + k);
+    const size_t beg = k >= 2 ? b->beg_r[k] : b->beg[k], cnt = k >= 2 ? b->cnt_r[k] : b->cnt[k];
+    // (RT2/RT3: as many workgroups as fit on a CU, whatever the tiles)
+    const unsigned grid = k >= 2 ? unsigned(std::max<int64_t>(1, std::min<int64_t>(int64_t(cnt), 4 * b->cus)))
+                                 : batch_grid(b, cnt);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st, b->d_probs,
+                       b->d_items + beg, int64_t(cnt), b->d_queue + 5 + k);
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {
