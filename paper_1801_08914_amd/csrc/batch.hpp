@@ -148,17 +148,13 @@ __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
 
 // The FP64 problems of order K: setup, then recovery.  The descriptors and
 // items are read-only and not aliased, and the item index is made
-// wave-uniform, so the arguments load into scalar registers.  Setup bodies
-// per order: RT2 inline, with the register budget of the single-plan kernel
-// (at most 128, two workgroups per CU; without the bound the persistent loop
-// takes 183 and one); the others called, one call per element block (their
-// own register allocation; inlined, the RT3 body spills 924 bytes against
-// 400 called).
+// wave-uniform, so the arguments load into scalar registers.  The RT0 and
+// RT1 setup bodies are called, one call per element block (each its own
+// register allocation).  RT2 and RT3 setups run in k_setup_multi below.
 template <int K>
 __device__ __attribute__((noinline)) void batch_setup_call(const SetupArgs& a, double* smem, int64_t blk) {
   if constexpr (K == 0) setup_generic_body<0, 16, 32>(global_args(a), smem, blk);
-  else if constexpr (K == 1) setup_generic_body<1, 64, 8>(global_args(a), smem, blk);
-  else setup_k3_body<kBatchThreadsK3>(global_args(a), smem, blk);
+  else setup_generic_body<1, 64, 8>(global_args(a), smem, blk);
 }
 
 template <int K>
@@ -172,11 +168,40 @@ __global__ __launch_bounds__(kBatchThreads, K == 2 ? 4 : 2) void k_setup_batch(c
     const SetupArgs& a = probs[it.prob].s;
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
-      if constexpr (K == 2) setup_generic_body<2, 512, 1>(global_args(a), smem, blk);
-      else batch_setup_call<K>(a, smem, blk);
+      batch_setup_call<K>(a, smem, blk);
       __syncthreads();   // the next block reuses the LDS
     }
   }
+}
+
+// RT2 and RT3 setups of the FP64 problems: up to kMultiProbs problems per
+// launch, their descriptors in the kernel arguments, one element per
+// workgroup, each problem's elements a consecutive range of the grid (the
+// hardware hands out the workgroups as CUs free up).  The body then compiles
+// as in the single-plan kernels: descriptor fields are loaded from the
+// argument segment where they are used, while a persistent loop over work
+// items keeps them live across the body and spills (RT2 inlined in such a
+// loop: 1040 bytes of spills against 276 here, 63 against 44 us per element
+// and CU; RT3 called from it: 400 bytes and 177 against 158 us).
+constexpr int kMultiProbs = 8;
+struct MultiArgs {
+  SetupArgs p[kMultiProbs];
+  int64_t start[kMultiProbs + 1];   // first workgroup of each problem; start[np] = grid
+  int32_t np;
+};
+
+template <int K>
+__global__ __launch_bounds__(kBatchThreads, K == 2 ? 4 : 1) void k_setup_multi(MultiArgs m) {
+  static_assert(K == 2 || K == 3, "RT2 and RT3 only");
+  extern __shared__ double smem[];
+  const int64_t g = blockIdx.x;
+  int pi = 0;
+#pragma unroll
+  for (int q = 1; q < kMultiProbs; ++q) pi += (q < m.np && g >= m.start[q]) ? 1 : 0;
+  pi = __builtin_amdgcn_readfirstlane(pi);
+  const SetupArgs& a = m.p[pi];
+  if constexpr (K == 2) setup_generic_body<2, 512, 1>(a, smem, g - m.start[pi]);
+  else setup_k3_body<kBatchThreadsK3>(a, smem, g - m.start[pi]);
 }
 
 template <int K>

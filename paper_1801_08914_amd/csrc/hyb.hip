@@ -861,6 +861,7 @@ void batch_build_items(hyb_batch* b) {
   b->items.clear();
   for (size_t p = 0; p < b->plans.size(); ++p) {
     const hyb::Plan& P = b->plans[p]->P;
+    if (!P.mixed && P.ord.k >= 2) continue;   // RT2/RT3 setups: k_setup_multi
     const int epb = batch_epb_of(P);
     const int64_t nblk = (P.ne + epb - 1) / epb;
     for (int64_t q = 0; q < nblk; q += ipb) {
@@ -950,15 +951,29 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
   // the queue counters start at zero (a kernel, not a memset: graph replays)
   hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue, int64_t(5), 0);
   HYB_HIP(hipGetLastError());
-  // the orders' launches, most expensive first
-  for (int k = 3; k >= 0; --k) {
+  // the orders' launches, most expensive first: RT3 and RT2 problems
+  // kMultiProbs at a time, their descriptors in the kernel arguments
+  for (int k = 3; k >= 2; --k) {
+    hyb::MultiArgs m{};
+    for (size_t p = 0; p <= b->probs.size(); ++p) {
+      const bool take = p < b->probs.size() && !b->probs[p].mixed && b->probs[p].k == k && b->probs[p].s.ne > 0;
+      if (take) {
+        m.start[m.np + 1] = m.start[m.np] + b->probs[p].s.ne;
+        m.p[m.np++] = b->probs[p].s;
+      }
+      if (m.np == hyb::kMultiProbs || (p == b->probs.size() && m.np > 0)) {
+        hipLaunchKernelGGL(k == 3 ? hyb::k_setup_multi<3> : hyb::k_setup_multi<2>, dim3(unsigned(m.start[m.np])),
+                           dim3(hyb::kBatchThreads), hyb::batch_setup_lds(k), st, m);
+        HYB_HIP(hipGetLastError());
+        m = hyb::MultiArgs{};
+      }
+    }
+  }
+  for (int k = 1; k >= 0; --k) {
     if (!b->cnt[k]) continue;
-    const auto kern = k == 3 ? hyb::k_setup_batch<3>
-                      : k == 2 ? hyb::k_setup_batch<2>
-                      : k == 1 ? hyb::k_setup_batch<1>
-                               : hyb::k_setup_batch<0>;
-    hipLaunchKernelGGL(kern, dim3(batch_grid(b, b->cnt[k])), dim3(hyb::kBatchThreads), hyb::batch_setup_lds(k), st,
-                       b->d_probs, b->d_items + b->beg[k], int64_t(b->cnt[k]), b->d_queue + k);
+    hipLaunchKernelGGL(k == 1 ? hyb::k_setup_batch<1> : hyb::k_setup_batch<0>, dim3(batch_grid(b, b->cnt[k])),
+                       dim3(hyb::kBatchThreads), hyb::batch_setup_lds(k), st, b->d_probs, b->d_items + b->beg[k],
+                       int64_t(b->cnt[k]), b->d_queue + k);
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {
@@ -975,12 +990,12 @@ int batch_launch_recover(hyb_batch* b, hipStream_t st) {
   hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue + 5, int64_t(5), 0);
   HYB_HIP(hipGetLastError());
   for (int k = 3; k >= 0; --k) {
-    if (!b->cnt[k]) continue;
+    const size_t beg = k >= 2 ? b->beg_r[k] : b->beg[k], cnt = k >= 2 ? b->cnt_r[k] : b->cnt[k];
+    if (!cnt) continue;
     const auto kern = k == 3 ? hyb::k_recover_batch<3>
                       : k == 2 ? hyb::k_recover_batch<2>
                       : k == 1 ? hyb::k_recover_batch<1>
                                : hyb::k_recover_batch<0>;
-    const size_t beg = k >= 2 ? b->beg_r[k] : b->beg[k], cnt = k >= 2 ? b->cnt_r[k] : b->cnt[k];
     // (RT2/RT3: as many workgroups as fit on a CU, whatever the tiles)
     const unsigned grid = k >= 2 ? unsigned(std::max<int64_t>(1, std::min<int64_t>(int64_t(cnt), 4 * b->cus)))
                                  : batch_grid(b, cnt);
@@ -1114,8 +1129,8 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
   {
     const void* ks[4] = {reinterpret_cast<const void*>(hyb::k_setup_batch<0>),
                          reinterpret_cast<const void*>(hyb::k_setup_batch<1>),
-                         reinterpret_cast<const void*>(hyb::k_setup_batch<2>),
-                         reinterpret_cast<const void*>(hyb::k_setup_batch<3>)};
+                         reinterpret_cast<const void*>(hyb::k_setup_multi<2>),
+                         reinterpret_cast<const void*>(hyb::k_setup_multi<3>)};
     const void* kr[4] = {reinterpret_cast<const void*>(hyb::k_recover_batch<0>),
                          reinterpret_cast<const void*>(hyb::k_recover_batch<1>),
                          reinterpret_cast<const void*>(hyb::k_recover_batch<2>),
