@@ -427,16 +427,16 @@ def run_c4(args):
           file=sys.stderr, flush=True)
     flops = sum(algo_counts(p.k)["setup_flops"] * p.mesh.ne for p in probs)
     rbytes = sum(algo_counts(p.k)["recover_bytes"] * p.mesh.ne for p in probs)
-    roof = {"bound": "mfma", "kernel": "k_setup_batch<3,2,1,0> (setup phase: k_batch_zero, then one "
-                                        "persistent launch per order)",
+    roof = {"bound": "mfma", "kernel": "setup phase: k_batch_zero, k_setup_multi<3> and <2> (up to eight "
+                                        "problems per launch), persistent k_setup_batch<1> and <0>",
             "achieved": flops / (setup_ms * 1e-3) / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": flops / (setup_ms * 1e-3) / FP64_PEAK,
-            "traffic": traffic_from_profile("k_setup_batch", ne, "hbm_traffic_uneven_batch_64.json"),
+            "traffic": traffic_from_profile("setup", ne, "hbm_traffic_uneven_batch_64.json"),
             "phase_ms": setup_ms, "algorithmic_flops": flops,
             "flops_per_element_by_order": {k: algo_counts(k)["setup_flops"] for k in range(4)},
             "recover_phase_ms": rec_ms, "recover_hbm_gbs": rbytes / (rec_ms * 1e-3) / 1e9,
             "recover_hbm_frac": rbytes / (rec_ms * 1e-3) / HBM_PEAK,
-            "recover_traffic": traffic_from_profile("k_recover_batch", ne, "hbm_traffic_uneven_batch_64.json")}
+            "recover_traffic": traffic_from_profile("recover", ne, "hbm_traffic_uneven_batch_64.json")}
     picks = [next(i for i, p in enumerate(probs) if p.k == k) for k in range(4) if any(p.k == k for p in probs)]
     parity = None if args.no_parity else _c4_parity(probs, plans, lams, picks)
     del b, plans
@@ -448,7 +448,9 @@ def run_c4(args):
            "config": {"workload": "uneven batch: 64 jittered n^3 problems, n~U{8..24}, k~U{0..3}, alpha and beta "
                                   "lognormal per problem, seed 4",
                       "elements": ne, "elements_by_order": by_k, "problems": len(probs),
-                      "precision": "fp64-plain", "launch": "one persistent launch per order and phase, hipGraph replay",
+                      "precision": "fp64-plain",
+                      "launch": "RT2/RT3 setups up to eight problems per launch, other orders and recoveries one "
+                                "persistent launch per order, hipGraph replay",
                       "autotuned_tiles": {"blocks_per_cu": tiles[0], "items_per_block": tiles[1]}},
            "step_ms_p50": 1e3 * float(np.median(ts)), "step_ms_p90": 1e3 * float(np.percentile(ts, 90)),
            "host_planning_s": plan_s, "roofline": roof}

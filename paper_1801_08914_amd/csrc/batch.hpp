@@ -1,8 +1,10 @@
-// Batches of independent problems of mixed order: per order present, one
-// persistent launch walks that order's part of a cost-sorted list of work
-// items (problem, run of element blocks) and runs the order's element
-// routine on each (a kernel per order: each gets the register allocation,
-// and so the occupancy, of the single-plan kernel of that order).
+// Batches of independent problems of mixed order, a kernel per order and
+// phase (each gets the register allocation, and so the occupancy, of the
+// single-plan kernel of that order).  RT0 and RT1: one persistent launch
+// walks that order's part of a cost-sorted list of work items (problem, run
+// of element blocks).  RT2 and RT3: launches of up to eight problems with
+// their descriptors in the kernel arguments.  Mixed-precision problems: one
+// persistent launch over their items.
 #pragma once
 
 #include "kernels_common.hpp"
@@ -183,25 +185,46 @@ __global__ __launch_bounds__(kBatchThreads, K == 2 ? 4 : 2) void k_setup_batch(c
 // items keeps them live across the body and spills (RT2 inlined in such a
 // loop: 1040 bytes of spills against 276 here, 63 against 44 us per element
 // and CU; RT3 called from it: 400 bytes and 177 against 158 us).
+// The recoveries of RT2 and RT3 problems likewise (recover_teams(K)
+// elements per workgroup).
 constexpr int kMultiProbs = 8;
-struct MultiArgs {
-  SetupArgs p[kMultiProbs];
+template <class Args>
+struct MultiT {
+  Args p[kMultiProbs];
   int64_t start[kMultiProbs + 1];   // first workgroup of each problem; start[np] = grid
   int32_t np;
 };
+using MultiArgs = MultiT<SetupArgs>;
+using MultiRecArgs = MultiT<RecoverArgs>;
+
+// The problem of workgroup g (wave-uniform).
+template <class Args>
+__device__ __forceinline__ int multi_problem(const MultiT<Args>& m, int64_t g) {
+  int pi = 0;
+#pragma unroll
+  for (int q = 1; q < kMultiProbs; ++q) pi += (q < m.np && g >= m.start[q]) ? 1 : 0;
+  return __builtin_amdgcn_readfirstlane(pi);
+}
 
 template <int K>
 __global__ __launch_bounds__(kBatchThreads, K == 2 ? 4 : 1) void k_setup_multi(MultiArgs m) {
   static_assert(K == 2 || K == 3, "RT2 and RT3 only");
   extern __shared__ double smem[];
   const int64_t g = blockIdx.x;
-  int pi = 0;
-#pragma unroll
-  for (int q = 1; q < kMultiProbs; ++q) pi += (q < m.np && g >= m.start[q]) ? 1 : 0;
-  pi = __builtin_amdgcn_readfirstlane(pi);
+  const int pi = multi_problem(m, g);
   const SetupArgs& a = m.p[pi];
   if constexpr (K == 2) setup_generic_body<2, 512, 1>(a, smem, g - m.start[pi]);
   else setup_k3_body<kBatchThreadsK3>(a, smem, g - m.start[pi]);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBatchThreads) void k_recover_multi(MultiRecArgs m) {
+  static_assert(K == 2 || K == 3, "RT2 and RT3 only");
+  static_assert(recover_team(K) * recover_teams(K) == kBatchThreads, "one element per team");
+  extern __shared__ double smem[];
+  const int64_t g = blockIdx.x;
+  const int pi = multi_problem(m, g);
+  recover_generic_body<K, recover_team(K), recover_teams(K)>(m.p[pi], smem, g - m.start[pi]);
 }
 
 template <int K>
@@ -213,17 +236,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb
   for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem& it = items[__builtin_amdgcn_readfirstlane(int(w))];
     const RecoverArgs a = global_args(probs[it.prob].r);
-    if constexpr (K >= 2) {
-      // an item holds at most recover_teams(K) elements, one per team
-      recover_generic_body<K, recover_team(K), 1>(a, smem, it.blk0, it.blk0 + it.nblk);
+    for (int b = 0; b < it.nblk; ++b) {
+      const int64_t blk = it.blk0 + b;
+      if constexpr (K == 0) recover_generic_body<0, 16, 32>(a, smem, blk);
+      else recover_generic_body<1, 64, 8>(a, smem, blk);
       __syncthreads();
-    } else {
-      for (int b = 0; b < it.nblk; ++b) {
-        const int64_t blk = it.blk0 + b;
-        if constexpr (K == 0) recover_generic_body<0, 16, 32>(a, smem, blk);
-        else recover_generic_body<1, 64, 8>(a, smem, blk);
-        __syncthreads();
-      }
     }
   }
 }

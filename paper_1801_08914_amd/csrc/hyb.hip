@@ -812,11 +812,10 @@ struct hyb_batch {
   int cus = 0;
   hyb_batch_tiles tiles{0, 0};
   std::vector<hyb::BatchProb> probs;       // host copy of the descriptors
-  std::vector<hyb::BatchItem> items;       // cost-sorted work list: FP64 problems' items by order, then mixed
+  std::vector<hyb::BatchItem> items;       // cost-sorted work list: FP64 RT0/RT1 items by order, then mixed
   size_t n64 = 0;                          // items of FP64 problems (the first n64)
   size_t beg[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};   // the FP64 items of order k
   size_t n_mx = 0;                         // items of mixed problems (after the FP64 ones)
-  size_t beg_r[4] = {0, 0, 0, 0}, cnt_r[4] = {0, 0, 0, 0};   // RT2/RT3 recovery items (after the mixed ones)
   hyb::BatchProb* d_probs = nullptr;
   hyb::BatchItem* d_items = nullptr;
   size_t cap_items = 0;
@@ -861,7 +860,7 @@ void batch_build_items(hyb_batch* b) {
   b->items.clear();
   for (size_t p = 0; p < b->plans.size(); ++p) {
     const hyb::Plan& P = b->plans[p]->P;
-    if (!P.mixed && P.ord.k >= 2) continue;   // RT2/RT3 setups: k_setup_multi
+    if (!P.mixed && P.ord.k >= 2) continue;   // RT2/RT3: k_setup_multi, k_recover_multi
     const int epb = batch_epb_of(P);
     const int64_t nblk = (P.ne + epb - 1) / epb;
     for (int64_t q = 0; q < nblk; q += ipb) {
@@ -889,25 +888,6 @@ void batch_build_items(hyb_batch* b) {
     ++b->n64;
   }
   b->n_mx = b->items.size() - b->n64;
-  // the RT2 and RT3 recoveries run several elements per workgroup, one per
-  // team: their own items of that many elements, whatever the tiles
-  for (int k = 3; k >= 2; --k) {
-    const int per = hyb::recover_teams(k);
-    b->beg_r[k] = b->items.size();
-    b->cnt_r[k] = 0;
-    for (size_t p = 0; p < b->plans.size(); ++p) {
-      const hyb::Plan& P = b->plans[p]->P;
-      if (P.mixed || P.ord.k != k) continue;
-      for (int64_t q = 0; q < P.ne; q += per) {
-        hyb::BatchItem it{};
-        it.prob = int32_t(p);
-        it.blk0 = q;
-        it.nblk = int32_t(std::min<int64_t>(per, P.ne - q));
-        b->items.push_back(it);
-        ++b->cnt_r[k];
-      }
-    }
-  }
   b->dirty = true;
 }
 
@@ -989,18 +969,28 @@ int batch_launch_recover(hyb_batch* b, hipStream_t st) {
   const size_t nmx = b->n_mx;
   hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue + 5, int64_t(5), 0);
   HYB_HIP(hipGetLastError());
-  for (int k = 3; k >= 0; --k) {
-    const size_t beg = k >= 2 ? b->beg_r[k] : b->beg[k], cnt = k >= 2 ? b->cnt_r[k] : b->cnt[k];
-    if (!cnt) continue;
-    const auto kern = k == 3 ? hyb::k_recover_batch<3>
-                      : k == 2 ? hyb::k_recover_batch<2>
-                      : k == 1 ? hyb::k_recover_batch<1>
-                               : hyb::k_recover_batch<0>;
-    // (RT2/RT3: as many workgroups as fit on a CU, whatever the tiles)
-    const unsigned grid = k >= 2 ? unsigned(std::max<int64_t>(1, std::min<int64_t>(int64_t(cnt), 4 * b->cus)))
-                                 : batch_grid(b, cnt);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st, b->d_probs,
-                       b->d_items + beg, int64_t(cnt), b->d_queue + 5 + k);
+  for (int k = 3; k >= 2; --k) {
+    const int per = hyb::recover_teams(k);
+    hyb::MultiRecArgs m{};
+    for (size_t p = 0; p <= b->probs.size(); ++p) {
+      const bool take = p < b->probs.size() && !b->probs[p].mixed && b->probs[p].k == k && b->probs[p].r.ne > 0;
+      if (take) {
+        m.start[m.np + 1] = m.start[m.np] + (b->probs[p].r.ne + per - 1) / per;
+        m.p[m.np++] = b->probs[p].r;
+      }
+      if (m.np == hyb::kMultiProbs || (p == b->probs.size() && m.np > 0)) {
+        hipLaunchKernelGGL(k == 3 ? hyb::k_recover_multi<3> : hyb::k_recover_multi<2>, dim3(unsigned(m.start[m.np])),
+                           dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st, m);
+        HYB_HIP(hipGetLastError());
+        m = hyb::MultiRecArgs{};
+      }
+    }
+  }
+  for (int k = 1; k >= 0; --k) {
+    if (!b->cnt[k]) continue;
+    hipLaunchKernelGGL(k == 1 ? hyb::k_recover_batch<1> : hyb::k_recover_batch<0>, dim3(batch_grid(b, b->cnt[k])),
+                       dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st, b->d_probs, b->d_items + b->beg[k],
+                       int64_t(b->cnt[k]), b->d_queue + 5 + k);
     HYB_HIP(hipGetLastError());
   }
   if (nmx) {
@@ -1133,8 +1123,8 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
                          reinterpret_cast<const void*>(hyb::k_setup_multi<3>)};
     const void* kr[4] = {reinterpret_cast<const void*>(hyb::k_recover_batch<0>),
                          reinterpret_cast<const void*>(hyb::k_recover_batch<1>),
-                         reinterpret_cast<const void*>(hyb::k_recover_batch<2>),
-                         reinterpret_cast<const void*>(hyb::k_recover_batch<3>)};
+                         reinterpret_cast<const void*>(hyb::k_recover_multi<2>),
+                         reinterpret_cast<const void*>(hyb::k_recover_multi<3>)};
     for (int k = 0; k < 4 && e1 == hipSuccess; ++k) {
       e1 = hipFuncSetAttribute(ks[k], hipFuncAttributeMaxDynamicSharedMemorySize, int(hyb::batch_setup_lds(k)));
       if (e1 == hipSuccess)
