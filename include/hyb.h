@@ -337,29 +337,33 @@ void hyb_destroy(hyb_plan_t* plan);
 /*
  * ---------------------------------------------------------------------------
  * Batches of independent problems of mixed order and mesh (the uneven batch
- * of many small hybridization problems; each problem is a bound plan).  The
- * setup of every element of every problem runs in ONE persistent launch (after
- * one launch that clears the same-face blocks of every H), the recovery in
- * another; work items (problem, run of element blocks) are sorted by cost and
- * taken from a work queue (an atomic counter, most expensive first) by a
- * grid of blocks_per_cu x (compute units) workgroups.
+ * of many small hybridization problems; each problem is a bound plan).  After
+ * one launch that clears the same-face blocks of every H, the setup runs as a
+ * few launches per order present, most expensive order first, and the
+ * recovery likewise: FP64 RT2 and RT3 problems up to eight per launch, their
+ * descriptors in the kernel arguments, one grid range per problem; FP64 RT0
+ * and RT1 problems in one persistent launch per order, whose work items
+ * (problem, run of element blocks) are sorted by cost and taken from a work
+ * queue (an atomic counter, most expensive first) by a grid of
+ * blocks_per_cu x (compute units) workgroups.
  * Every order uses the generic element routines (Gauss quadrature, packed
  * Cholesky, inverse of the face block), so a batch sets its plans to that
  * record layout; H, r, y and u of each problem equal those of the plan's own
  * calls.  HYB_MIXED plans run the mixed-precision element routines (the
- * same as their own calls, so again the same bits) in a second persistent
- * launch per phase over their work items, after the FP64 problems' launch.
+ * same as their own calls, so again the same bits) in one more persistent
+ * launch per phase over their work items, after the FP64 problems' launches.
  * With graphs enabled the launch sequences are captured into hipGraphs
  * on the batch's own stream (ordered after and before the plans' stream by
- * events) and replayed; descriptors are device copies, so new coefficient
- * values written into the same buffers need no re-capture.
+ * events) and replayed; descriptors are copies (device arrays and kernel
+ * arguments), so new coefficient values written into the same buffers need
+ * no re-capture, and hyb_batch_set with other buffers re-captures.
  * The batch allocates a few small device arrays itself (descriptors, work
  * list); the plans' buffers stay caller-owned and must outlive the batch.
  */
 typedef struct hyb_batch hyb_batch_t;
 
 typedef struct {
-  int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu x CUs (0: 2) */
+  int32_t blocks_per_cu;    /* persistent grids = blocks_per_cu x CUs (0: 2) */
   int32_t items_per_block;  /* element blocks per work item (0: 1) */
 } hyb_batch_tiles;
 
@@ -399,8 +403,8 @@ int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best);
 /*
  * Timing of the batch phases with HIP events recorded on the stream each
  * phase runs on (the batch's own stream on graph replays): one pair around
- * every setup phase (the clearing of the same-face blocks, then the
- * persistent setup launches) and one around every recovery phase.
+ * every setup phase (the clearing of the same-face blocks, then the setup
+ * launches) and one around every recovery phase.
  * hyb_batch_timing_enable(b, 1) starts collecting (and drops earlier pairs;
  * the autotuner's passes are not timed); hyb_batch_timing_read synchronises
  * and returns the summed milliseconds and counts of each phase since
