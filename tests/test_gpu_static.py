@@ -4,8 +4,10 @@ The GPU assembles S = sum_T sigma-scattered S_hat_T with S_hat_T = L_bb
 L_bb^T from the i-first element Cholesky; the oracle assembles
 A_bb - A_bi A_ii^{-1} A_ib from dense solves (pinned against the Schur
 complement of the conforming matrix).  Both are FP64 with different
-rounding: they agree to about kappa(A_ii) 2^-53 relative to the row, below
-1e-10 here (the observed value is printed).  The solution through the GPU's
+rounding, each within 10 kappa_s 2^-53 of the exact values (kappa_s of the
+equilibrated element matrices bounds that of their interior blocks), so
+they agree to 20 kappa_s 2^-53 relative to the row (the observed value is
+printed).  The solution through the GPU's
 PCG and recovery equals the conforming solution (Theorem 2.1) and the
 hybridized one.
 """
@@ -16,7 +18,8 @@ import scipy.sparse as sp
 import synth
 from oracle import conforming
 from oracle import static as ostat
-from tests.gpu_common import norm_rel, rel_inf, require_gpu, row_rel_err
+from oracle import topology as otopo
+from tests.gpu_common import kappa_of, norm_rel, oracle_gap_bound, rel_inf, require_gpu, row_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -56,8 +59,10 @@ def test_S_and_load_match_oracle(k, N, jit, rot, wg):
     rg = plan.r().cpu().numpy()
     eS = row_rel_err(ref.S, val)
     er = rel_inf(ref.r, rg)
-    print(f"  S row-relative {eS:.1e}, normwise {norm_rel(ref.S.data, val):.1e}; load {er:.1e}", flush=True)
-    assert eS <= 1e-10 and er <= 1e-10
+    bound = oracle_gap_bound(kappa_of(k, mesh, a, b, otopo.build_topology(mesh.e2v)))
+    print(f"  S row-relative {eS:.1e}, normwise {norm_rel(ref.S.data, val):.1e}; load {er:.1e}; "
+          f"bound 20 kappa_s u = {bound:.1e}", flush=True)
+    assert eS <= bound and er <= bound
 
 
 @pytest.mark.parametrize("k,N,jit,rot,wg", CASES)
