@@ -113,10 +113,10 @@ def test_batch_graph_replays_and_autotune():
 
 
 def test_batch_padding_teams_leave_rt3_records_alone():
-    """RT3 runs two elements per block in a batch: with an odd element count
-    the last block has a padding team, whose safe element index is 0 and
-    whose matrix would be element 0's HBM record.  One- and 27-element RT3
-    problems (and an RT2 one between them) give the single plans' bits."""
+    """RT3 recovers eight elements per workgroup (one per wave), RT2 two:
+    past a problem's last element the padding teams take element 0 as their
+    safe index and must write nothing.  One- and 27-element RT3 problems
+    (and an RT2 one between them) give the single plans' bits."""
     torch = require_gpu()
     from paper_1801_08914_amd import Plan
     rng = np.random.default_rng(45)
@@ -141,6 +141,45 @@ def test_batch_padding_teams_leave_rt3_records_alone():
             assert torch.equal(val.cpu(), single.csr()[2].cpu()), i
             assert torch.equal(r.cpu(), single.r().cpu()), i
             assert torch.equal(ub.cpu(), u), i
+
+
+def test_batch_more_problems_per_order_than_one_launch_takes():
+    """RT2 and RT3 problems go eight to a launch (their descriptors in the
+    kernel arguments): ten RT3 and nine RT2 problems of 1 or 8 elements, and
+    two RT1 ones, take several launches per order and phase; every problem
+    gives its single plan's bits, eager and on graph replays."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Plan
+    rng = np.random.default_rng(49)
+    probs = []
+    for i, (n, k) in enumerate([(1 + (i % 2), 3) for i in range(10)] + [(2 - (i % 2), 2) for i in range(9)] +
+                               [(2, 1), (1, 1)]):
+        mesh = synth.structured_hex(n, jitter=0.2 if n > 1 else 0.0, rng=rng)
+        probs.append(synth.Problem(f"many_{i}_k{k}_n{n}", mesh, k, synth.lognormal(rng, mesh.ne),
+                                   synth.lognormal(rng, mesh.ne, 0.5), synth.element_loads(rng, mesh.ne)))
+    b, plans, lams = _batch(torch, probs)
+    singles = []
+    for i, p in enumerate(probs):
+        single = Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True).bind()
+        single.setup(p.alpha, p.beta, p.f)
+        u = single.recover(torch.as_tensor(lams[i], device="cuda")).cpu()
+        torch.cuda.synchronize()
+        assert single.status()[0] == 0, (i, single.status())
+        singles.append((single.csr()[2].cpu(), single.r().cpu(), u))
+    for graph in (False, True, True):
+        b.graph(graph)
+        for pl in plans:
+            pl.csr()[2].zero_()
+            pl.r().zero_()
+        b.setup()
+        b.recover()
+        got = _outputs(torch, b, plans)
+        for i, p in enumerate(probs):
+            val, r, ub = got[i]
+            assert torch.equal(val.cpu(), singles[i][0]), (graph, i, p.name)
+            assert torch.equal(r.cpu(), singles[i][1]), (graph, i, p.name)
+            assert torch.equal(ub.cpu(), singles[i][2]), (graph, i, p.name)
+        print(f"  graph={graph}: {len(probs)} problems equal their single plans", flush=True)
 
 
 def test_batch_mixed_and_fp64_plans_together():
