@@ -1247,7 +1247,34 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
     tl[b] = v;
   }
   __syncthreads();
-  if (!a.stat) {
+  if constexpr (!recover_stages<K>() && TEAM == 64) {
+    if (!a.stat) {
+      // One wave per element, the face block read once, by rows (coalesced):
+      // row c gives z_c = y_c - sum_{c' <= c} L_bb[c][c'] tl[c'] (a wave sum,
+      // every lane the same value), then its terms L_bb[c][b] z_c of
+      // u_b = sum_{c >= b} L_bb[c][b] z_c for the lanes' b = lane, lane + 64.
+      static_assert(nb <= 128, "two face dofs per lane");
+      const int b1 = lane + 64;
+      const double t0 = tl[lane], t1 = b1 < nb ? tl[b1] : 0.0;
+      double u0 = 0.0, u1 = 0.0;
+#pragma unroll 4
+      for (int c = 0; c < nb; ++c) {
+        const double* row = F + pk(ni + c, ni);   // entries 0..c of face row c
+        const double l0 = row[lane <= c ? lane : c];
+        const double l1 = row[b1 <= c ? b1 : c];
+        const double m0 = lane <= c ? l0 : 0.0, m1 = b1 <= c ? l1 : 0.0;
+        double p = m0 * t0 + m1 * t1;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, 64);
+        const double zc = yv[ni + c] - p;
+        u0 += m0 * zc;
+        u1 += m1 * zc;
+      }
+      tl[lane] = u0;   // u_b
+      if (b1 < nb) tl[b1] = u1;
+    }
+    __syncthreads();
+  } else if (!a.stat) {
     // (loops unrolled so that the loads run ahead of the chain of sums)
     // (face row b: Lfb + pk(b, 0) in LDS, or F + pk(ni + b, ni) in the
     // record; column b steps by the row lengths in both)
