@@ -1299,16 +1299,31 @@ __device__ __forceinline__ void recover_generic_body(const RecoverArgs& a, doubl
     }
     __syncthreads();
   }
-  for (int j = lane; j < ni; j += TEAM) {
-    double s = yv[j];
-    const double* fc = F + pk(ni, j);
-    int p = 0;
-#pragma unroll 8
-    for (int b = 0; b < nb; ++b) {
-      s -= fc[p] * tl[b];
-      p += ni + b + 1;
+  {
+    // z_j = y_j - sum_b L[ni + b][j] u_b for the lane's rows j = lane + TEAM r,
+    // all of them in one pass over b (their loads issued together)
+    constexpr int RPJ = (ni + TEAM - 1) / TEAM;
+    double s[RPJ > 0 ? RPJ : 1];
+#pragma unroll
+    for (int r = 0; r < RPJ; ++r) {
+      const int j = lane + TEAM * r;
+      s[r] = j < ni ? yv[j] : 0.0;
     }
-    zb[j] = s;
+#pragma unroll 8
+    for (int b = 0; b < (lane < ni ? nb : 0); ++b) {
+      const double* row = F + pk(ni + b, 0);   // face row b: its L_bi part, columns j
+      const double ub = tl[b];
+#pragma unroll
+      for (int r = 0; r < RPJ; ++r) {
+        const int j = lane + TEAM * r;
+        s[r] -= row[j < ni ? j : 0] * ub;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPJ; ++r) {
+      const int j = lane + TEAM * r;
+      if (j < ni) zb[j] = s[r];
+    }
   }
   __syncthreads();
   if constexpr (TEAM >= 64 && recover_stages<K>()) {
