@@ -368,9 +368,10 @@ typedef struct {
 } hyb_batch_tiles;
 
 /* plans: count bound plans (the batch keeps pointers, it does not own them),
- * launched on plans[0]'s stream; FP64 and HYB_MIXED plans may be mixed.
- * Errors: HYB_E_ARG (also for a HYB_STATIC plan: batches run the
- * hybridization kernels), HYB_E_STATE (unbound), HYB_E_NOMEM, HYB_E_HIP. */
+ * launched on plans[0]'s stream; FP64, HYB_MIXED and HYB_STATIC plans may
+ * be mixed (a static-condensation plan assembles S and recovers from the
+ * face dofs x given as its lambda, as its own calls do).
+ * Errors: HYB_E_ARG, HYB_E_STATE (unbound), HYB_E_NOMEM, HYB_E_HIP. */
 int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out);
 
 /* Device inputs of problem p: alpha, beta (ne), f (ne x 3, NULL: matrix

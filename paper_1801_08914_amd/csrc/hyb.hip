@@ -1062,10 +1062,8 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
   *out = nullptr;
   for (int32_t i = 0; i < count; ++i)
     if (!plans[i]) return HYB_E_ARG;
-  for (int32_t i = 0; i < count; ++i) {
+  for (int32_t i = 0; i < count; ++i)
     if (!plans[i]->P.bound) return HYB_E_STATE;
-    if (plans[i]->P.stat) return HYB_E_ARG;   // hybridization (FP64 or mixed) only
-  }
   hyb_batch* b = new (std::nothrow) hyb_batch;
   if (!b) return HYB_E_NOMEM;
   b->plans.assign(plans, plans + count);
@@ -1099,10 +1097,12 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
     pr.s.r = P.buf.r;
     pr.s.status = P.buf.status;
     pr.s.mode = hyb::MODE_MATRIX;
+    pr.s.stat = P.stat ? 1 : 0;   // static condensation: S and its load, u_b = sigma x
     pr.r.mp = pr.s.mp;
     pr.r.ne = P.ne;
     pr.r.factor = P.buf.factor;
     pr.r.y = P.buf.y;
+    pr.r.stat = pr.s.stat;
     if (P.mixed) {
       b->lds_setup_mx = std::max(b->lds_setup_mx, hyb::batch_setup_lds_mixed(P.ord.k));
       b->lds_recover_mx = std::max(b->lds_recover_mx, hyb::batch_recover_lds_mixed(P.ord.k));

@@ -85,7 +85,7 @@ def test_solution_equals_conforming_and_hybridized(k, N, jit, rot, wg):
 
 def test_static_rhs_reuse_and_argument_errors():
     torch = require_gpu()
-    from paper_1801_08914_amd import Batch, HybError, Plan
+    from paper_1801_08914_amd import HybError, Plan
     mesh, a, b, f, g = _problem(2, 3, 0.2, True, False, 7200)
     f2 = np.random.default_rng(3).standard_normal(f.shape)
     p1 = _plan(torch, mesh, 2, a, b, f, None)
@@ -95,5 +95,42 @@ def test_static_rhs_reuse_and_argument_errors():
     assert torch.equal(p1.r().cpu(), p2.r().cpu())
     with pytest.raises(HybError):
         Plan(mesh.xyz, mesh.e2v, 2, system="static", precision="mixed")
-    with pytest.raises(HybError):
-        Batch([p1])
+
+
+def test_static_plans_in_a_batch_equal_single_plans():
+    """Static-condensation plans of every order (with boundary data) in one
+    batch, beside a hybridization plan: S, its load and the recovered u equal
+    the single plans' bits, eager and on graph replays."""
+    torch = require_gpu()
+    from paper_1801_08914_amd import Batch, Plan
+    cases = [(0, 4, "static"), (1, 3, "static"), (2, 3, "static"), (3, 2, "static"), (2, 2, "hybrid")]
+    probs, plans, singles, xs = [], [], [], []
+    for i, (k, N, system) in enumerate(cases):
+        mesh, a, b, f, g = _problem(k, N, 0.2, True, True, 7300 + 10 * k + N)
+        probs.append((mesh, k, a, b, f, g, system))
+        plans.append(Plan(mesh.xyz, mesh.e2v, k, system=system, generic=True).bind())
+        single = Plan(mesh.xyz, mesh.e2v, k, system=system, generic=True).bind()
+        single.setup(a, b, f, g)
+        x = np.random.default_rng(7400 + i).standard_normal(max(single.m, 1))
+        u = single.recover(torch.as_tensor(x, device="cuda")).cpu()
+        torch.cuda.synchronize()
+        assert single.status()[0] == 0, (i, single.status())
+        singles.append((single.csr()[2].cpu(), single.r().cpu(), u))
+        xs.append(x)
+    bt = Batch(plans)
+    for i, (mesh, k, a, b, f, g, system) in enumerate(probs):
+        bt.set(i, a, b, f, g=g, lam=xs[i])
+    for graph in (False, True, True):
+        bt.graph(graph)
+        for pl in plans:
+            pl.csr()[2].zero_()
+            pl.r().zero_()
+        bt.setup()
+        bt.recover()
+        torch.cuda.synchronize()
+        for i, pl in enumerate(plans):
+            assert pl.status()[0] == 0, (i, pl.status())
+            assert torch.equal(pl.csr()[2].cpu(), singles[i][0]), (graph, i)
+            assert torch.equal(pl.r().cpu(), singles[i][1]), (graph, i)
+            assert torch.equal(bt.u(i).cpu(), singles[i][2]), (graph, i)
+        print(f"  graph={graph}: {len(plans)} plans equal their single plans", flush=True)
