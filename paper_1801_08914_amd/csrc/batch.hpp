@@ -1,10 +1,9 @@
-// Batches of independent problems of mixed order, a kernel per order and
-// phase (each gets the register allocation, and so the occupancy, of the
-// single-plan kernel of that order).  RT0 and RT1: one persistent launch
-// walks that order's part of a cost-sorted list of work items (problem, run
-// of element blocks).  RT2 and RT3: launches of up to eight problems with
-// their descriptors in the kernel arguments.  Mixed-precision problems: one
-// persistent launch over their items.
+// Batches of independent problems of mixed order.  FP64 problems: a kernel
+// per order and phase (each gets the register allocation, and so the
+// occupancy, of the single-plan kernel of that order), launched for up to
+// eight problems at a time with their descriptors in the kernel arguments.
+// Mixed-precision problems: one persistent launch per phase over a list of
+// work items.
 #pragma once
 
 #include "kernels_common.hpp"
@@ -31,14 +30,11 @@ struct BatchItem {
   int64_t blk0;      // first element block (blocks of the order's EPB elements)
 };
 
-// Element blocks per order (teams x lanes = 512 threads for every order:
-// 32 x 16, 8 x 64, then one element on 512 lanes for k = 2 and k = 3, the
-// teams of the single-plan kernels).  The per-element arithmetic does not
-// depend on the team size (every entry is summed in a fixed order), so a
+// Element blocks of the mixed-precision problems per order (512-thread
+// workgroups): 8 x 64, 4 x 128, then one element per block (RT3: its FP64
+// element matrix in the workgroup's scratch slot).  The per-element
+// arithmetic does not depend on the number of elements per workgroup, so a
 // batch gives the single plans' bits.
-__host__ __device__ constexpr int batch_epb(int k) { return k == 0 ? 32 : (k == 1 ? 8 : 1); }
-// Mixed-precision problems: 8 x 64, 4 x 128, then one element per block
-// (RT3: its FP64 element matrix in the workgroup's scratch slot).
 __host__ __device__ constexpr int batch_epb_mixed(int k) { return k == 0 ? 8 : (k == 1 ? 4 : 1); }
 constexpr int kBatchThreads = 512;
 constexpr int kBatchThreadsK3 = 512;
@@ -113,7 +109,7 @@ __device__ __forceinline__ RecoverArgs global_args(const RecoverArgs& s) {
 template <int K, int TEAM, int EPB>
 __device__ __attribute__((noinline)) void batch_setup_mx(const SetupArgs& a, double* smem, int64_t blk, int sweeps,
                                                          double* scratch) {
-  setup_mixed_body<K, TEAM, EPB>(a, smem, blk, sweeps, scratch);
+  setup_mixed_body<K, TEAM, EPB>(global_args(a), smem, blk, sweeps, scratch);
 }
 
 // The next work item of a persistent workgroup from the launch's queue
@@ -148,45 +144,16 @@ __global__ __launch_bounds__(256) void k_batch_zero(const BatchProb* probs) {
   if (P.mixed && blockIdx.x == 0 && threadIdx.x == 0) P.s.status[2] = 0;
 }
 
-// The FP64 problems of order K: setup, then recovery.  The descriptors and
-// items are read-only and not aliased, and the item index is made
-// wave-uniform, so the arguments load into scalar registers.  The RT0 and
-// RT1 setup bodies are called, one call per element block (each its own
-// register allocation).  RT2 and RT3 setups run in k_setup_multi below.
-template <int K>
-__device__ __attribute__((noinline)) void batch_setup_call(const SetupArgs& a, double* smem, int64_t blk) {
-  if constexpr (K == 0) setup_generic_body<0, 16, 32>(global_args(a), smem, blk);
-  else setup_generic_body<1, 64, 8>(global_args(a), smem, blk);
-}
-
-template <int K>
-__global__ __launch_bounds__(kBatchThreads, K == 2 ? 4 : 2) void k_setup_batch(const BatchProb* __restrict__ probs,
-                                                                               const BatchItem* __restrict__ items,
-                                                                               int64_t nitems, int32_t* queue) {
-  extern __shared__ double smem[];
-  __shared__ int64_t item;
-  for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
-    const BatchItem& it = items[__builtin_amdgcn_readfirstlane(int(w))];
-    const SetupArgs& a = probs[it.prob].s;
-    for (int b = 0; b < it.nblk; ++b) {
-      const int64_t blk = it.blk0 + b;
-      batch_setup_call<K>(a, smem, blk);
-      __syncthreads();   // the next block reuses the LDS
-    }
-  }
-}
-
-// RT2 and RT3 setups of the FP64 problems: up to kMultiProbs problems per
-// launch, their descriptors in the kernel arguments, one element per
-// workgroup, each problem's elements a consecutive range of the grid (the
-// hardware hands out the workgroups as CUs free up).  The body then compiles
-// as in the single-plan kernels: descriptor fields are loaded from the
-// argument segment where they are used, while a persistent loop over work
-// items keeps them live across the body and spills (RT2 inlined in such a
-// loop: 1040 bytes of spills against 276 here, 63 against 44 us per element
-// and CU; RT3 called from it: 400 bytes and 177 against 158 us).
-// The recoveries of RT2 and RT3 problems likewise (recover_teams(K)
-// elements per workgroup).
+// The FP64 problems: per order, launches of up to kMultiProbs problems with
+// their descriptors in the kernel arguments, each problem's element blocks a
+// consecutive range of the grid (the hardware hands out the workgroups as
+// CUs free up), in the single-plan kernels' teams (and so their bits).  The
+// body then compiles as in the single-plan kernels: descriptor fields are
+// loaded from the argument segment where they are used, while a persistent
+// loop over work items keeps them live across the body and spills (RT2
+// inlined in such a loop: 1040 bytes of spills against 276 here, 63 against
+// 44 us per element and CU; RT3 called from it: 400 bytes and 177 against
+// 156 us; RT1 10.7 against 9.7 us).
 constexpr int kMultiProbs = 8;
 template <class Args>
 struct MultiT {
@@ -206,48 +173,34 @@ __device__ __forceinline__ int multi_problem(const MultiT<Args>& m, int64_t g) {
   return __builtin_amdgcn_readfirstlane(pi);
 }
 
+// Setup teams (lanes per element) and elements per workgroup of order k:
+// those of the single-plan kernels.
+__host__ __device__ constexpr int setup_team(int k) { return k == 0 ? 16 : (k == 1 ? 64 : 512); }
+__host__ __device__ constexpr int setup_teams(int k) { return k == 0 ? 16 : (k == 1 ? 4 : 1); }
+
 template <int K>
-__global__ __launch_bounds__(kBatchThreads, K == 2 ? 4 : 1) void k_setup_multi(MultiArgs m) {
-  static_assert(K == 2 || K == 3, "RT2 and RT3 only");
+__global__ __launch_bounds__(setup_team(K) * setup_teams(K), K == 2 ? 4 : (K == 3 ? 1 : 2)) void k_setup_multi(
+    MultiArgs m) {
   extern __shared__ double smem[];
   const int64_t g = blockIdx.x;
   const int pi = multi_problem(m, g);
   const SetupArgs& a = m.p[pi];
-  if constexpr (K == 2) setup_generic_body<2, 512, 1>(a, smem, g - m.start[pi]);
+  if constexpr (K <= 2) setup_generic_body<K, setup_team(K), setup_teams(K)>(a, smem, g - m.start[pi]);
   else setup_k3_body<kBatchThreadsK3>(a, smem, g - m.start[pi]);
 }
 
 template <int K>
-__global__ __launch_bounds__(kBatchThreads) void k_recover_multi(MultiRecArgs m) {
-  static_assert(K == 2 || K == 3, "RT2 and RT3 only");
-  static_assert(recover_team(K) * recover_teams(K) == kBatchThreads, "one element per team");
+__global__ __launch_bounds__(recover_team(K) * recover_teams(K)) void k_recover_multi(MultiRecArgs m) {
   extern __shared__ double smem[];
   const int64_t g = blockIdx.x;
   const int pi = multi_problem(m, g);
   recover_generic_body<K, recover_team(K), recover_teams(K)>(m.p[pi], smem, g - m.start[pi]);
 }
 
-template <int K>
-__global__ __launch_bounds__(kBatchThreads) void k_recover_batch(const BatchProb* __restrict__ probs,
-                                                                 const BatchItem* __restrict__ items, int64_t nitems,
-                                                                 int32_t* queue) {
-  extern __shared__ double smem[];
-  __shared__ int64_t item;
-  for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
-    const BatchItem& it = items[__builtin_amdgcn_readfirstlane(int(w))];
-    const RecoverArgs a = global_args(probs[it.prob].r);
-    for (int b = 0; b < it.nblk; ++b) {
-      const int64_t blk = it.blk0 + b;
-      if constexpr (K == 0) recover_generic_body<0, 16, 32>(a, smem, blk);
-      else recover_generic_body<1, 64, 8>(a, smem, blk);
-      __syncthreads();
-    }
-  }
-}
-
-// The same two phases for the batch's mixed-precision problems (their work
-// items follow the FP64 ones in the list; a separate launch, so the FP64
-// kernels keep their own LDS size).
+// The mixed-precision problems: one persistent launch per phase walks a
+// cost-sorted list of work items (problem, run of element blocks) taken from
+// an atomic work queue, whatever their orders (the mixed element routines are
+// called, each with its own register allocation).
 __global__ __launch_bounds__(kBatchThreads) void k_setup_batch_mixed(const BatchProb* probs, const BatchItem* items,
                                                                      int64_t nitems, double* scratch,
                                                                      int32_t* queue) {
@@ -279,13 +232,14 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch_mixed(const Bat
   for (int64_t w = next_item(queue, &item); w < nitems; w = next_item(queue, &item)) {
     const BatchItem it = items[w];
     const BatchProb& P = probs[it.prob];
+    const RecoverArgs a = global_args(P.r);
     for (int b = 0; b < it.nblk; ++b) {
       const int64_t blk = it.blk0 + b;
       switch (P.k) {
-        case 0: recover_mixed_body<0, 64, 8>(P.r, smem, blk); break;
-        case 1: recover_mixed_body<1, 128, 4>(P.r, smem, blk); break;
-        case 2: recover_mixed_body<2, 512, 1>(P.r, smem, blk); break;
-        default: recover_mixed_body<3, 512, 1>(P.r, smem, blk); break;
+        case 0: recover_mixed_body<0, 64, 8>(a, smem, blk); break;
+        case 1: recover_mixed_body<1, 128, 4>(a, smem, blk); break;
+        case 2: recover_mixed_body<2, 512, 1>(a, smem, blk); break;
+        default: recover_mixed_body<3, 512, 1>(a, smem, blk); break;
       }
       __syncthreads();
     }
@@ -295,16 +249,16 @@ __global__ __launch_bounds__(kBatchThreads) void k_recover_batch_mixed(const Bat
 // LDS bytes of one block of the batch kernels for order k.
 inline size_t batch_setup_lds(int k) {
   switch (k) {
-    case 0: return 8 * 32 * size_t(GenericLayout<0, 16, 32>::per);
-    case 1: return 8 * 8 * size_t(GenericLayout<1, 64, 8>::per);
-    case 2: return 8 * size_t(GenericLayout<2, 512, 1>::per);
+    case 0: return 8 * size_t(setup_teams(0)) * size_t(GenericLayout<0, setup_team(0), setup_teams(0)>::per);
+    case 1: return 8 * size_t(setup_teams(1)) * size_t(GenericLayout<1, setup_team(1), setup_teams(1)>::per);
+    case 2: return 8 * size_t(GenericLayout<2, setup_team(2), setup_teams(2)>::per);
     default: return 8 * size_t(K3Layout::per);
   }
 }
 inline size_t batch_recover_lds(int k) {
   switch (k) {
-    case 0: return 8 * 32 * size_t(recover_per<0>());
-    case 1: return 8 * 8 * size_t(recover_per<1>());
+    case 0: return 8 * size_t(recover_teams(0)) * size_t(recover_per<0>());
+    case 1: return 8 * size_t(recover_teams(1)) * size_t(recover_per<1>());
     case 2: return 8 * size_t(recover_teams(2)) * size_t(recover_per<2>());
     default: return 8 * size_t(recover_teams(3)) * size_t(recover_per<3>());
   }

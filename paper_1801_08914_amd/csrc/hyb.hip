@@ -812,10 +812,8 @@ struct hyb_batch {
   int cus = 0;
   hyb_batch_tiles tiles{0, 0};
   std::vector<hyb::BatchProb> probs;       // host copy of the descriptors
-  std::vector<hyb::BatchItem> items;       // cost-sorted work list: FP64 RT0/RT1 items by order, then mixed
-  size_t n64 = 0;                          // items of FP64 problems (the first n64)
-  size_t beg[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};   // the FP64 items of order k
-  size_t n_mx = 0;                         // items of mixed problems (after the FP64 ones)
+  std::vector<hyb::BatchItem> items;       // cost-sorted work list of the mixed problems
+  size_t n_mx = 0;                         // its length
   hyb::BatchProb* d_probs = nullptr;
   hyb::BatchItem* d_items = nullptr;
   size_t cap_items = 0;
@@ -826,7 +824,7 @@ struct hyb_batch {
   hipStream_t gstream = nullptr;           // capture/replay stream (graphs need a non-null stream)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   double* scratch = nullptr;               // k = 3 mixed: a slot per workgroup of the mixed launch
-  int32_t* d_queue = nullptr;              // work-queue counters of the persistent launches (kQueues)
+  int32_t* d_queue = nullptr;              // work-queue counters of the mixed launches (kQueues)
   // optional HIP-event timing of each phase (start/stop pairs, launch order)
   bool timing = false;
   std::vector<hipEvent_t> ev_setup, ev_recover, ev_pool;
@@ -834,11 +832,10 @@ struct hyb_batch {
 
 namespace {
 
-// queue counters: FP64 setup per order (0..3), mixed setup, FP64 recovery per
-// order (5..8), mixed recovery
-constexpr int kQueues = 10;
+// queue counters: mixed setup, mixed recovery
+constexpr int kQueues = 2;
 
-int batch_epb_of(const hyb::Plan& P) { return P.mixed ? hyb::batch_epb_mixed(P.ord.k) : hyb::batch_epb(P.ord.k); }
+int batch_epb_of(const hyb::Plan& P) { return hyb::batch_epb_mixed(P.ord.k); }
 
 // Relative cost of one element block of a plan (flops of assembly and
 // factorization of the batch kernels, per block of its elements).
@@ -860,7 +857,7 @@ void batch_build_items(hyb_batch* b) {
   b->items.clear();
   for (size_t p = 0; p < b->plans.size(); ++p) {
     const hyb::Plan& P = b->plans[p]->P;
-    if (!P.mixed && P.ord.k >= 2) continue;   // RT2/RT3: k_setup_multi, k_recover_multi
+    if (!P.mixed) continue;   // FP64 problems: k_setup_multi, k_recover_multi
     const int epb = batch_epb_of(P);
     const int64_t nblk = (P.ne + epb - 1) / epb;
     for (int64_t q = 0; q < nblk; q += ipb) {
@@ -871,23 +868,12 @@ void batch_build_items(hyb_batch* b) {
       b->items.push_back(it);
     }
   }
-  // FP64 problems' items first, by order (descending), then the mixed ones;
-  // within each group most expensive first, stable: deterministic order
+  // most expensive first, stable: deterministic order
   std::stable_sort(b->items.begin(), b->items.end(), [&](const hyb::BatchItem& x, const hyb::BatchItem& y) {
     const hyb::Plan &px = b->plans[x.prob]->P, &py = b->plans[y.prob]->P;
-    if (px.mixed != py.mixed) return !px.mixed;
-    if (!px.mixed && px.ord.k != py.ord.k) return px.ord.k > py.ord.k;
     return batch_block_cost(px) * x.nblk > batch_block_cost(py) * y.nblk;
   });
-  b->n64 = 0;
-  for (int k = 0; k < 4; ++k) b->beg[k] = b->cnt[k] = 0;
-  while (b->n64 < b->items.size() && !b->plans[b->items[b->n64].prob]->P.mixed) {
-    const int k = b->plans[b->items[b->n64].prob]->P.ord.k;
-    if (b->cnt[k] == 0) b->beg[k] = b->n64;
-    ++b->cnt[k];
-    ++b->n64;
-  }
-  b->n_mx = b->items.size() - b->n64;
+  b->n_mx = b->items.size();
   b->dirty = true;
 }
 
@@ -929,37 +915,37 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
   HYB_HIP(hipGetLastError());
   const size_t nmx = b->n_mx;
   // the queue counters start at zero (a kernel, not a memset: graph replays)
-  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue, int64_t(5), 0);
-  HYB_HIP(hipGetLastError());
-  // the orders' launches, most expensive first: RT3 and RT2 problems
-  // kMultiProbs at a time, their descriptors in the kernel arguments
-  for (int k = 3; k >= 2; --k) {
+  if (nmx) {   // the queue counter starts at zero (a kernel, not a memset: graph replays)
+    hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue, int64_t(1), 0);
+    HYB_HIP(hipGetLastError());
+  }
+  // the FP64 problems by order, most expensive order first, kMultiProbs
+  // problems per launch with their descriptors in the kernel arguments
+  for (int k = 3; k >= 0; --k) {
+    const int per = hyb::setup_teams(k);
+    const auto kern = k == 3 ? hyb::k_setup_multi<3>
+                      : k == 2 ? hyb::k_setup_multi<2>
+                      : k == 1 ? hyb::k_setup_multi<1>
+                               : hyb::k_setup_multi<0>;
     hyb::MultiArgs m{};
     for (size_t p = 0; p <= b->probs.size(); ++p) {
       const bool take = p < b->probs.size() && !b->probs[p].mixed && b->probs[p].k == k && b->probs[p].s.ne > 0;
       if (take) {
-        m.start[m.np + 1] = m.start[m.np] + b->probs[p].s.ne;
+        m.start[m.np + 1] = m.start[m.np] + (b->probs[p].s.ne + per - 1) / per;
         m.p[m.np++] = b->probs[p].s;
       }
       if (m.np == hyb::kMultiProbs || (p == b->probs.size() && m.np > 0)) {
-        hipLaunchKernelGGL(k == 3 ? hyb::k_setup_multi<3> : hyb::k_setup_multi<2>, dim3(unsigned(m.start[m.np])),
-                           dim3(hyb::kBatchThreads), hyb::batch_setup_lds(k), st, m);
+        hipLaunchKernelGGL(kern, dim3(unsigned(m.start[m.np])), dim3(hyb::setup_team(k) * per),
+                           hyb::batch_setup_lds(k), st, m);
         HYB_HIP(hipGetLastError());
         m = hyb::MultiArgs{};
       }
     }
   }
-  for (int k = 1; k >= 0; --k) {
-    if (!b->cnt[k]) continue;
-    hipLaunchKernelGGL(k == 1 ? hyb::k_setup_batch<1> : hyb::k_setup_batch<0>, dim3(batch_grid(b, b->cnt[k])),
-                       dim3(hyb::kBatchThreads), hyb::batch_setup_lds(k), st, b->d_probs, b->d_items + b->beg[k],
-                       int64_t(b->cnt[k]), b->d_queue + k);
-    HYB_HIP(hipGetLastError());
-  }
   if (nmx) {
     const unsigned gm = std::min<unsigned>(batch_grid(b, nmx), unsigned(hyb::kMixedSlots));
     hipLaunchKernelGGL(hyb::k_setup_batch_mixed, dim3(gm), dim3(hyb::kBatchThreads), b->lds_setup_mx, st,
-                       b->d_probs, b->d_items + b->n64, int64_t(nmx), b->scratch, b->d_queue + 4);
+                       b->d_probs, b->d_items, int64_t(nmx), b->scratch, b->d_queue);
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
@@ -967,10 +953,16 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
 
 int batch_launch_recover(hyb_batch* b, hipStream_t st) {
   const size_t nmx = b->n_mx;
-  hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue + 5, int64_t(5), 0);
-  HYB_HIP(hipGetLastError());
-  for (int k = 3; k >= 2; --k) {
+  if (nmx) {
+    hipLaunchKernelGGL(hyb::k_fill_i32, dim3(1), dim3(64), 0, st, b->d_queue + 1, int64_t(1), 0);
+    HYB_HIP(hipGetLastError());
+  }
+  for (int k = 3; k >= 0; --k) {
     const int per = hyb::recover_teams(k);
+    const auto kern = k == 3 ? hyb::k_recover_multi<3>
+                      : k == 2 ? hyb::k_recover_multi<2>
+                      : k == 1 ? hyb::k_recover_multi<1>
+                               : hyb::k_recover_multi<0>;
     hyb::MultiRecArgs m{};
     for (size_t p = 0; p <= b->probs.size(); ++p) {
       const bool take = p < b->probs.size() && !b->probs[p].mixed && b->probs[p].k == k && b->probs[p].r.ne > 0;
@@ -979,23 +971,16 @@ int batch_launch_recover(hyb_batch* b, hipStream_t st) {
         m.p[m.np++] = b->probs[p].r;
       }
       if (m.np == hyb::kMultiProbs || (p == b->probs.size() && m.np > 0)) {
-        hipLaunchKernelGGL(k == 3 ? hyb::k_recover_multi<3> : hyb::k_recover_multi<2>, dim3(unsigned(m.start[m.np])),
-                           dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st, m);
+        hipLaunchKernelGGL(kern, dim3(unsigned(m.start[m.np])), dim3(hyb::recover_team(k) * per),
+                           hyb::batch_recover_lds(k), st, m);
         HYB_HIP(hipGetLastError());
         m = hyb::MultiRecArgs{};
       }
     }
   }
-  for (int k = 1; k >= 0; --k) {
-    if (!b->cnt[k]) continue;
-    hipLaunchKernelGGL(k == 1 ? hyb::k_recover_batch<1> : hyb::k_recover_batch<0>, dim3(batch_grid(b, b->cnt[k])),
-                       dim3(hyb::kBatchThreads), hyb::batch_recover_lds(k), st, b->d_probs, b->d_items + b->beg[k],
-                       int64_t(b->cnt[k]), b->d_queue + 5 + k);
-    HYB_HIP(hipGetLastError());
-  }
   if (nmx) {
     hipLaunchKernelGGL(hyb::k_recover_batch_mixed, dim3(batch_grid(b, nmx)), dim3(hyb::kBatchThreads),
-                       b->lds_recover_mx, st, b->d_probs, b->d_items + b->n64, int64_t(nmx), b->d_queue + 9);
+                       b->lds_recover_mx, st, b->d_probs, b->d_items, int64_t(nmx), b->d_queue + 1);
     HYB_HIP(hipGetLastError());
   }
   return HYB_OK;
@@ -1117,12 +1102,12 @@ int hyb_batch_create(hyb_plan_t* const* plans, int32_t count, hyb_batch_t** out)
   if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
   {
-    const void* ks[4] = {reinterpret_cast<const void*>(hyb::k_setup_batch<0>),
-                         reinterpret_cast<const void*>(hyb::k_setup_batch<1>),
+    const void* ks[4] = {reinterpret_cast<const void*>(hyb::k_setup_multi<0>),
+                         reinterpret_cast<const void*>(hyb::k_setup_multi<1>),
                          reinterpret_cast<const void*>(hyb::k_setup_multi<2>),
                          reinterpret_cast<const void*>(hyb::k_setup_multi<3>)};
-    const void* kr[4] = {reinterpret_cast<const void*>(hyb::k_recover_batch<0>),
-                         reinterpret_cast<const void*>(hyb::k_recover_batch<1>),
+    const void* kr[4] = {reinterpret_cast<const void*>(hyb::k_recover_multi<0>),
+                         reinterpret_cast<const void*>(hyb::k_recover_multi<1>),
                          reinterpret_cast<const void*>(hyb::k_recover_multi<2>),
                          reinterpret_cast<const void*>(hyb::k_recover_multi<3>)};
     for (int k = 0; k < 4 && e1 == hipSuccess; ++k) {

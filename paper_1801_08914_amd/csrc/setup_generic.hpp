@@ -1183,14 +1183,14 @@ __global__ __launch_bounds__(TEAM* EPB, K == 2 ? 4 : 2) void k_setup_generic(Set
 // record directly with many elements in flight per CU)
 template <int K>
 constexpr bool recover_stages() { return K <= 2; }
-// Recovery team (lanes per element) of the RT2 and RT3 kernels and the
-// elements of a 512-lane workgroup.  RT3 runs one wave per element: every
-// step waits on record loads (the back substitution on one wave in any
-// case), so the elements in flight per CU set the rate (16 with 64-lane
-// teams, 4 with 256-lane ones).  RT2 stages 26 KB of the factor per element
-// in LDS: 256-lane teams keep six elements per CU.
-__host__ __device__ constexpr int recover_team(int k) { return k == 3 ? 64 : 256; }
-__host__ __device__ constexpr int recover_teams(int k) { return 512 / recover_team(k); }
+// Recovery team (lanes per element) and elements per workgroup of order k.
+// RT3 runs one wave per element: every step waits on record loads (the back
+// substitution on one wave in any case), so the elements in flight per CU
+// set the rate (16 with 64-lane teams, 4 with 256-lane ones).  RT2 stages
+// 26 KB of the factor per element in LDS: 256-lane teams keep six elements
+// per CU.
+__host__ __device__ constexpr int recover_team(int k) { return k == 0 ? 16 : (k == 1 ? 64 : (k == 2 ? 256 : 64)); }
+__host__ __device__ constexpr int recover_teams(int k) { return k == 0 ? 16 : (k == 1 ? 4 : (k == 2 ? 2 : 8)); }
 template <int K>
 constexpr int recover_per() {
   return 2 * RT<K>::n + RT<K>::nb + (recover_stages<K>() ? RT<K>::ni * (RT<K>::ni + 1) / 2 + RT<K>::nbpk : 0);
