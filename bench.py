@@ -384,10 +384,10 @@ def _copy_calibration():
 
 def run_c4(args):
     """The uneven batch (64 jittered problems, n in 8..24, k in 0..3): setup +
-    recovery of every problem in one persistent launch per phase, tiles from
-    the library's autotuner, replayed as hipGraphs; the FP64 plain form is
-    the line's value, the mixed-precision form a leg beside it.  Recovery
-    uses a seeded random lambda (its cost does not depend on the values)."""
+    recovery of every problem, a few launches per order and phase (up to
+    eight problems each), replayed as hipGraphs; the FP64 plain form is the
+    line's value, the mixed-precision form a leg beside it.  Recovery uses a
+    seeded random lambda (its cost does not depend on the values)."""
     import synth
     probs = synth.config_c4()
     ne = sum(p.mesh.ne for p in probs)
@@ -427,8 +427,8 @@ def run_c4(args):
           file=sys.stderr, flush=True)
     flops = sum(algo_counts(p.k)["setup_flops"] * p.mesh.ne for p in probs)
     rbytes = sum(algo_counts(p.k)["recover_bytes"] * p.mesh.ne for p in probs)
-    roof = {"bound": "mfma", "kernel": "setup phase: k_batch_zero, k_setup_multi<3> and <2> (up to eight "
-                                        "problems per launch), persistent k_setup_batch<1> and <0>",
+    roof = {"bound": "mfma", "kernel": "setup phase: k_batch_zero, then k_setup_multi<3>, <2>, <1>, <0> (up to "
+                                        "eight problems per launch)",
             "achieved": flops / (setup_ms * 1e-3) / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": flops / (setup_ms * 1e-3) / FP64_PEAK,
             "traffic": traffic_from_profile("setup", ne, "hbm_traffic_uneven_batch_64.json"),
@@ -449,9 +449,8 @@ def run_c4(args):
                                   "lognormal per problem, seed 4",
                       "elements": ne, "elements_by_order": by_k, "problems": len(probs),
                       "precision": "fp64-plain",
-                      "launch": "RT2/RT3 setups up to eight problems per launch, other orders and recoveries one "
-                                "persistent launch per order, hipGraph replay",
-                      "autotuned_tiles": {"blocks_per_cu": tiles[0], "items_per_block": tiles[1]}},
+                      "launch": "per order and phase, launches of up to eight problems (descriptors in the "
+                                "kernel arguments), hipGraph replay"},
            "step_ms_p50": 1e3 * float(np.median(ts)), "step_ms_p90": 1e3 * float(np.percentile(ts, 90)),
            "host_planning_s": plan_s, "roofline": roof}
     if parity is not None:
@@ -467,19 +466,23 @@ def c4_mixed_leg(args, probs, tiles, ne, plain_value, lams, picks):
     """The same uneven batch with every problem in the mixed-precision form
     (FP32 element factors and solves, FP64 refinement), refined (adaptive
     sweeps with the backward-error test) and unrefined: one persistent
-    launch per phase over the mixed problems' items, the FP64 form's tiles,
-    hipGraph replay.  Problems with an element that needed the FP64 fallback
-    are counted (the result is still within the bound), failures too."""
+    launch per phase over the mixed problems' items, hipGraph replay, tiles
+    from the library's autotuner on the unrefined batch (or --tiles).
+    Problems with an element that needed the FP64 fallback are counted (the
+    result is still within the bound), failures too."""
     import torch
 
     from paper_1801_08914_amd import Batch, Plan
     out = {}
-    for name, sweeps in (("refined", None), ("unrefined", 0)):
+    tiles = tuple(int(x) for x in args.tiles.split(",")) if args.tiles else None
+    for name, sweeps in (("unrefined", 0), ("refined", None)):
         plans = [Plan(p.mesh.xyz, p.mesh.e2v, p.k, generic=True, precision="mixed", sweeps=sweeps).bind("cuda:0")
                  for p in probs]
         b = Batch(plans)
         for i, p in enumerate(probs):
             b.set(i, p.alpha, p.beta, p.f, lam=lams[i])
+        if tiles is None:
+            tiles = b.autotune(reps=1)
         b.tiles(*tiles)
         b.graph(True)
         steps = max(1, min(args.steps, 5))

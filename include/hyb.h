@@ -338,20 +338,20 @@ void hyb_destroy(hyb_plan_t* plan);
  * ---------------------------------------------------------------------------
  * Batches of independent problems of mixed order and mesh (the uneven batch
  * of many small hybridization problems; each problem is a bound plan).  After
- * one launch that clears the same-face blocks of every H, the setup runs as a
- * few launches per order present, most expensive order first, and the
- * recovery likewise: FP64 RT2 and RT3 problems up to eight per launch, their
- * descriptors in the kernel arguments, one grid range per problem; FP64 RT0
- * and RT1 problems in one persistent launch per order, whose work items
- * (problem, run of element blocks) are sorted by cost and taken from a work
- * queue (an atomic counter, most expensive first) by a grid of
- * blocks_per_cu x (compute units) workgroups.
+ * one launch that clears the same-face blocks of every H, the setup of the
+ * FP64 problems runs as a few launches per order present, most expensive
+ * order first, and the recovery likewise: up to eight problems per launch,
+ * their descriptors in the kernel arguments, one grid range per problem, in
+ * the single-plan kernels' teams.
  * Every order uses the generic element routines (Gauss quadrature, packed
  * Cholesky, inverse of the face block), so a batch sets its plans to that
  * record layout; H, r, y and u of each problem equal those of the plan's own
  * calls.  HYB_MIXED plans run the mixed-precision element routines (the
- * same as their own calls, so again the same bits) in one more persistent
- * launch per phase over their work items, after the FP64 problems' launches.
+ * same as their own calls, so again the same bits) in one persistent launch
+ * per phase, after the FP64 problems' launches, whose work items (problem,
+ * run of element blocks) are sorted by cost and taken from a work queue (an
+ * atomic counter, most expensive first) by a grid of
+ * blocks_per_cu x (compute units) workgroups.
  * With graphs enabled the launch sequences are captured into hipGraphs
  * on the batch's own stream (ordered after and before the plans' stream by
  * events) and replayed; descriptors are copies (device arrays and kernel
@@ -363,7 +363,7 @@ void hyb_destroy(hyb_plan_t* plan);
 typedef struct hyb_batch hyb_batch_t;
 
 typedef struct {
-  int32_t blocks_per_cu;    /* persistent grids = blocks_per_cu x CUs (0: 2) */
+  int32_t blocks_per_cu;    /* mixed problems' grid = blocks_per_cu x CUs (0: 2) */
   int32_t items_per_block;  /* element blocks per work item (0: 1) */
 } hyb_batch_tiles;
 
@@ -397,8 +397,9 @@ int hyb_batch_graph(hyb_batch_t* b, int enable);
 /* Autotuner: times reps setup + recovery passes for every candidate tile
  * pair (blocks_per_cu in {1,2,4,8} x items_per_block in {1,2,4,8}) on the
  * batch's own inputs (HIP events), keeps the fastest and returns it in best
- * (may be NULL).  Needs every input of hyb_batch_set; overwrites the
- * outputs. */
+ * (may be NULL).  The tiles shape the mixed problems' persistent launch; a
+ * batch without mixed problems keeps the default pair.  Needs every input
+ * of hyb_batch_set; overwrites the outputs. */
 int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best);
 
 /*

@@ -1197,6 +1197,14 @@ int hyb_batch_autotune(hyb_batch_t* b, int reps, hyb_batch_tiles* best) {
   if (!b || reps <= 0) return HYB_E_ARG;
   for (const auto& pr : b->probs)
     if (!pr.s.alpha || !pr.s.beta || !pr.r.lambda || !pr.r.u) return HYB_E_STATE;
+  bool any_mixed = false;
+  for (const auto& pr : b->probs) any_mixed |= pr.mixed != 0;
+  if (!any_mixed) {   // the tiles shape only the mixed problems' launch
+    const hyb_batch_tiles t{2, 1};
+    const int rc = hyb_batch_set_tiles(b, &t);
+    if (!rc && best) *best = t;
+    return rc;
+  }
   const bool graph = b->use_graph, timing = b->timing;
   b->use_graph = false;
   b->timing = false;
