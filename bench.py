@@ -382,6 +382,46 @@ def _copy_calibration():
     del src, dst
 
 
+def measured_peaks():
+    """What the chip reaches on plain work, beside the published peaks: a
+    1 GiB device-to-device copy (HBM read + write) and an FP64 8192^3 matrix
+    product from the vendor BLAS through torch (matrix cores), each the best
+    of five timed repetitions (HIP events on torch's stream)."""
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best_ms(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            ev0.record()
+            fn()
+            ev1.record()
+            ev1.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            best = ms if best is None else min(best, ms)
+        return best
+
+    n = 128 * 1024 * 1024   # doubles: 1 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    copy_ms = best_ms(lambda: dst.copy_(src))
+    del src, dst
+    m = 8192
+    a = torch.randn(m, m, dtype=torch.float64, device="cuda:0")
+    b = torch.randn(m, m, dtype=torch.float64, device="cuda:0")
+    c = torch.empty_like(a)
+    gemm_ms = best_ms(lambda: torch.matmul(a, b, out=c), reps=3)
+    del a, b, c
+    torch.cuda.empty_cache()
+    hbm = 2.0 * 8 * n / (copy_ms * 1e-3)
+    dgemm = 2.0 * m ** 3 / (gemm_ms * 1e-3)
+    return {"hbm_copy_gbs": hbm / 1e9, "hbm_copy_frac_of_peak": hbm / HBM_PEAK,
+            "dgemm_tflops": dgemm / 1e12, "dgemm_frac_of_peak": dgemm / FP64_PEAK,
+            "how": "1 GiB device copy (read + write bytes); FP64 8192^3 torch.matmul; best of 5 / 3"}
+
+
 def run_c4(args):
     """The uneven batch (64 jittered problems, n in 8..24, k in 0..3): setup +
     recovery of every problem, a few launches per order and phase (up to
@@ -456,6 +496,13 @@ def run_c4(args):
     if parity is not None:
         out["error_vs_oracle"] = parity
     out["mixed"] = mixed
+    if not (args.no_peaks or args.copy_calib):   # (counter runs: the calibration copy stays the largest)
+        pk = measured_peaks()
+        roof["measured_peaks"] = pk
+        roof["frac_of_measured_dgemm"] = roof["achieved"] / pk["dgemm_tflops"]
+        roof["recover_frac_of_measured_copy"] = rbytes / (rec_ms * 1e-3) / (pk["hbm_copy_gbs"] * 1e9)
+        print(f"measured peaks: copy {pk['hbm_copy_gbs']:.0f} GB/s, FP64 GEMM {pk['dgemm_tflops']:.1f} TFLOP/s",
+              file=sys.stderr, flush=True)
     if cpu is not None:
         cpu["gpu_over_cpu"] = value / cpu["value"]
         out["cpu_baseline"] = cpu
@@ -689,6 +736,7 @@ def main():
                          "latency; c2: RT1 32^3; c3: RT2 48^3 jittered; c5: the serving stream; softhard: the "
                          "soft-hard materials study; spe10: the SPE10-shaped stand-in")
     ap.add_argument("--no-legs", action="store_true", help="c4: skip the C2 and C3 legs")
+    ap.add_argument("--no-peaks", action="store_true", help="c4: skip the measured copy / FP64 GEMM peaks")
     ap.add_argument("--tiles", default="", help="c4: fixed batch tiles 'blocks_per_cu,items_per_block' "
                                                 "instead of the autotuner's (profiling runs)")
     ap.add_argument("--requests", type=int, default=40, help="c5: requests in the stream")
