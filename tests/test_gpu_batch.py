@@ -1,8 +1,9 @@
-"""Uneven batches of problems of mixed order and mesh in one persistent launch
-(through the C ABI): every problem's H, r and u equal those of its own plan
-calls bitwise (same element routines), they match the oracle, hipGraph
-replays equal the eager launches on every replay, and the autotuner's choice
-leaves the results unchanged."""
+"""Uneven batches of problems of mixed order and mesh (through the C ABI; a
+few launches per order and phase, mixed-precision problems in a persistent
+launch): every problem's H, r and u equal those of its own plan calls
+bitwise (same element routines), they match the oracle, hipGraph replays
+equal the eager launches on every replay, and the autotuner's choice leaves
+the results unchanged."""
 import numpy as np
 import pytest
 

@@ -105,9 +105,9 @@ def test_c3_rt2_48cubed_jittered_sampled():
 
 def test_c4_uneven_batch_sampled():
     """The full uneven batch (64 problems, n in 8..24, k in 0..3) in the
-    launch configuration the benchmark times (per-order persistent launches,
-    autotuned tiles, hipGraph replay): sampled rows and elements of one
-    problem of each order against the oracle."""
+    launch configuration the benchmark times (multi-problem launches per
+    order, hipGraph replay): sampled rows and elements of one problem of
+    each order against the oracle."""
     torch = require_gpu()
     from paper_1801_08914_amd import Batch, Plan
     probs = synth.config_c4()
