@@ -834,6 +834,8 @@ namespace {
 
 // queue counters: mixed setup, mixed recovery
 constexpr int kQueues = 2;
+// the multi-problem descriptors travel as kernel arguments (at most 4 KB)
+static_assert(sizeof(hyb::MultiArgs) <= 4096 && sizeof(hyb::MultiRecArgs) <= 4096, "kernel-argument size");
 
 int batch_epb_of(const hyb::Plan& P) { return hyb::batch_epb_mixed(P.ord.k); }
 
@@ -935,6 +937,7 @@ int batch_launch_setup(hyb_batch* b, hipStream_t st) {
         m.p[m.np++] = b->probs[p].s;
       }
       if (m.np == hyb::kMultiProbs || (p == b->probs.size() && m.np > 0)) {
+        if (m.start[m.np] > int64_t(INT32_MAX)) return HYB_E_ARG;   // grid beyond the x-dimension limit
         hipLaunchKernelGGL(kern, dim3(unsigned(m.start[m.np])), dim3(hyb::setup_team(k) * per),
                            hyb::batch_setup_lds(k), st, m);
         HYB_HIP(hipGetLastError());
@@ -971,6 +974,7 @@ int batch_launch_recover(hyb_batch* b, hipStream_t st) {
         m.p[m.np++] = b->probs[p].r;
       }
       if (m.np == hyb::kMultiProbs || (p == b->probs.size() && m.np > 0)) {
+        if (m.start[m.np] > int64_t(INT32_MAX)) return HYB_E_ARG;   // grid beyond the x-dimension limit
         hipLaunchKernelGGL(kern, dim3(unsigned(m.start[m.np])), dim3(hyb::recover_team(k) * per),
                            hyb::batch_recover_lds(k), st, m);
         HYB_HIP(hipGetLastError());
